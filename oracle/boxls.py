@@ -1,0 +1,362 @@
+"""Plain FP64 reference for box-constrained least squares with Gap-safe screening.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): never imported by the
+product path.
+
+Problem (Sec. 2, eq. LR, with the least-squares fidelity of Sec. 5):
+    minimise  P(x) = sum_i f([Ax]_i; y_i),  f(z; y) = 1/2 (z - y)^2,
+    subject to l <= x <= u,   l finite, u_j in R or +inf.
+Non-negative LS is l = 0, u = +inf; bounded-variable LS has every u_j finite.
+
+Conventions: A is an (m, n) array (any memory order), vectors are 1-D FP64
+arrays, J_inf = {j : u_j = +inf}.  For the negative and positive parts we use
+[z]^- = min(0, z) and [z]^+ = max(0, z) (Sec. 1, Notations).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+INF = math.inf
+
+
+# ---------------------------------------------------------------------------
+# Objectives (Sec. 2 eq. LR; Sec. 3.1 eqs. Dual_obj and Dual_set; Sec. 5)
+# ---------------------------------------------------------------------------
+def primal(A, y, x) -> float:
+    """P(x) = 1/2 ||Ax - y||^2 (eq. LR with the LS fidelity of Sec. 5)."""
+    r = np.asarray(A, dtype=np.float64) @ x - y
+    return 0.5 * float(r @ r)
+
+
+def fconj(v, y):
+    """Fenchel conjugate of f(.; y) = 1/2 (. - y)^2 (Sec. 5):
+    f*(v; y) = 1/2 ((y + v)^2 - y^2), applied entrywise."""
+    return 0.5 * ((y + v) ** 2 - y ** 2)
+
+
+def dual(A, y, l, u, theta) -> float:
+    """Dual objective, eq. Dual_obj (Sec. 3.1):
+    D(theta) = - sum_i f*(-theta_i; y_i) - sum_j l_j [A^T theta]^-_j
+               - sum_{j not in J_inf} u_j [A^T theta]^+_j.
+    Evaluated as written; feasibility (eq. Dual_set) is a separate check."""
+    A = np.asarray(A, dtype=np.float64)
+    c = A.T @ theta
+    fin = np.isfinite(u)
+    val = -float(np.sum(fconj(-theta, y)))
+    val -= float(np.sum(l * np.minimum(c, 0.0)))
+    val -= float(np.sum(u[fin] * np.maximum(c[fin], 0.0)))
+    return val
+
+
+def dual_feasible(A, u, theta, tol: float = 0.0) -> bool:
+    """Membership in F_D, eq. Dual_set: a_j^T theta <= 0 for every j in J_inf."""
+    A = np.asarray(A, dtype=np.float64)
+    J = ~np.isfinite(u)
+    if not np.any(J):
+        return True
+    return bool(np.all(A[:, J].T @ theta <= tol))
+
+
+def duality_gap(A, y, l, u, x, theta) -> float:
+    """Gap(x, theta) = P(x) - D(theta), eq. Dual_Gap (Sec. 3.3)."""
+    return primal(A, y, x) - dual(A, y, l, u, theta)
+
+
+def gap_closed_form(A, y, l, u, x, eps, t) -> float:
+    """Per-coordinate form of the gap at theta = (y - Ax) + eps t.
+
+    Substituting theta into eq. Dual_obj with f* from Sec. 5:
+    1/2||y||^2 - 1/2||y - theta||^2 = 1/2||y||^2 - 1/2||Ax - eps t||^2, so
+    P - D = -<theta, Ax> + 1/2 eps^2 ||t||^2 + sum_j (l_j [g_j]^- + u_j [g_j]^+)
+    with g = A^T theta, and -x_j g_j + l_j[g_j]^- + u_j[g_j]^+ regroups into
+        sum_j (u_j - x_j)[g_j]^+ + (x_j - l_j)[-g_j]^+ + 1/2 eps^2 ||t||^2;
+    a term with u_j = +inf and g_j <= 0 contributes 0.
+    Used only as a cross-check of ``duality_gap``."""
+    A = np.asarray(A, dtype=np.float64)
+    theta = (y - A @ x) + (eps * t if eps else 0.0)
+    g = A.T @ theta
+    pos = np.maximum(g, 0.0)
+    up = np.zeros_like(pos)
+    k = pos > 0                                         # 0 * inf := 0
+    up[k] = (u[k] - x[k]) * pos[k]
+    lo = (x - l) * np.maximum(-g, 0.0)
+    tt = 0.0 if not eps else 0.5 * eps * eps * float(t @ t)
+    return float(np.sum(up) + np.sum(lo)) + tt
+
+
+# ---------------------------------------------------------------------------
+# Dual points (Sec. 4)
+# ---------------------------------------------------------------------------
+def residual_dual_point(A, y, x):
+    """Theta(x) = -grad F(Ax; y) = y - Ax for the LS fidelity
+    (eq. BVLR_dual_up, Sec. 4.1)."""
+    return y - np.asarray(A, dtype=np.float64) @ x
+
+
+def translate(A, z, t, J):
+    """Dual translation Xi_t(z) = z + (max_{j in J} (a_j^T z)^+ / |a_j^T t|) t
+    (eq. BVLR_dual_up2, Sec. 4.2).  J selects the columns whose dual constraint
+    is active (J_inf).  Returns (theta, eps)."""
+    A = np.asarray(A, dtype=np.float64)
+    if not np.any(J):
+        return z.copy(), 0.0
+    AJ = A[:, J]
+    num = np.maximum(AJ.T @ z, 0.0)
+    den = np.abs(AJ.T @ t)
+    eps = float(np.max(num / den))
+    return z + eps * t, eps
+
+
+def interior_direction_ok(A, u, t) -> bool:
+    """t in Int(F_D) (Sec. 4.2, eq. interior_FD): a_j^T t < 0 for every
+    j in J_inf."""
+    A = np.asarray(A, dtype=np.float64)
+    J = ~np.isfinite(u)
+    if not np.any(J):
+        return True
+    return bool(np.all(A[:, J].T @ t < 0.0))
+
+
+def dual_point(A, y, u, x, t):
+    """The dual update Theta(x) used by the screening loop.
+
+    * No infinite upper bound (BVLR): theta = y - Ax (Sec. 4.1).
+    * Otherwise dual translation of y - Ax along t (Sec. 4.2) over J_inf.
+    * If t is not in Int(F_D) for this matrix (possible for signed A, where
+      Prop. 2 offers no direction), the always-feasible theta = 0 is used
+      (D(0) = 0), so the gap equals P(x) and nothing can be screened.
+    Returns (theta, eps, t_valid)."""
+    z = residual_dual_point(A, y, x)
+    J = ~np.isfinite(u)
+    if not np.any(J):
+        return z, 0.0, True
+    if not interior_direction_ok(A, u, t):
+        return np.zeros_like(z), 0.0, False
+    theta, eps = translate(A, z, t, J)
+    return theta, eps, True
+
+
+# ---------------------------------------------------------------------------
+# Gap-safe sphere and rule (Sec. 3.3, eqs. GAP_Safe_sph and safe_rule)
+# ---------------------------------------------------------------------------
+def safe_radius(gap: float, alpha: float = 1.0) -> float:
+    """r = sqrt(2 Gap / alpha) (eq. GAP_Safe_sph); alpha = 1 for LS since f''=1.
+    A gap that rounds below zero is taken as zero."""
+    return math.sqrt(2.0 * max(gap, 0.0) / alpha)
+
+
+def safe_rule(A, theta, radius, u):
+    """eq. safe_rule: a_j^T theta < -r ||a_j||  =>  x*_j = l_j ;
+                      a_j^T theta >  r ||a_j||  =>  x*_j = u_j (u_j finite).
+    Returns boolean masks (lower, upper)."""
+    A = np.asarray(A, dtype=np.float64)
+    c = A.T @ theta
+    nrm = np.sqrt(np.sum(A * A, axis=0))
+    lower = c < -radius * nrm
+    upper = (c > radius * nrm) & np.isfinite(u)
+    return lower, upper
+
+
+# ---------------------------------------------------------------------------
+# Primal solvers (Sec. 5: projected gradient [Polyak 2015]; coordinate
+# descent [Franc et al. 2005]).  Neither algorithm is printed in the paper.
+# ---------------------------------------------------------------------------
+def project(x, l, u):
+    """Euclidean projection on the box [l, u]."""
+    return np.minimum(np.maximum(x, l), u)
+
+
+def pg_step(A, y, l, u, x, eta):
+    """One projected-gradient step x <- Pi_[l,u](x - eta grad P(x)) with
+    grad P(x) = -A^T (y - Ax) (eq. grad, Sec. 4.1)."""
+    A = np.asarray(A, dtype=np.float64)
+    g = A.T @ (y - A @ x)
+    return project(x + eta * g, l, u)
+
+
+def cd_sweep(A, y, l, u, x):
+    """One cyclic sweep of exact coordinate minimisation, j = 0..n-1 in order:
+    x_j <- Pi_[l_j,u_j](x_j + a_j^T r / ||a_j||^2), r <- r - delta_j a_j,
+    with r = y - Ax kept current.  Zero columns are skipped (P does not depend
+    on those coordinates)."""
+    A = np.asarray(A, dtype=np.float64)
+    x = x.copy()
+    r = y - A @ x
+    for j in range(A.shape[1]):
+        a = A[:, j]
+        d = float(a @ a)
+        if d == 0.0:
+            continue
+        xj = min(max(x[j] + float(a @ r) / d, l[j]), u[j])
+        delta = xj - x[j]
+        if delta != 0.0:
+            x[j] = xj
+            r -= delta * a
+    return x
+
+
+def lipschitz(A) -> float:
+    """L = ||A||_2^2, the Lipschitz constant of grad P (largest singular value
+    squared, from an SVD)."""
+    return float(np.linalg.norm(np.asarray(A, dtype=np.float64), 2) ** 2)
+
+
+def lipschitz_power(A, iters: int = 100, seed: int = 0) -> float:
+    """Power-iteration estimate of ||A||_2^2 (lower bound) for matrices too
+    large for an SVD."""
+    A = np.asarray(A, dtype=np.float64)
+    v = np.random.default_rng(seed).standard_normal(A.shape[1])
+    v /= np.linalg.norm(v)
+    lam = 0.0
+    for _ in range(iters):
+        w = A.T @ (A @ v)
+        lam = float(np.linalg.norm(w))
+        v = w / lam
+    return lam
+
+
+# ---------------------------------------------------------------------------
+# The screening loop (Alg. 1; Alg. 2 is its l = 0, u = +inf case)
+# ---------------------------------------------------------------------------
+@dataclass
+class Result:
+    x: np.ndarray
+    sat: np.ndarray            # int8: -1 screened at l, +1 screened at u, 0 kept
+    status: str                # "ok" (gap < eps_gap) or "maxiter"
+    gap: float
+    primal: float
+    dual: float
+    radius: float
+    iters: int
+    passes: int
+    t_valid: bool
+    history: list = field(default_factory=list)
+
+
+def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
+          max_iter: int = 100000, step: float | None = None, t=None,
+          screening: bool = True, x0=None, keep_theta: bool = False) -> Result:
+    """Alg. 1 with the least-squares simplification of Remark 3.
+
+    Each pass:
+      1. K primal iterations (PG steps, or CD sweeps) on the reduced problem
+         min 1/2 ||A_P x_P - y'||^2 over the preserved set P (Alg. 1,
+         PrimalUpdate on F(A_P . + z)), where y' = y - A_S x_S folds the fixed
+         coordinates into the data (Remark 3);
+      2. dual update theta = Theta(x) on the reduced problem (Sec. 4);
+      3. gap of the reduced problem and safe radius (eqs. Dual_Gap,
+         GAP_Safe_sph);
+      4. stop if the gap is below eps_gap (the returned x is the one whose gap
+         was just measured);
+      5. otherwise (screening on) apply the safe rule on P, fix the screened
+         coordinates at their bound, fold them into y' and remove them from P.
+
+    ``screening=False`` is the unscreened baseline: the same iterations and the
+    same gap evaluation for stopping, but step 5 is skipped.
+    ``step`` defaults to 1/||A||_2^2; ``t`` defaults to -1 (Sec. 5).
+    ``keep_theta`` stores each pass's dual point, iterate and preserved set in
+    the history (for the safe-sphere checks)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    y = np.asarray(y, dtype=np.float64)
+    l = np.asarray(l, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    t = -np.ones(m) if t is None else np.asarray(t, dtype=np.float64)
+    if solver not in ("pg", "cd"):
+        raise ValueError(solver)
+    eta = (1.0 / lipschitz(A)) if step is None else float(step)
+    x = project(np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64), l, u)
+    sat = np.zeros(n, dtype=np.int8)
+    P = np.arange(n)
+    yp = y.copy()
+    iters = passes = 0
+    hist = []
+    status = "maxiter"
+    gap = prim = dl = rad = float("nan")
+    t_valid = True
+    while True:
+        AP, lP, uP = A[:, P], l[P], u[P]
+        xP = x[P]
+        kk = min(K, max_iter - iters)
+        for _ in range(kk):
+            xP = pg_step(AP, yp, lP, uP, xP, eta) if solver == "pg" else cd_sweep(AP, yp, lP, uP, xP)
+        iters += kk
+        x[P] = xP
+        theta, eps, t_valid = dual_point(AP, yp, uP, xP, t)
+        prim = primal(AP, yp, xP)
+        dl = dual(AP, yp, lP, uP, theta)
+        gap = prim - dl
+        rad = safe_radius(gap)
+        passes += 1
+        hist.append({"iters": iters, "gap": gap, "radius": rad, "n_active": int(P.size),
+                     "eps": eps, "primal": prim, "t_valid": t_valid})
+        if keep_theta:
+            hist[-1]["theta"] = theta.copy()
+            hist[-1]["x"] = x.copy()
+            hist[-1]["active"] = P.copy()
+        if gap < eps_gap:
+            status = "ok"
+            break
+        if iters >= max_iter:
+            break
+        if screening and P.size:
+            lo, hi = safe_rule(AP, theta, rad, uP)
+            S = lo | hi
+            if np.any(S):
+                x[P[lo]] = l[P[lo]]
+                x[P[hi]] = u[P[hi]]
+                sat[P[lo]] = -1
+                sat[P[hi]] = 1
+                yp = yp - A[:, P[S]] @ x[P[S]]
+                P = P[~S]
+    return Result(x, sat, status, gap, prim, dl, rad, iters, passes, t_valid, hist)
+
+
+# ---------------------------------------------------------------------------
+# Exact optima and optimality checks (Sec. 3.2, eqs. optimality1-2; App. C)
+# ---------------------------------------------------------------------------
+def kkt_violation(A, y, l, u, x) -> float:
+    """Largest violation of the optimality conditions eqs. optimality1-2 at x
+    with theta = y - Ax: |a_j^T theta| on free coordinates, (a_j^T theta)^+ at
+    lower bounds, (-a_j^T theta)^+ at upper bounds, plus box infeasibility."""
+    A = np.asarray(A, dtype=np.float64)
+    g = A.T @ (y - A @ x)
+    at_l = x <= l
+    at_u = (x >= u) & np.isfinite(u)
+    free = ~(at_l | at_u)
+    v = 0.0
+    if np.any(free):
+        v = max(v, float(np.max(np.abs(g[free]))))
+    if np.any(at_l):
+        v = max(v, float(np.max(np.maximum(g[at_l], 0.0))))
+    if np.any(at_u):
+        v = max(v, float(np.max(np.maximum(-g[at_u], 0.0))))
+    v = max(v, float(np.max(np.maximum(l - x, 0.0), initial=0.0)))
+    v = max(v, float(np.max(np.maximum(x - u, 0.0), initial=0.0)))
+    return v
+
+
+def polish(A, y, l, u, x):
+    """Exact optimum from an approximate one: keep the saturation pattern of x
+    (coordinates exactly on a bound), solve the unconstrained least squares on
+    the free set F for the folded data y - A_S x_S, and accept the result when
+    it lies strictly inside the box on F and satisfies the sign conditions of
+    eq. optimality2 on the saturated set.  Returns (x_exact, accepted)."""
+    A = np.asarray(A, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64).copy()
+    F = (x > l) & (x < u)
+    S = ~F
+    yF = y - A[:, S] @ x[S]
+    if np.any(F):
+        sol, *_ = np.linalg.lstsq(A[:, F], yF, rcond=None)
+        x[F] = sol
+    ok = bool(np.all(x[F] > l[F]) and np.all(x[F] < u[F]))
+    g = A.T @ (y - A @ x)
+    scale = 1e-9 * max(1.0, float(np.max(np.abs(g), initial=0.0)))
+    at_l = S & (x <= l)
+    at_u = S & (x >= u)
+    ok = ok and bool(np.all(g[at_l] <= scale)) and bool(np.all(g[at_u] >= -scale))
+    return x, ok
