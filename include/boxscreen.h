@@ -1,0 +1,177 @@
+/*
+ * boxscreen.h -- C ABI of the gfx950 (MI355X) Gap-safe screening library for
+ * box-constrained least squares:
+ *
+ *     minimise  P(x) = 1/2 ||A x - y||^2   subject to   l <= x <= u,
+ *
+ * the least-squares instance (Sec. 5) of the box-constrained linear regression
+ * problem eq. LR (Sec. 2) of Dantas, Soubies and Fevotte, "Accelerating
+ * Non-Negative and Bounded-Variable Linear Regression Algorithms with Safe
+ * Screening" (arXiv:2202.07258).  l is finite; u_j may be +INFINITY (the
+ * non-negative case l = 0, u = +inf and mixed constraints are covered).
+ *
+ * Every solver runs the dynamic screening loop of Alg. 1 (Alg. 2 for NNLS):
+ * a few primal iterations on the preserved set, a dual point built from the
+ * residual (dual scaling for finite boxes, Sec. 4.1; dual translation along t
+ * for columns with u_j = +inf, Sec. 4.2), the duality gap (eq. Dual_Gap), the
+ * Gap-safe radius (eq. GAP_Safe_sph), the saturation test (eq. safe_rule),
+ * and removal of the screened columns, until the gap is below eps_gap.
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers on the current HIP device, owned
+ *    by the caller.  The library never frees caller memory.  Inputs (A, y, l,
+ *    u, t) are read only; x, sat and explicit outputs are written.
+ *  - A is column-major: element (i, j) is at A[i + j*lda], lda >= m.  Its
+ *    element type is given by a_dtype; the problem solved is the one defined
+ *    by the stored values (FP32 storage is promoted exactly to FP64).
+ *  - Vectors are FP64 unless stated otherwise.  Every matrix-vector product
+ *    accumulates in FP64; the gap, dual point and screening test are FP64 and
+ *    carry an explicit rounding margin, so a screened coordinate is provably
+ *    saturated at the optimum of the stored problem.
+ *  - Work is enqueued on opts->stream (NULL: the default stream).  A call
+ *    returns after the solve has finished and info has been filled.
+ *  - Errors are reported by the return code; no exception crosses the ABI.
+ *    Argument and shape checks happen before any launch; checks that need the
+ *    device data (non-finite values, l > u) happen before the first iteration
+ *    and leave x and sat unspecified.  bxs_last_error() describes the last
+ *    failure of the calling thread.
+ *  - Calls are not re-entrant on the same workspace; distinct calls with
+ *    distinct workspaces may run concurrently on different streams.
+ */
+#ifndef BOXSCREEN_H
+#define BOXSCREEN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BXS_OK            = 0,  /* gap < eps_gap reached                              */
+    BXS_ERR_ARG       = 1,  /* NULL pointer, bad enum or option value              */
+    BXS_ERR_SHAPE     = 2,  /* m, n < 1, lda < m, or m above the supported maximum */
+    BXS_ERR_NONFINITE = 3,  /* NaN/Inf in A, y, x0, t, or NaN in l/u               */
+    BXS_ERR_BOUNDS    = 4,  /* l_j = -inf, u_j = -inf or l_j > u_j                 */
+    BXS_ERR_DEVICE    = 5,  /* HIP runtime error (message in bxs_last_error)       */
+    BXS_ERR_NOMEM     = 6,  /* workspace too small or allocation failure           */
+    BXS_MAXITER       = 7   /* max_iter reached first: x = last iterate, info set  */
+} bxs_status;
+
+typedef enum { BXS_PG = 0, BXS_CD = 1 } bxs_solver;   /* projected gradient / cyclic coordinate descent */
+typedef enum { BXS_F64 = 0, BXS_F32 = 1 } bxs_dtype;  /* storage type of A                               */
+
+/* Largest number of rows a single instance may have. */
+#define BXS_MAX_ROWS 16384
+
+/* One record per screening pass (Alg. 1 loop body), written to opts->history. */
+typedef struct {
+    long   iters;      /* primal iterations (PG steps or CD sweeps) done before this pass */
+    long   n_active;   /* size of the preserved set when the gap was evaluated            */
+    double gap;        /* certified duality gap of the reduced problem (eq. Dual_Gap)      */
+    double radius;     /* Gap-safe radius sqrt(2 gap) (eq. GAP_Safe_sph, alpha = 1)         */
+    double eps;        /* dual-translation coefficient (0 for finite boxes)                 */
+    double primal;     /* 1/2 ||r||^2 of the reduced problem                                */
+    long   n_screened; /* coordinates removed by this pass                                   */
+} bxs_pass_record;
+
+typedef struct {
+    int     solver;          /* bxs_solver                                                      */
+    int     screening;       /* 1: dynamic Gap-safe screening; 0: unscreened baseline (same
+                                iterations and gap evaluations, nothing is removed)            */
+    int     screen_every;    /* K >= 1: PG steps or CD sweeps between two screening passes     */
+    long    max_iter;        /* >= 1: iteration budget (PG steps or CD sweeps)                  */
+    double  eps_gap;         /* >= 0: absolute gap tolerance (stop when gap < eps_gap)          */
+    double  step;            /* PG step; <= 0 selects 1/(1.05 L), L from power iteration        */
+    int     power_iters;     /* power-iteration count for L (<= 0: 20)                          */
+    const double* t;         /* device m-vector translation direction for the u_j = +inf
+                                columns (Sec. 4.2); NULL means t = -1 (Sec. 5).  If some
+                                preserved column has a_j^T t >= 0 the library falls back to
+                                the always-feasible dual point theta = 0 and nothing is
+                                screened (info.t_valid = 0).                                    */
+    void*   stream;          /* hipStream_t or NULL                                             */
+    void*   workspace;       /* device scratch of workspace_bytes, or NULL (library allocates) */
+    size_t  workspace_bytes;
+    bxs_pass_record* history;/* HOST array for per-pass records, or NULL                        */
+    long    history_cap;     /* capacity of history (records beyond it are dropped)            */
+    int     profile;         /* 1: time every primal-iteration sweep with HIP events recorded on
+                                opts->stream and report it in info.sweep_ms / sweep_launches  */
+} bxs_opts;
+
+typedef struct {
+    int    status;      /* bxs_status of this instance                                  */
+    int    t_valid;     /* 0 when the theta = 0 fallback was used                       */
+    long   iters;       /* primal iterations done                                       */
+    long   passes;      /* screening passes done                                        */
+    long   n_active;    /* preserved coordinates at exit                                */
+    long   n_lower;     /* coordinates screened at l                                    */
+    long   n_upper;     /* coordinates screened at u                                    */
+    double gap;         /* certified gap at the returned x                              */
+    double primal;      /* 1/2 ||Ax - y||^2 at the returned x                           */
+    double radius;      /* last safe radius                                             */
+    double eps;         /* last translation coefficient                                 */
+    double step;        /* PG step used                                                 */
+    double lipschitz;   /* power-iteration estimate of ||A||_2^2 (0 if step was given)  */
+    double ms_setup;    /* device time of the setup phase (column norms, A^T t, L)      */
+    double ms_solve;    /* device time of the iterations and screening passes           */
+    long   col_iters;   /* sum over primal iterations of the preserved-set size         */
+    double sweep_ms;    /* opts->profile: summed duration of the primal-iteration sweep
+                           launches (PG: fused A^T r / update / A x; CD: the sweep)      */
+    long   sweep_launches; /* opts->profile: number of timed sweep launches             */
+} bxs_info;
+
+/* Fill *opts with defaults: PG, screening on, K = 10, max_iter = 100000,
+ * eps_gap = 1e-6, step from power iteration, t = -1, default stream. */
+void bxs_default_opts(bxs_opts* opts);
+
+/* Bytes of device workspace a call with these sizes needs (m, n per instance). */
+bxs_status bxs_workspace_size(long m, long n, const bxs_opts* opts, size_t* bytes);
+bxs_status bxs_workspace_size_batch(long count, const long* m, const long* n,
+                                    const bxs_opts* opts, size_t* bytes);
+
+/* Bounded-variable / mixed LS (Alg. 1).
+ *   A    [lda*n] a_dtype, column-major            y [m]
+ *   l, u [n] bounds (u_j may be +inf)             x [n] in: start point (clipped
+ *   sat  [n] signed char out: -1 screened at l,      to the box), out: solution
+ *        +1 screened at u, 0 kept in the preserved set
+ *   info host, may be NULL.  Returns BXS_OK, BXS_MAXITER or an error code. */
+bxs_status solve_bvls(long m, long n, int a_dtype, const void* A, long lda,
+                      const double* y, const double* l, const double* u,
+                      double* x, signed char* sat, const bxs_opts* opts, bxs_info* info);
+
+/* Non-negative LS (Alg. 2): solve_bvls with l = 0, u = +inf, dual translation
+ * along opts->t (default -1, valid for A >= 0 with no zero column, Prop. 2). */
+bxs_status solve_nnls(long m, long n, int a_dtype, const void* A, long lda,
+                      const double* y, double* x, signed char* sat,
+                      const bxs_opts* opts, bxs_info* info);
+
+/* One independent problem of a batch (pointers are device pointers). */
+typedef struct {
+    long m, n, lda;
+    const void* A;       /* column-major, element type a_dtype of the call */
+    const double* y;     /* [m]                                            */
+    const double* l;     /* [n] or NULL (l = 0)                            */
+    const double* u;     /* [n] or NULL (u = +inf)                         */
+    double* x;           /* [n] in/out                                     */
+    signed char* sat;    /* [n] out                                        */
+} bxs_problem;
+
+/* Uneven batch: `count` independent problems of different shapes solved
+ * together, every kernel launch covering all unfinished problems.  probs and
+ * infos are HOST arrays of length count; infos may be NULL.  opts->history is
+ * ignored.  Returns BXS_OK when every problem reached its gap, BXS_MAXITER
+ * when at least one did not, or the first error. */
+bxs_status solve_bvls_varbatch(long count, int a_dtype, const bxs_problem* probs,
+                               const bxs_opts* opts, bxs_info* infos);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* bxs_last_error(void);
+
+/* Library version string. */
+const char* bxs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BOXSCREEN_H */

@@ -1,0 +1,569 @@
+// Host driver and C ABI of the boxscreen library.
+//
+// The driver validates arguments, lays out one workspace for all instances of
+// a call, and runs the screening loop of Alg. 1:
+//   setup : x0 clipped, y' = y, column norms, w = A^T t, step from power
+//           iteration on A A^T (unless given), r = y' - A x0;
+//   pass  : K primal iterations (PG: fused g = A_P^T r / update / A_P x sweep
+//           + partial reduction; CD: one sequential sweep per instance), a
+//           correlation sweep g = A_P^T r, the screening kernel (dual point,
+//           gap, radius, safe rule, compaction) and the fold of the newly
+//           screened columns into y' and r;
+//   stop  : after each pass the host reads one counter of stopped instances.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "bxs_internal.h"
+
+namespace bxs {
+
+static thread_local std::string g_last_error;
+
+static bxs_status fail(bxs_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define BXS_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(BXS_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct InstSpec {
+    long m, n, lda;
+    const void* A;
+    const double *y, *l, *u;
+    double* x;
+    signed char* sat;
+};
+
+struct PlanSizes {
+    int items_cap;
+    int g_target;
+    size_t bytes;
+};
+
+// Per-instance device bytes.
+static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap)
+{
+    PlanSizes p;
+    p.g_target = g_target;
+    long cap = std::max<long>((long)g_target + 1, (n + kCbMax - 1) / kCbMax);
+    cap = std::min<long>(cap, (n + kCbMin - 1) / kCbMin);
+    p.items_cap = (int)std::max<long>(cap, 1);
+    size_t b = 0;
+    b += align_up(sizeof(double) * 2 * m, 256);                   // yp, r
+    b += align_up(sizeof(double) * 6 * n, 256);                   // g, w, cn, cn2, fval, fdx
+    b += align_up(sizeof(int) * 2 * n, 256);                      // idx, fidx
+    b += align_up(sizeof(double) * 2 * (size_t)p.items_cap * m, 256);  // part, part2
+    b += align_up(sizeof(double) * p.items_cap, 256);             // iscal
+    b += align_up(sizeof(bxs_pass_record) * std::max<long>(rec_cap, 0), 256);
+    p.bytes = b;
+    return p;
+}
+
+static int device_cus()
+{
+    static thread_local int cached = 0;
+    if (cached) return cached;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    cached = cus;
+    return cus;
+}
+
+// Work-group targets: spread the columns of each instance over a share of
+// 2 x CUs workgroups proportional to its size m*n (at least one).
+static std::vector<int> group_targets(const std::vector<InstSpec>& specs, int cus)
+{
+    double total = 0.0;
+    for (auto& s : specs) total += (double)s.m * (double)s.n;
+    std::vector<int> g(specs.size());
+    for (size_t i = 0; i < specs.size(); ++i) {
+        const double share = total > 0 ? (double)specs[i].m * (double)specs[i].n / total : 1.0;
+        g[i] = std::max(1, (int)ceil(2.0 * cus * share));
+    }
+    return g;
+}
+
+static size_t common_bytes(long count, long total_items, long total_ritems)
+{
+    size_t b = 0;
+    b += align_up(sizeof(Inst) * count, 256);
+    b += align_up(sizeof(State) * count, 256);
+    b += align_up(sizeof(Item) * total_items, 256);
+    b += align_up(sizeof(RItem) * total_ritems, 256);
+    b += align_up(sizeof(int) * (count + 16), 256);               // instance lists + counter
+    return b;
+}
+
+static bxs_status check_opts(const bxs_opts* o)
+{
+    if (!o) return fail(BXS_ERR_ARG, "opts is NULL");
+    if (o->solver != BXS_PG && o->solver != BXS_CD) return fail(BXS_ERR_ARG, "unknown solver %d", o->solver);
+    if (o->screening != 0 && o->screening != 1) return fail(BXS_ERR_ARG, "screening must be 0 or 1");
+    if (o->screen_every < 1) return fail(BXS_ERR_ARG, "screen_every must be >= 1");
+    if (o->max_iter < 1) return fail(BXS_ERR_ARG, "max_iter must be >= 1");
+    if (!(o->eps_gap >= 0.0) || isinf(o->eps_gap)) return fail(BXS_ERR_ARG, "eps_gap must be finite and >= 0");
+    if (isnan(o->step) || isinf(o->step)) return fail(BXS_ERR_ARG, "step must be finite");
+    if (o->workspace && o->workspace_bytes == 0) return fail(BXS_ERR_ARG, "workspace given with 0 bytes");
+    if (o->history && o->history_cap < 0) return fail(BXS_ERR_ARG, "history_cap < 0");
+    return BXS_OK;
+}
+
+static bxs_status check_spec(const InstSpec& s, long i)
+{
+    if (s.m < 1 || s.n < 1) return fail(BXS_ERR_SHAPE, "problem %ld: m=%ld n=%ld must be >= 1", i, s.m, s.n);
+    if (s.lda < s.m) return fail(BXS_ERR_SHAPE, "problem %ld: lda=%ld < m=%ld", i, s.lda, s.m);
+    if (s.m > BXS_MAX_ROWS) return fail(BXS_ERR_SHAPE, "problem %ld: m=%ld exceeds %d rows", i, s.m, BXS_MAX_ROWS);
+    if (s.n > 0x7fffffffL / 2) return fail(BXS_ERR_SHAPE, "problem %ld: n=%ld too large", i, s.n);
+    if (!s.A || !s.y || !s.x || !s.sat) return fail(BXS_ERR_ARG, "problem %ld: NULL array argument", i);
+    return BXS_OK;
+}
+
+struct Plan {
+    std::vector<InstSpec> specs;
+    std::vector<PlanSizes> sizes;
+    std::vector<Inst> insts;                 // host copy of the device descriptors
+    std::vector<Item> items[kNumBuckets];
+    std::vector<RItem> ritems;
+    std::vector<int> cd_list[kNumBuckets];
+    long rec_cap = 0;
+    int vec = 1;
+    size_t bytes = 0;
+};
+
+static bxs_status build_plan(Plan& P, int dtype, long rec_cap)
+{
+    const long count = (long)P.specs.size();
+    const int cus = device_cus();
+    std::vector<int> g = group_targets(P.specs, cus);
+    P.rec_cap = rec_cap;
+    P.sizes.resize(count);
+    long total_items = 0;
+    size_t inst_bytes = 0;
+    const size_t esz = dtype == BXS_F32 ? 4 : 8;
+    const int vecw = dtype == BXS_F32 ? 4 : 2;
+    P.vec = 1;
+    for (long i = 0; i < count; ++i) {
+        const InstSpec& s = P.specs[i];
+        P.sizes[i] = instance_sizes(s.m, s.n, g[i], (i == 0 && count == 1) ? rec_cap : 0);
+        total_items += P.sizes[i].items_cap;
+        inst_bytes += P.sizes[i].bytes;
+        if ((s.lda % vecw) != 0 || ((uintptr_t)s.A % 16) != 0) P.vec = 0;
+        (void)esz;
+    }
+    long total_ritems = 0;
+    for (auto& s : P.specs) total_ritems += (s.m + 63) / 64;
+    P.bytes = common_bytes(count, total_items, total_ritems) + inst_bytes + 256;
+    return BXS_OK;
+}
+
+// Lay out the workspace and fill the host-side descriptor / item tables.
+static void layout(Plan& P, char* base)
+{
+    const long count = (long)P.specs.size();
+    long total_items = 0, total_ritems = 0;
+    for (long i = 0; i < count; ++i) {
+        total_items += P.sizes[i].items_cap;
+        total_ritems += (P.specs[i].m + 63) / 64;
+    }
+    char* cur = (char*)align_up((uintptr_t)base, 256);
+    auto take = [&](size_t bytes) { char* p = cur; cur += align_up(bytes, 256); return p; };
+    take(sizeof(Inst) * count);
+    take(sizeof(State) * count);
+    take(sizeof(Item) * total_items);
+    take(sizeof(RItem) * total_ritems);
+    take(sizeof(int) * (count + 16));
+    P.insts.resize(count);
+    for (int b = 0; b < kNumBuckets; ++b) { P.items[b].clear(); P.cd_list[b].clear(); }
+    P.ritems.clear();
+    for (long i = 0; i < count; ++i) {
+        const InstSpec& s = P.specs[i];
+        const PlanSizes& z = P.sizes[i];
+        Inst I;
+        memset(&I, 0, sizeof(I));
+        I.A = s.A; I.lda = s.lda; I.m = (int)s.m; I.n = (int)s.n;
+        I.y = s.y; I.l = s.l; I.u = s.u; I.t = nullptr; I.x = s.x; I.sat = s.sat;
+        I.yp = (double*)take(sizeof(double) * 2 * s.m);
+        I.r = I.yp + s.m;
+        double* nv = (double*)take(sizeof(double) * 6 * s.n);
+        I.g = nv; I.w = nv + s.n; I.cn = nv + 2 * s.n; I.cn2 = nv + 3 * s.n;
+        I.fval = nv + 4 * s.n; I.fdx = nv + 5 * s.n;
+        int* iv = (int*)take(sizeof(int) * 2 * s.n);
+        I.idx = iv; I.fidx = iv + s.n;
+        I.part = (double*)take(sizeof(double) * 2 * (size_t)z.items_cap * s.m);
+        I.part2 = I.part + (size_t)z.items_cap * s.m;
+        I.iscal = (double*)take(sizeof(double) * z.items_cap);
+        const long rc = (i == 0 && count == 1) ? P.rec_cap : 0;
+        I.rec = rc > 0 ? (bxs_pass_record*)take(sizeof(bxs_pass_record) * rc) : nullptr;
+        I.rec_cap = (int)rc;
+        I.items_cap = z.items_cap;
+        I.g_target = z.g_target;
+        const int b = bucket_for_rows(s.m);
+        I.item_base = (int)P.items[b].size();
+        for (int t = 0; t < z.items_cap; ++t) P.items[b].push_back(Item{(int)i, t});
+        P.cd_list[b].push_back((int)i);
+        for (int rb = 0; rb < (int)((s.m + 63) / 64); ++rb) P.ritems.push_back(RItem{(int)i, rb});
+        P.insts[i] = I;
+    }
+}
+
+struct DevTables {
+    Inst* insts;
+    State* st;
+    Item* items[kNumBuckets];
+    int n_items[kNumBuckets];
+    RItem* ritems;
+    int n_ritems;
+    int* lists[kNumBuckets];
+    int n_list[kNumBuckets];
+    int* done_counter;
+};
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~PinnedBuf() { if (p) (void)hipHostFree(p); }
+};
+
+static bxs_status pinned(size_t bytes, void** out)
+{
+    static thread_local PinnedBuf buf;
+    if (buf.bytes < bytes) {
+        if (buf.p) (void)hipHostFree(buf.p);
+        buf.p = nullptr;
+        buf.bytes = 0;
+        BXS_HIP(hipHostMalloc(&buf.p, bytes, hipHostMallocDefault));
+        buf.bytes = bytes;
+    }
+    *out = buf.p;
+    return BXS_OK;
+}
+
+static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bxs_info* infos,
+                      bxs_pass_record* history, long history_cap)
+{
+    const long count = (long)P.specs.size();
+    hipStream_t stream = (hipStream_t)o->stream;
+    void* ws = o->workspace;
+    bool owned = false;
+    if (ws) {
+        if (o->workspace_bytes < P.bytes)
+            return fail(BXS_ERR_NOMEM, "workspace of %zu bytes, %zu needed", o->workspace_bytes, P.bytes);
+    } else {
+        if (hipMalloc(&ws, P.bytes) != hipSuccess) return fail(BXS_ERR_NOMEM, "hipMalloc(%zu) failed", P.bytes);
+        owned = true;
+    }
+    struct Guard {
+        void* p; bool own; hipStream_t s;
+        ~Guard() { if (own && p) { (void)hipStreamSynchronize(s); (void)hipFree(p); } }
+    } guard{ws, owned, stream};
+
+    layout(P, (char*)ws);
+    for (long i = 0; i < count; ++i) P.insts[i].t = t;
+
+    // device tables
+    DevTables D;
+    char* cur = (char*)align_up((uintptr_t)ws, 256);
+    long total_items = 0;
+    for (long i = 0; i < count; ++i) total_items += P.sizes[i].items_cap;
+    D.insts = (Inst*)cur; cur += align_up(sizeof(Inst) * count, 256);
+    D.st = (State*)cur; cur += align_up(sizeof(State) * count, 256);
+    Item* items_base = (Item*)cur; cur += align_up(sizeof(Item) * total_items, 256);
+    D.ritems = (RItem*)cur; cur += align_up(sizeof(RItem) * P.ritems.size(), 256);
+    int* ints = (int*)cur;
+    D.done_counter = ints + count;
+    D.n_ritems = (int)P.ritems.size();
+    std::vector<Item> all_items;
+    std::vector<int> all_lists;
+    long off = 0, loff = 0;
+    for (int b = 0; b < kNumBuckets; ++b) {
+        D.items[b] = items_base + off;
+        D.n_items[b] = (int)P.items[b].size();
+        all_items.insert(all_items.end(), P.items[b].begin(), P.items[b].end());
+        off += D.n_items[b];
+        D.lists[b] = ints + loff;
+        D.n_list[b] = (int)P.cd_list[b].size();
+        all_lists.insert(all_lists.end(), P.cd_list[b].begin(), P.cd_list[b].end());
+        loff += D.n_list[b];
+    }
+    // the per-bucket item lists were built with per-bucket positions; fix item_base
+    BXS_HIP(hipMemcpyAsync(D.insts, P.insts.data(), sizeof(Inst) * count, hipMemcpyHostToDevice, stream));
+    BXS_HIP(hipMemsetAsync(D.st, 0, sizeof(State) * count, stream));
+    BXS_HIP(hipMemcpyAsync(items_base, all_items.data(), sizeof(Item) * all_items.size(), hipMemcpyHostToDevice, stream));
+    BXS_HIP(hipMemcpyAsync(D.ritems, P.ritems.data(), sizeof(RItem) * P.ritems.size(), hipMemcpyHostToDevice, stream));
+    BXS_HIP(hipMemcpyAsync(ints, all_lists.data(), sizeof(int) * all_lists.size(), hipMemcpyHostToDevice, stream));
+    BXS_HIP(hipMemsetAsync(D.done_counter, 0, sizeof(int), stream));
+
+    LaunchCtx c;
+    c.stream = stream; c.dtype = dtype; c.vec = P.vec;
+    c.insts = D.insts; c.st = D.st; c.done_counter = D.done_counter;
+
+    hipEvent_t ev0, ev1, ev2;
+    BXS_HIP(hipEventCreate(&ev0));
+    BXS_HIP(hipEventCreate(&ev1));
+    BXS_HIP(hipEventCreate(&ev2));
+    struct EvGuard {
+        hipEvent_t a, b, c;
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); }
+    } eg{ev0, ev1, ev2};
+    BXS_HIP(hipEventRecord(ev0, stream));
+
+    // ---- setup ----
+    BXS_HIP(launch_init(c, (int)count, nullptr));
+    for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_colstats(c, b, D.items[b], D.n_items[b]));
+    const bool do_pow = !(o->step > 0.0);
+    if (do_pow) {
+        BXS_HIP(launch_pow_init(c, (int)count));
+        const int np = o->power_iters > 0 ? o->power_iters : 20;
+        for (int k = 0; k < np; ++k) {
+            for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModePow, D.items[b], D.n_items[b]));
+            BXS_HIP(launch_reduce(c, kRedPow, D.ritems, D.n_ritems));
+            BXS_HIP(launch_pow_normalize(c, (int)count, k == np - 1, 0.0));
+        }
+    } else {
+        BXS_HIP(launch_set_step(c, (int)count, o->step));
+    }
+    for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
+    BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+    BXS_HIP(hipEventRecord(ev1, stream));
+
+    // validation flags
+    std::vector<State> hst(count);
+    BXS_HIP(hipMemcpyAsync(hst.data(), D.st, sizeof(State) * count, hipMemcpyDeviceToHost, stream));
+    BXS_HIP(hipStreamSynchronize(stream));
+    for (long i = 0; i < count; ++i) {
+        if (hst[i].err & kErrNonfinite) return fail(BXS_ERR_NONFINITE, "problem %ld: non-finite value in A, y, x0, t or bounds", i);
+        if (hst[i].err & kErrBounds) return fail(BXS_ERR_BOUNDS, "problem %ld: l_j = -inf, u_j = -inf or l_j > u_j", i);
+    }
+
+    // ---- screening loop ----
+    int* hdone = nullptr;
+    {
+        void* pp = nullptr;
+        bxs_status s = pinned(64, &pp);
+        if (s != BXS_OK) return s;
+        hdone = (int*)pp;
+    }
+    const int K = o->screen_every;
+    long long iters = 0;
+    // optional per-launch timing of the primal-iteration sweeps
+    std::vector<hipEvent_t> pev;
+    struct PevGuard {
+        std::vector<hipEvent_t>* v;
+        ~PevGuard() { for (auto e : *v) (void)hipEventDestroy(e); }
+    } pguard{&pev};
+    if (o->profile) {
+        pev.resize(2 * (size_t)K);
+        for (auto& e : pev) BXS_HIP(hipEventCreate(&e));
+    }
+    double sweep_ms = 0.0;
+    long sweep_launches = 0;
+    while (true) {
+        const long long kk = std::min<long long>(K, o->max_iter - iters);
+        for (long long k = 0; k < kk; ++k) {
+            if (o->profile) BXS_HIP(hipEventRecord(pev[2 * k], stream));
+            if (o->solver == BXS_PG) {
+                for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModePG, D.items[b], D.n_items[b]));
+            } else {
+                for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_cd(c, b, D.lists[b], D.n_list[b], 1));
+            }
+            if (o->profile) BXS_HIP(hipEventRecord(pev[2 * k + 1], stream));
+            if (o->solver == BXS_PG) {
+                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+            } else {
+                // fresh residual from the updated iterate
+                for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
+                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+            }
+        }
+        iters += kk;
+        for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
+        const int final_pass = iters >= o->max_iter;
+        BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, iters, (int)kk));
+        if (o->screening) {
+            for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
+            BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));
+        }
+        BXS_HIP(hipMemcpyAsync(hdone, D.done_counter, sizeof(int), hipMemcpyDeviceToHost, stream));
+        BXS_HIP(hipStreamSynchronize(stream));
+        if (o->profile) {
+            for (long long k = 0; k < kk; ++k) {
+                float ms = 0.f;
+                BXS_HIP(hipEventElapsedTime(&ms, pev[2 * k], pev[2 * k + 1]));
+                sweep_ms += ms;
+                ++sweep_launches;
+            }
+        }
+        if (*hdone >= count || final_pass) break;
+    }
+    BXS_HIP(hipEventRecord(ev2, stream));
+    BXS_HIP(hipMemcpyAsync(hst.data(), D.st, sizeof(State) * count, hipMemcpyDeviceToHost, stream));
+    std::vector<bxs_pass_record> hrec;
+    long nrec = 0;
+    if (history && count == 1 && P.rec_cap > 0) {
+        hrec.resize(P.rec_cap);
+        BXS_HIP(hipMemcpyAsync(hrec.data(), P.insts[0].rec, sizeof(bxs_pass_record) * P.rec_cap,
+                               hipMemcpyDeviceToHost, stream));
+    }
+    BXS_HIP(hipStreamSynchronize(stream));
+    float ms_setup = 0.f, ms_solve = 0.f;
+    BXS_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
+    BXS_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
+
+    bxs_status worst = BXS_OK;
+    for (long i = 0; i < count; ++i) {
+        const State& S = hst[i];
+        const int status = S.done ? S.status : BXS_MAXITER;
+        if (status != BXS_OK) worst = (bxs_status)status;
+        if (infos) {
+            bxs_info& f = infos[i];
+            memset(&f, 0, sizeof(f));
+            f.status = status;
+            f.t_valid = S.t_valid;
+            f.iters = S.done ? S.iters : iters;
+            f.passes = S.passes;
+            f.n_active = S.n_active;
+            f.n_lower = S.n_lower;
+            f.n_upper = S.n_upper;
+            f.gap = S.gap;
+            f.primal = S.primal;
+            f.radius = S.radius;
+            f.eps = S.eps;
+            f.step = S.step;
+            f.lipschitz = S.lipschitz;
+            f.ms_setup = ms_setup;
+            f.ms_solve = ms_solve;
+            f.col_iters = S.col_iters;
+            f.sweep_ms = sweep_ms;
+            f.sweep_launches = sweep_launches;
+        }
+    }
+    if (history && count == 1) {
+        nrec = std::min<long>(hst[0].passes, std::min<long>(history_cap, P.rec_cap));
+        for (long k = 0; k < nrec; ++k) history[k] = hrec[k];
+    }
+    return worst;
+}
+
+}  // namespace bxs
+
+using namespace bxs;
+
+extern "C" {
+
+void bxs_default_opts(bxs_opts* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->solver = BXS_PG;
+    o->screening = 1;
+    o->screen_every = 10;
+    o->max_iter = 100000;
+    o->eps_gap = 1e-6;
+    o->step = 0.0;
+    o->power_iters = 20;
+}
+
+const char* bxs_last_error(void) { return g_last_error.c_str(); }
+
+const char* bxs_version(void) { return "boxscreen 0.1.0 (gfx950)"; }
+
+bxs_status bxs_workspace_size_batch(long count, const long* m, const long* n, const bxs_opts* opts, size_t* bytes)
+{
+    if (count < 1 || !m || !n || !bytes) return fail(BXS_ERR_ARG, "bad arguments to bxs_workspace_size_batch");
+    bxs_status s = check_opts(opts);
+    if (s != BXS_OK) return s;
+    Plan P;
+    P.specs.resize(count);
+    for (long i = 0; i < count; ++i) {
+        InstSpec& sp = P.specs[i];
+        memset(&sp, 0, sizeof(sp));
+        sp.m = m[i]; sp.n = n[i]; sp.lda = m[i];
+        if (sp.m < 1 || sp.n < 1 || sp.m > BXS_MAX_ROWS) return fail(BXS_ERR_SHAPE, "problem %ld: bad shape", i);
+    }
+    build_plan(P, BXS_F64, (count == 1 && opts->history) ? opts->history_cap : 0);
+    *bytes = P.bytes;
+    return BXS_OK;
+}
+
+bxs_status bxs_workspace_size(long m, long n, const bxs_opts* opts, size_t* bytes)
+{
+    return bxs_workspace_size_batch(1, &m, &n, opts, bytes);
+}
+
+static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const bxs_opts* opts, bxs_info* infos)
+{
+    g_last_error.clear();
+    bxs_status s = check_opts(opts);
+    if (s != BXS_OK) return s;
+    if (a_dtype != BXS_F64 && a_dtype != BXS_F32) return fail(BXS_ERR_ARG, "unknown a_dtype %d", a_dtype);
+    for (size_t i = 0; i < specs.size(); ++i) {
+        s = check_spec(specs[i], (long)i);
+        if (s != BXS_OK) return s;
+    }
+    Plan P;
+    P.specs = specs;
+    const long rc = (specs.size() == 1 && opts->history) ? opts->history_cap : 0;
+    s = build_plan(P, a_dtype, rc);
+    if (s != BXS_OK) return s;
+    return run(P, a_dtype, opts, opts->t, infos, opts->history, opts->history_cap);
+}
+
+bxs_status solve_bvls(long m, long n, int a_dtype, const void* A, long lda, const double* y, const double* l,
+                      const double* u, double* x, signed char* sat, const bxs_opts* opts, bxs_info* info)
+{
+    if (!l || !u) return fail(BXS_ERR_ARG, "solve_bvls needs both bound arrays (use solve_nnls for l=0, u=+inf)");
+    std::vector<InstSpec> specs(1);
+    specs[0] = InstSpec{m, n, lda, A, y, l, u, x, sat};
+    return solve_common(specs, a_dtype, opts, info);
+}
+
+bxs_status solve_nnls(long m, long n, int a_dtype, const void* A, long lda, const double* y, double* x,
+                      signed char* sat, const bxs_opts* opts, bxs_info* info)
+{
+    std::vector<InstSpec> specs(1);
+    specs[0] = InstSpec{m, n, lda, A, y, nullptr, nullptr, x, sat};
+    return solve_common(specs, a_dtype, opts, info);
+}
+
+bxs_status solve_bvls_varbatch(long count, int a_dtype, const bxs_problem* probs, const bxs_opts* opts,
+                               bxs_info* infos)
+{
+    if (count < 1 || !probs) return fail(BXS_ERR_ARG, "count < 1 or probs is NULL");
+    if (!opts) return fail(BXS_ERR_ARG, "opts is NULL");
+    std::vector<InstSpec> specs(count);
+    for (long i = 0; i < count; ++i) {
+        const bxs_problem& p = probs[i];
+        specs[i] = InstSpec{p.m, p.n, p.lda, p.A, p.y, p.l, p.u, p.x, p.sat};
+    }
+    bxs_opts o2 = *opts;
+    o2.history = nullptr;
+    o2.history_cap = 0;
+    return solve_common(specs, a_dtype, &o2, infos);
+}
+
+}  // extern "C"

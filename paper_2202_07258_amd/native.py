@@ -1,0 +1,265 @@
+"""ctypes binding of libboxscreen.so: argument marshalling only.
+
+Every function takes PyTorch tensors that already live on the GPU, passes
+their device pointers and the current HIP stream to the C ABI declared in
+include/boxscreen.h, and returns the output tensors plus the info record.  All
+arithmetic of the solve happens in the library's HIP kernels; there is no
+fallback of any kind: if the shared library is missing or fails to load, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Any
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIBRARY_PATH = os.path.join(_PKG, "libboxscreen.so")
+
+BXS_OK, BXS_ERR_ARG, BXS_ERR_SHAPE, BXS_ERR_NONFINITE, BXS_ERR_BOUNDS, BXS_ERR_DEVICE, BXS_ERR_NOMEM, BXS_MAXITER = range(8)
+STATUS_NAMES = {0: "ok", 1: "err_arg", 2: "err_shape", 3: "err_nonfinite", 4: "err_bounds",
+                5: "err_device", 6: "err_nomem", 7: "maxiter"}
+BXS_PG, BXS_CD = 0, 1
+BXS_F64, BXS_F32 = 0, 1
+MAX_ROWS = 16384
+
+
+class PassRecord(C.Structure):
+    _fields_ = [("iters", C.c_long), ("n_active", C.c_long), ("gap", C.c_double), ("radius", C.c_double),
+                ("eps", C.c_double), ("primal", C.c_double), ("n_screened", C.c_long)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("solver", C.c_int), ("screening", C.c_int), ("screen_every", C.c_int),
+                ("max_iter", C.c_long), ("eps_gap", C.c_double), ("step", C.c_double),
+                ("power_iters", C.c_int), ("t", C.c_void_p), ("stream", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("history", C.POINTER(PassRecord)), ("history_cap", C.c_long), ("profile", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("status", C.c_int), ("t_valid", C.c_int), ("iters", C.c_long), ("passes", C.c_long),
+                ("n_active", C.c_long), ("n_lower", C.c_long), ("n_upper", C.c_long),
+                ("gap", C.c_double), ("primal", C.c_double), ("radius", C.c_double), ("eps", C.c_double),
+                ("step", C.c_double), ("lipschitz", C.c_double), ("ms_setup", C.c_double),
+                ("ms_solve", C.c_double), ("col_iters", C.c_long), ("sweep_ms", C.c_double),
+                ("sweep_launches", C.c_long)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("m", C.c_long), ("n", C.c_long), ("lda", C.c_long), ("A", C.c_void_p),
+                ("y", C.c_void_p), ("l", C.c_void_p), ("u", C.c_void_p), ("x", C.c_void_p),
+                ("sat", C.c_void_p)]
+
+
+EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls",
+            "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version"]
+
+_lib = None
+
+
+def load(path: str = LIBRARY_PATH) -> C.CDLL:
+    """Load libboxscreen.so (raises if it is absent: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(hipcc --offload-arch=gfx950); the solvers have no CPU fallback")
+    lib = C.CDLL(path)
+    lib.bxs_default_opts.argtypes = [C.POINTER(Opts)]
+    lib.bxs_default_opts.restype = None
+    lib.bxs_workspace_size.argtypes = [C.c_long, C.c_long, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+    lib.bxs_workspace_size.restype = C.c_int
+    lib.bxs_workspace_size_batch.argtypes = [C.c_long, C.POINTER(C.c_long), C.POINTER(C.c_long),
+                                             C.POINTER(Opts), C.POINTER(C.c_size_t)]
+    lib.bxs_workspace_size_batch.restype = C.c_int
+    lib.solve_bvls.argtypes = [C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]
+    lib.solve_bvls.restype = C.c_int
+    lib.solve_nnls.argtypes = [C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]
+    lib.solve_nnls.restype = C.c_int
+    lib.solve_bvls_varbatch.argtypes = [C.c_long, C.c_int, C.POINTER(Problem), C.POINTER(Opts), C.POINTER(Info)]
+    lib.solve_bvls_varbatch.restype = C.c_int
+    lib.bxs_last_error.argtypes = []
+    lib.bxs_last_error.restype = C.c_char_p
+    lib.bxs_version.argtypes = []
+    lib.bxs_version.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class BoxscreenError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _check_matrix(A: torch.Tensor):
+    if not (A.is_cuda and A.dim() == 2):
+        raise ValueError("A must be a 2-D tensor on the GPU")
+    if A.dtype not in (torch.float32, torch.float64):
+        raise ValueError("A must be float32 or float64")
+    m, n = A.shape
+    if A.stride(0) != 1 and m > 1:
+        raise ValueError("A must be column-major (stride(0) == 1); use colmajor()")
+    lda = A.stride(1) if n > 1 else max(m, 1)
+    return m, n, max(lda, m), (BXS_F32 if A.dtype == torch.float32 else BXS_F64)
+
+
+def _vec(v: torch.Tensor | None, length: int, name: str):
+    if v is None:
+        return None
+    if not (v.is_cuda and v.dtype == torch.float64 and v.dim() == 1 and v.numel() == length and v.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 GPU vector of length {length}")
+    return v
+
+
+def colmajor(A: Any, device="cuda", dtype=None) -> torch.Tensor:
+    """(m, n) column-major GPU tensor from a numpy array or tensor (copy)."""
+    T = torch.as_tensor(A)
+    if dtype is not None:
+        T = T.to(dtype)
+    return T.t().contiguous().to(device).t()
+
+
+def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, eps_gap=1e-6, step=0.0,
+              power_iters=20, t: torch.Tensor | None = None, history=0, stream=None,
+              profile=False) -> tuple[Opts, Any]:
+    lib = load()
+    o = Opts()
+    lib.bxs_default_opts(C.byref(o))
+    o.solver = {"pg": BXS_PG, "cd": BXS_CD}[solver] if isinstance(solver, str) else int(solver)
+    o.screening = 1 if screening else 0
+    o.screen_every = int(screen_every)
+    o.max_iter = int(max_iter)
+    o.eps_gap = float(eps_gap)
+    o.step = float(step)
+    o.power_iters = int(power_iters)
+    o.t = _ptr(t)
+    o.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    o.profile = 1 if profile else 0
+    hist = None
+    if history:
+        hist = (PassRecord * int(history))()
+        o.history = C.cast(hist, C.POINTER(PassRecord))
+        o.history_cap = int(history)
+    return o, hist
+
+
+def _info_dict(info: Info, hist=None, n_hist=0) -> dict:
+    d = {f: getattr(info, f) for f, _ in Info._fields_}
+    d["status_name"] = STATUS_NAMES.get(info.status, str(info.status))
+    if hist is not None:
+        d["history"] = [{f: getattr(hist[k], f) for f, _ in PassRecord._fields_} for k in range(n_hist)]
+    return d
+
+
+def _raise(lib, status):
+    msg = lib.bxs_last_error().decode()
+    raise BoxscreenError(status, msg)
+
+
+def workspace_bytes(m: int, n: int, opts: Opts) -> int:
+    lib = load()
+    b = C.c_size_t(0)
+    st = lib.bxs_workspace_size(int(m), int(n), C.byref(opts), C.byref(b))
+    if st != BXS_OK:
+        _raise(lib, st)
+    return int(b.value)
+
+
+def _run_single(kind, A, y, l, u, x0, kw):
+    lib = load()
+    m, n, lda, dt = _check_matrix(A)
+    dev = A.device
+    y = _vec(y, m, "y")
+    if kind == "bvls":
+        l = _vec(l, n, "l")
+        u = _vec(u, n, "u")
+    t = _vec(kw.pop("t", None), m, "t")
+    x = torch.zeros(n, dtype=torch.float64, device=dev) if x0 is None else _vec(x0, n, "x0").clone()
+    sat = torch.empty(n, dtype=torch.int8, device=dev)
+    opts, hist = make_opts(t=t, **kw)
+    wbytes = workspace_bytes(m, n, opts)
+    wst = torch.empty(wbytes, dtype=torch.uint8, device=dev)
+    opts.workspace = wst.data_ptr()
+    opts.workspace_bytes = wbytes
+    info = Info()
+    if kind == "bvls":
+        st = lib.solve_bvls(m, n, dt, A.data_ptr(), lda, y.data_ptr(), l.data_ptr(), u.data_ptr(),
+                            x.data_ptr(), sat.data_ptr(), C.byref(opts), C.byref(info))
+    else:
+        st = lib.solve_nnls(m, n, dt, A.data_ptr(), lda, y.data_ptr(), x.data_ptr(), sat.data_ptr(),
+                            C.byref(opts), C.byref(info))
+    if st not in (BXS_OK, BXS_MAXITER):
+        _raise(lib, st)
+    n_hist = min(int(info.passes), int(opts.history_cap)) if hist is not None else 0
+    return x, sat, _info_dict(info, hist, n_hist)
+
+
+def solve_bvls(A, y, l, u, x0=None, **kw):
+    """Box-constrained LS via libboxscreen (Alg. 1).  Returns (x, sat, info)."""
+    return _run_single("bvls", A, y, l, u, x0, dict(kw))
+
+
+def solve_nnls(A, y, x0=None, **kw):
+    """Non-negative LS via libboxscreen (Alg. 2).  Returns (x, sat, info)."""
+    return _run_single("nnls", A, y, None, None, x0, dict(kw))
+
+
+def solve_bvls_varbatch(problems: list[dict], **kw):
+    """Uneven batch.  Each problem is a dict with A (column-major GPU tensor),
+    y, l, u (GPU float64; l/u may be None), optional x0.  All matrices must
+    share one dtype.  Returns (xs, sats, infos, status)."""
+    lib = load()
+    count = len(problems)
+    arr = (Problem * count)()
+    xs, sats, keep = [], [], []
+    dt0 = None
+    ms = (C.c_long * count)()
+    ns = (C.c_long * count)()
+    for i, p in enumerate(problems):
+        m, n, lda, dt = _check_matrix(p["A"])
+        if dt0 is None:
+            dt0 = dt
+        elif dt != dt0:
+            raise ValueError("all matrices of a batch must share one dtype")
+        y = _vec(p["y"], m, "y")
+        l = _vec(p.get("l"), n, "l")
+        u = _vec(p.get("u"), n, "u")
+        x0 = p.get("x0")
+        x = torch.zeros(n, dtype=torch.float64, device=p["A"].device) if x0 is None else _vec(x0, n, "x0").clone()
+        sat = torch.empty(n, dtype=torch.int8, device=p["A"].device)
+        arr[i] = Problem(m, n, lda, p["A"].data_ptr(), y.data_ptr(), _ptr(l), _ptr(u), x.data_ptr(), sat.data_ptr())
+        xs.append(x)
+        sats.append(sat)
+        keep.append((y, l, u))
+        ms[i] = m
+        ns[i] = n
+    kw = dict(kw)
+    kw.pop("history", None)
+    opts, _ = make_opts(**kw)
+    b = C.c_size_t(0)
+    st = lib.bxs_workspace_size_batch(count, ms, ns, C.byref(opts), C.byref(b))
+    if st != BXS_OK:
+        _raise(lib, st)
+    wst = torch.empty(int(b.value), dtype=torch.uint8, device=problems[0]["A"].device)
+    opts.workspace = wst.data_ptr()
+    opts.workspace_bytes = int(b.value)
+    infos = (Info * count)()
+    st = lib.solve_bvls_varbatch(count, dt0, arr, C.byref(opts), infos)
+    if st not in (BXS_OK, BXS_MAXITER):
+        _raise(lib, st)
+    return xs, sats, [_info_dict(infos[i]) for i in range(count)], STATUS_NAMES[st]
+
+
+def version() -> str:
+    return load().bxs_version().decode()

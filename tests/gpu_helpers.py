@@ -1,0 +1,83 @@
+"""Shared helpers for the GPU parity tests: run one problem through the HIP
+library and through the FP64 oracle with identical inputs and schedule."""
+import numpy as np
+import torch
+
+from oracle import boxls as ob
+
+
+def to_dev(P, device="cuda"):
+    import paper_2202_07258_amd as bx
+    A = bx.colmajor(P.A, device=device)
+    y = torch.tensor(P.y, dtype=torch.float64, device=device)
+    l = torch.tensor(P.l, dtype=torch.float64, device=device)
+    u = torch.tensor(P.u, dtype=torch.float64, device=device)
+    return A, y, l, u
+
+
+def run_gpu(P, kind, **kw):
+    import paper_2202_07258_amd as bx
+    A, y, l, u = to_dev(P)
+    x0 = kw.pop("x0", None)
+    if x0 is not None:
+        x0 = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    t = kw.pop("t", None)
+    if t is not None:
+        kw["t"] = torch.tensor(t, dtype=torch.float64, device="cuda")
+    if kind == "nnls":
+        x, sat, info = bx.solve_nnls(A, y, x0, **kw)
+    else:
+        x, sat, info = bx.solve_bvls(A, y, l, u, x0, **kw)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), sat.cpu().numpy(), info
+
+
+def run_oracle(P, *, solver="pg", screen_every=10, eps_gap=1e-6, max_iter=100000, step=None,
+               screening=True, x0=None, t=None):
+    return ob.solve(P.A64(), P.y, P.l, P.u, solver=solver, K=screen_every, eps_gap=eps_gap,
+                    max_iter=max_iter, step=step, screening=screening, x0=x0, t=t)
+
+
+def assert_parity(P, xg, satg, info, res, xtol=1e-9, gap_rtol=1e-6, check_status=True):
+    """Trajectory parity: same stop pass, same iterate (to xtol relative to
+    max(1, ||x||_inf)), identical screened sets, matching gap."""
+    if check_status:
+        assert info["status_name"] == res.status, (info, res.status, res.gap)
+    assert info["iters"] == res.iters and info["passes"] == res.passes, (info["iters"], res.iters, info["passes"], res.passes)
+    scale = max(1.0, float(np.max(np.abs(res.x))))
+    err = float(np.max(np.abs(xg - res.x)))
+    assert err <= xtol * scale, err
+    np.testing.assert_array_equal(satg, res.sat)
+    yy = 0.5 * float(P.y @ P.y)
+    assert info["gap"] >= res.gap - 1e-12 * (1 + yy)          # certified bound is never below
+    assert abs(info["gap"] - res.gap) <= gap_rtol * abs(res.gap) + 1e-11 * (1 + yy)
+    assert bool(info["t_valid"]) == res.t_valid
+
+
+ORACLE_KEYS = ("solver", "screen_every", "eps_gap", "max_iter", "step", "screening", "x0", "t")
+
+
+def parity_vs_oracle(P, xg, sg, info, xtol=1e-9, **kw):
+    """Check one GPU result against the oracle run with the same schedule.
+
+    The GPU's gap is a certified upper bound (it carries rounding margins), so
+    it is never below the oracle's and can only stop later.  When the oracle's
+    last gap sits within 5% under eps_gap and the GPU needs exactly one more
+    pass, the GPU result is compared with the oracle run for the same number of
+    iterations instead."""
+    okw = {k: v for k, v in kw.items() if k in ORACLE_KEYS}
+    res = run_oracle(P, **okw)
+    status_ok = True
+    if (info["passes"] == res.passes + 1 and res.status == "ok"
+            and res.gap >= 0.95 * okw.get("eps_gap", 1e-6)):
+        res = run_oracle(P, **dict(okw, eps_gap=0.0, max_iter=info["iters"]))
+        status_ok = False
+    assert_parity(P, xg, sg, info, res, xtol=xtol, check_status=status_ok)
+    return res
+
+
+def check_parity(P, kind, xtol=1e-9, **kw):
+    """Run the GPU path on P and check trajectory parity with the oracle."""
+    xg, sg, info = run_gpu(P, kind, **dict(kw))
+    res = parity_vs_oracle(P, xg, sg, info, xtol=xtol, **kw)
+    return xg, sg, info, res

@@ -1,0 +1,94 @@
+"""C-ABI checks that need no GPU: the shared library loads, exports every
+function that include/boxscreen.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2202_07258_amd import native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "boxscreen.h")
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*([A-Za-z_][A-Za-z_0-9]*)\s*\(",
+                       txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(N.LIBRARY_PATH):
+        pytest.fail("libboxscreen.so not built: run __graft_entry__.build()")
+    return N.load()
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared_functions()
+    for n in ["solve_bvls", "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
+              "bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(N.EXPORTED) == sorted(_declared_functions())
+
+
+def test_default_opts(lib):
+    o = N.Opts()
+    lib.bxs_default_opts(C.byref(o))
+    assert (o.solver, o.screening, o.screen_every, o.max_iter, o.eps_gap, o.step, o.power_iters) == \
+        (0, 1, 10, 100000, 1e-6, 0.0, 20)
+    assert not o.t and not o.workspace and not o.stream
+
+
+def _opts(lib, **kw):
+    o = N.Opts()
+    lib.bxs_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+FAKE = 1 << 20   # never dereferenced: every case below fails validation first
+
+
+@pytest.mark.parametrize("m,n,lda,code", [(0, 5, 1, N.BXS_ERR_SHAPE), (5, 0, 5, N.BXS_ERR_SHAPE),
+                                          (5, 5, 4, N.BXS_ERR_SHAPE), (20000, 5, 20000, N.BXS_ERR_SHAPE)])
+def test_shape_errors(lib, m, n, lda, code):
+    o = _opts(lib)
+    info = N.Info()
+    st = lib.solve_bvls(m, n, 0, FAKE, lda, FAKE, FAKE, FAKE, FAKE, FAKE, C.byref(o), C.byref(info))
+    assert st == code
+    assert lib.bxs_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value", [("solver", 7), ("screening", 2), ("screen_every", 0),
+                                         ("max_iter", 0), ("eps_gap", -1.0), ("eps_gap", float("inf")),
+                                         ("step", float("nan"))])
+def test_option_errors(lib, field, value):
+    o = _opts(lib, **{field: value})
+    st = lib.solve_nnls(8, 8, 0, FAKE, 8, FAKE, FAKE, FAKE, C.byref(o), None)
+    assert st == N.BXS_ERR_ARG
+
+
+def test_null_arguments(lib):
+    o = _opts(lib)
+    assert lib.solve_bvls(8, 8, 0, None, 8, FAKE, FAKE, FAKE, FAKE, FAKE, C.byref(o), None) == N.BXS_ERR_ARG
+    assert lib.solve_bvls(8, 8, 0, FAKE, 8, FAKE, None, FAKE, FAKE, FAKE, C.byref(o), None) == N.BXS_ERR_ARG
+    assert lib.solve_nnls(8, 8, 0, FAKE, 8, FAKE, FAKE, FAKE, None, None) == N.BXS_ERR_ARG
+    assert lib.solve_nnls(8, 8, 5, FAKE, 8, FAKE, FAKE, FAKE, C.byref(o), None) == N.BXS_ERR_ARG
+    assert lib.solve_bvls_varbatch(0, 0, None, C.byref(o), None) == N.BXS_ERR_ARG
+
+
+def test_workspace_query_shape_check(lib):
+    o = _opts(lib)
+    b = C.c_size_t(0)
+    assert lib.bxs_workspace_size(0, 10, C.byref(o), C.byref(b)) == N.BXS_ERR_SHAPE

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs, same step, same schedule.  Sizes span several work items
+and a ragged tail of columns and rows, every kernel bucket of m, FP64 and FP32
+storage, PG and CD, NNLS / BVLS / mixed bounds, screened and unscreened.
+
+Tolerance: both sides compute in FP64, so trajectory parity is checked at
+1e-9 relative to max(1, ||x||_inf), far inside the 1e-6 (FP64) and 1e-4
+(FP32 storage) bars; screened sets must be identical."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import boxls as ob
+from synth import workloads as W
+from tests.gpu_helpers import assert_parity, check_parity, parity_vs_oracle, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def planted(seed, m, n, nf_frac=0.4, scale=0.05, dtype=np.float64, box=None):
+    rng = W.rng_for(90, seed, m, n)
+    A = np.asfortranarray(W.unit_columns(rng.standard_normal((m, n))).astype(dtype))
+    if box is None:
+        l, u = -rng.random(n), rng.random(n)
+    else:
+        l, u = np.full(n, box[0]), np.full(n, box[1])
+    y, x, th, F = W.planted_bvls(A, l, u, int(nf_frac * m), scale, rng)
+    return W.Problem(A, y, l, u, x, True, {})
+
+
+def step_of(P):
+    return 1.0 / (1.05 * ob.lipschitz(P.A64()))
+
+
+@pytest.mark.parametrize("m,n", [(50, 173), (120, 301), (300, 1000), (700, 1800), (1500, 3333), (3001, 6007)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_pg_bvls_trajectory_parity(m, n, dtype):
+    print(f"\n[pg bvls] m={m} n={n} {np.dtype(dtype).name}", flush=True)
+    P = planted(1, m, n, dtype=dtype)
+    eta = step_of(P)
+    kw = dict(screen_every=10, eps_gap=1e-8, max_iter=4000, step=eta)
+    xg, sg, info, res = check_parity(P, "bvls", **kw)
+    assert res.status == "ok" and np.count_nonzero(res.sat) > 0
+
+
+def test_pg_unscreened_parity():
+    P = planted(2, 300, 900)
+    eta = step_of(P)
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=5000, step=eta, screening=False)
+    xg, sg, info, res = check_parity(P, "bvls", **kw)
+    assert not np.any(sg)
+
+
+def test_pg_nnls_companion_parity():
+    P = W.c1_companion(0)                       # 200 x 500, A >= 0, t = -1 interior
+    eta = step_of(P)
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=3000, step=eta)
+    xg, sg, info, res = check_parity(P, "nnls", **kw)
+    assert info["t_valid"] == 1
+
+
+def test_pg_nnls_translation_screens():
+    # well-conditioned non-negative matrix: dual translation along t = -1
+    # certifies most zero coordinates within a few hundred iterations
+    rng = W.rng_for(93, 0)
+    n = 200
+    A = np.asfortranarray(np.diag(0.5 + rng.random(n)) + 0.05 * rng.random((n, n)))
+    P = W.Problem(A, rng.standard_normal(n), np.zeros(n), np.full(n, np.inf))
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=5000, step=step_of(P))
+    xg, sg, info, res = check_parity(P, "nnls", **kw)
+    assert res.status == "ok" and np.count_nonzero(sg) > n // 2 and info["eps"] >= 0.0
+
+
+def test_pg_nnls_c1_as_specified():
+    # signed Gaussian columns: t = -1 is not interior, theta = 0, nothing screened
+    P = W.c1_nnls(0)
+    eta = step_of(P)
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=4000, step=eta)
+    xg, sg, info, res = check_parity(P, "nnls", **kw)
+    assert info["t_valid"] == 0 and not np.any(sg) and info["status_name"] == "ok"
+
+
+def test_pg_nnls_user_direction():
+    # signed A with an interior direction from an LP: screening becomes possible
+    rng = W.rng_for(91, 0)
+    A = np.asfortranarray(rng.standard_normal((40, 60)))
+    t = W.interior_direction(A)
+    assert t is not None
+    y = rng.standard_normal(40)
+    P = W.Problem(A, y, np.zeros(60), np.full(60, np.inf))
+    eta = step_of(P)
+    kw = dict(screen_every=5, eps_gap=1e-10, max_iter=20000, step=eta, t=t)
+    xg, sg, info, res = check_parity(P, "nnls", **kw)
+
+
+def test_pg_mixed_bounds():
+    rng = W.rng_for(92, 0)
+    P = W.c1_companion(1, 100, 260)
+    u = P.u.copy()
+    u[::3] = 0.2 + rng.random(u[::3].size)
+    P = W.Problem(P.A, P.y, P.l, u)
+    eta = step_of(P)
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=3000, step=eta)
+    xg, sg, info, res = check_parity(P, "bvls", **kw)
+
+
+@pytest.mark.parametrize("m,n", [(40, 97), (200, 450)])
+def test_cd_parity(m, n):
+    print(f"\n[cd bvls] m={m} n={n}", flush=True)
+    P = planted(3, m, n)
+    kw = dict(solver="cd", screen_every=1, eps_gap=1e-10, max_iter=2000)
+    xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, **kw)
+
+
+def test_cd_nnls_parity():
+    P = W.c1_companion(2, 150, 400)
+    kw = dict(solver="cd", screen_every=1, eps_gap=1e-9, max_iter=3000)
+    xg, sg, info, res = check_parity(P, "nnls", xtol=1e-8, **kw)
+
+
+def test_power_iteration_step():
+    P = planted(4, 500, 1500, dtype=np.float32)
+    xg, sg, info = run_gpu(P, "bvls", eps_gap=1e-6, max_iter=50)
+    L = ob.lipschitz(P.A64())
+    assert 0.9 * L <= info["lipschitz"] <= L * (1 + 1e-12)
+    assert info["step"] == pytest.approx(1.0 / (1.05 * info["lipschitz"]), rel=1e-15)
+
+
+def test_warm_start_and_max_iter():
+    P = planted(5, 100, 300)
+    eta = step_of(P)
+    x0 = np.clip(np.random.default_rng(0).standard_normal(300), P.l, P.u)
+    kw = dict(screen_every=7, eps_gap=1e-14, max_iter=50, step=eta, x0=x0)
+    res = run_oracle(P, **kw)
+    xg, sg, info = run_gpu(P, "bvls", **kw)
+    assert info["status_name"] == "maxiter" and info["iters"] == 50
+    assert_parity(P, xg, sg, info, res)
+
+
+def test_edge_single_column_and_row():
+    rng = np.random.default_rng(7)
+    for m, n in [(1, 1), (1, 7), (9, 1)]:
+        A = np.asfortranarray(rng.standard_normal((m, n)))
+        P = W.Problem(A, rng.standard_normal(m), -np.ones(n), np.ones(n))
+        eta = step_of(P)
+        kw = dict(screen_every=3, eps_gap=1e-12, max_iter=3000, step=eta)
+        xg, sg, info, res = check_parity(P, "bvls", **kw)
+
+
+def test_everything_screened():
+    # orthonormal columns, 39 coordinates pushed far outside the box and one
+    # that reaches its bound slowly (step 0.3): the preserved set empties
+    Q, _ = np.linalg.qr(W.rng_for(94, 0).standard_normal((64, 40)))
+    c = 3.0 * np.sign(W.rng_for(94, 1).standard_normal(40))
+    c[39] = 0.55
+    P = W.Problem(np.asfortranarray(Q), Q @ c, -0.5 * np.ones(40), 0.5 * np.ones(40))
+    kw = dict(screen_every=1, eps_gap=1e-9, max_iter=100, step=0.3)
+    xg, sg, info, res = check_parity(P, "bvls", **kw)
+    assert info["n_active"] == 0 and np.all(sg != 0) and res.status == "ok"
+
+
+def test_determinism():
+    P = planted(6, 800, 2500, dtype=np.float32)
+    kw = dict(eps_gap=1e-8, max_iter=3000)
+    x1, s1, i1 = run_gpu(P, "bvls", **kw)
+    x2, s2, i2 = run_gpu(P, "bvls", **kw)
+    assert np.array_equal(x1, x2) and np.array_equal(s1, s2) and i1["iters"] == i2["iters"]
+
+
+def test_history_records():
+    P = planted(7, 200, 600)
+    eta = step_of(P)
+    res = run_oracle(P, screen_every=10, eps_gap=1e-9, step=eta)
+    xg, sg, info = run_gpu(P, "bvls", screen_every=10, eps_gap=1e-9, step=eta, history=1000)
+    h = info["history"]
+    assert len(h) == res.passes
+    for hg, ho in zip(h, res.history):
+        assert hg["iters"] == ho["iters"] and hg["n_active"] == ho["n_active"]
+        assert hg["gap"] == pytest.approx(ho["gap"], rel=1e-6, abs=1e-11)
+
+
+def test_device_side_validation():
+    import paper_2202_07258_amd as bx
+    P = planted(8, 30, 50)
+    A, y, l, u = (torch.tensor(v, device="cuda") for v in (P.A, P.y, P.l, P.u))
+    A = bx.colmajor(P.A)
+    ybad = y.clone(); ybad[3] = float("nan")
+    with pytest.raises(bx.BoxscreenError, match="err_nonfinite"):
+        bx.solve_bvls(A, ybad, l, u)
+    lbad = l.clone(); lbad[5] = u[5] + 1.0
+    with pytest.raises(bx.BoxscreenError, match="err_bounds"):
+        bx.solve_bvls(A, y, lbad, u)
+    lbad = l.clone(); lbad[5] = -float("inf")
+    with pytest.raises(bx.BoxscreenError, match="err_bounds"):
+        bx.solve_bvls(A, y, lbad, u)
+
+
+def test_varbatch_parity():
+    shapes = [(37, 120), (64, 200), (130, 300), (257, 700), (513, 1100), (1100, 2500), (2100, 4400)]
+    probs = [planted(10 + i, m, n, dtype=np.float32, box=(0.0, 1.0)) for i, (m, n) in enumerate(shapes)]
+    eta = 1.0 / (1.05 * max(ob.lipschitz(P.A64()) for P in probs))
+    import paper_2202_07258_amd as bx
+    from tests.gpu_helpers import to_dev
+    dev = []
+    for P in probs:
+        A, y, l, u = to_dev(P)
+        dev.append({"A": A, "y": y, "l": l, "u": u})
+    kw = dict(screen_every=10, eps_gap=1e-8, max_iter=5000, step=eta)
+    xs, sats, infos, status = bx.solve_bvls_varbatch(dev, **kw)
+    torch.cuda.synchronize()
+    for P, x, s, info in zip(probs, xs, sats, infos):
+        parity_vs_oracle(P, x.cpu().numpy(), s.cpu().numpy(), info, **kw)
+    assert status == "ok"
