@@ -164,6 +164,18 @@ typedef struct {
 bxs_status solve_bvls_varbatch(long count, int a_dtype, const bxs_problem* probs,
                                const bxs_opts* opts, bxs_info* infos);
 
+/* Kernel-shape tuning.  The column sweeps come in several compiled shapes
+ * ("variants": threads per column, column groups per workgroup, rows per
+ * thread, columns per round).  Each problem is assigned a row class, the
+ * smallest default variant that holds its m rows; bxs_set_sweep_variant
+ * selects which variant later calls use for a class (v < 0 restores the
+ * default).  These settings are process-wide and must not change while a
+ * solve is running.  Used by the autotuner, which times the candidates. */
+int        bxs_num_sweep_variants(void);
+bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi, long* capacity);
+int        bxs_row_class(long m);            /* -1 if m > BXS_MAX_ROWS */
+bxs_status bxs_set_sweep_variant(int row_class, int v);
+
 /* Thread-local description of the last error (empty string if none). */
 const char* bxs_last_error(void);
 

@@ -74,7 +74,7 @@ static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap)
     b += align_up(sizeof(double) * 6 * n, 256);                   // g, w, cn, cn2, fval, fdx
     b += align_up(sizeof(int) * 2 * n, 256);                      // idx, fidx
     b += align_up(sizeof(double) * 2 * (size_t)p.items_cap * m, 256);  // part, part2
-    b += align_up(sizeof(double) * p.items_cap, 256);             // iscal
+    b += align_up(sizeof(double) * kItemScalars * p.items_cap, 256);  // iscal
     b += align_up(sizeof(bxs_pass_record) * std::max<long>(rec_cap, 0), 256);
     p.bytes = b;
     return p;
@@ -94,16 +94,31 @@ static int device_cus()
     return cus;
 }
 
+// Sweep-variant preference per row-count class (the smallest default
+// variant whose capacity holds m); set by bxs_set_sweep_variant.
+static int g_variant_pref[kNumDefaultVariants] = {0, 1, 2, 3, 4, 21, 18, 7, 8};
+
+static int choose_variant(long m)
+{
+    const int cls = default_variant_for_rows(m);
+    if (cls < 0) return -1;
+    const int v = g_variant_pref[cls];
+    return (v >= 0 && v < kNumVariants && variant_capacity(v) >= m) ? v : cls;
+}
+
 // Work-group targets: spread the columns of each instance over a share of
-// 2 x CUs workgroups proportional to its size m*n (at least one).
-static std::vector<int> group_targets(const std::vector<InstSpec>& specs, int cus)
+// the chip's resident workgroups (CUs x kThreadsPerCU / workgroup size)
+// proportional to its size m*n, at least one.
+static std::vector<int> group_targets(const std::vector<InstSpec>& specs, const std::vector<int>& variant, int cus)
 {
     double total = 0.0;
     for (auto& s : specs) total += (double)s.m * (double)s.n;
     std::vector<int> g(specs.size());
     for (size_t i = 0; i < specs.size(); ++i) {
         const double share = total > 0 ? (double)specs[i].m * (double)specs[i].n / total : 1.0;
-        g[i] = std::max(1, (int)ceil(2.0 * cus * share));
+        const int wg = kVariants[variant[i]].tpc * kVariants[variant[i]].ng;
+        const double resident = (double)cus * std::max(1, kThreadsPerCU / wg);
+        g[i] = std::max(1, (int)ceil(resident * share));
     }
     return g;
 }
@@ -147,9 +162,10 @@ struct Plan {
     std::vector<InstSpec> specs;
     std::vector<PlanSizes> sizes;
     std::vector<Inst> insts;                 // host copy of the device descriptors
-    std::vector<Item> items[kNumBuckets];
+    std::vector<Item> items[kNumVariants];
     std::vector<RItem> ritems;
-    std::vector<int> cd_list[kNumBuckets];
+    std::vector<int> cd_list[kNumCdBuckets];
+    std::vector<int> variant;                // sweep variant per instance
     long rec_cap = 0;
     int vec = 1;
     size_t bytes = 0;
@@ -159,7 +175,9 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap)
 {
     const long count = (long)P.specs.size();
     const int cus = device_cus();
-    std::vector<int> g = group_targets(P.specs, cus);
+    P.variant.resize(count);
+    for (long i = 0; i < count; ++i) P.variant[i] = choose_variant(P.specs[i].m);
+    std::vector<int> g = group_targets(P.specs, P.variant, cus);
     P.rec_cap = rec_cap;
     P.sizes.resize(count);
     long total_items = 0;
@@ -198,7 +216,8 @@ static void layout(Plan& P, char* base)
     take(sizeof(RItem) * total_ritems);
     take(sizeof(int) * (count + 16));
     P.insts.resize(count);
-    for (int b = 0; b < kNumBuckets; ++b) { P.items[b].clear(); P.cd_list[b].clear(); }
+    for (int b = 0; b < kNumVariants; ++b) P.items[b].clear();
+    for (int b = 0; b < kNumCdBuckets; ++b) P.cd_list[b].clear();
     P.ritems.clear();
     for (long i = 0; i < count; ++i) {
         const InstSpec& s = P.specs[i];
@@ -216,16 +235,16 @@ static void layout(Plan& P, char* base)
         I.idx = iv; I.fidx = iv + s.n;
         I.part = (double*)take(sizeof(double) * 2 * (size_t)z.items_cap * s.m);
         I.part2 = I.part + (size_t)z.items_cap * s.m;
-        I.iscal = (double*)take(sizeof(double) * z.items_cap);
+        I.iscal = (double*)take(sizeof(double) * kItemScalars * z.items_cap);
         const long rc = (i == 0 && count == 1) ? P.rec_cap : 0;
         I.rec = rc > 0 ? (bxs_pass_record*)take(sizeof(bxs_pass_record) * rc) : nullptr;
         I.rec_cap = (int)rc;
         I.items_cap = z.items_cap;
         I.g_target = z.g_target;
-        const int b = bucket_for_rows(s.m);
+        const int b = P.variant[i];
         I.item_base = (int)P.items[b].size();
         for (int t = 0; t < z.items_cap; ++t) P.items[b].push_back(Item{(int)i, t});
-        P.cd_list[b].push_back((int)i);
+        P.cd_list[cd_bucket_for_rows(s.m)].push_back((int)i);
         for (int rb = 0; rb < (int)((s.m + 63) / 64); ++rb) P.ritems.push_back(RItem{(int)i, rb});
         P.insts[i] = I;
     }
@@ -234,12 +253,12 @@ static void layout(Plan& P, char* base)
 struct DevTables {
     Inst* insts;
     State* st;
-    Item* items[kNumBuckets];
-    int n_items[kNumBuckets];
+    Item* items[kNumVariants];
+    int n_items[kNumVariants];
     RItem* ritems;
     int n_ritems;
-    int* lists[kNumBuckets];
-    int n_list[kNumBuckets];
+    int* lists[kNumCdBuckets];
+    int n_list[kNumCdBuckets];
     int* done_counter;
 };
 
@@ -300,17 +319,18 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     std::vector<Item> all_items;
     std::vector<int> all_lists;
     long off = 0, loff = 0;
-    for (int b = 0; b < kNumBuckets; ++b) {
+    for (int b = 0; b < kNumVariants; ++b) {
         D.items[b] = items_base + off;
         D.n_items[b] = (int)P.items[b].size();
         all_items.insert(all_items.end(), P.items[b].begin(), P.items[b].end());
         off += D.n_items[b];
+    }
+    for (int b = 0; b < kNumCdBuckets; ++b) {
         D.lists[b] = ints + loff;
         D.n_list[b] = (int)P.cd_list[b].size();
         all_lists.insert(all_lists.end(), P.cd_list[b].begin(), P.cd_list[b].end());
         loff += D.n_list[b];
     }
-    // the per-bucket item lists were built with per-bucket positions; fix item_base
     BXS_HIP(hipMemcpyAsync(D.insts, P.insts.data(), sizeof(Inst) * count, hipMemcpyHostToDevice, stream));
     BXS_HIP(hipMemsetAsync(D.st, 0, sizeof(State) * count, stream));
     BXS_HIP(hipMemcpyAsync(items_base, all_items.data(), sizeof(Item) * all_items.size(), hipMemcpyHostToDevice, stream));
@@ -334,20 +354,20 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
 
     // ---- setup ----
     BXS_HIP(launch_init(c, (int)count, nullptr));
-    for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_colstats(c, b, D.items[b], D.n_items[b]));
+    for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_colstats(c, b, D.items[b], D.n_items[b]));
     const bool do_pow = !(o->step > 0.0);
     if (do_pow) {
         BXS_HIP(launch_pow_init(c, (int)count));
         const int np = o->power_iters > 0 ? o->power_iters : 20;
         for (int k = 0; k < np; ++k) {
-            for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModePow, D.items[b], D.n_items[b]));
+            for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModePow, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedPow, D.ritems, D.n_ritems));
             BXS_HIP(launch_pow_normalize(c, (int)count, k == np - 1, 0.0));
         }
     } else {
         BXS_HIP(launch_set_step(c, (int)count, o->step));
     }
-    for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
+    for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
     BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
     BXS_HIP(hipEventRecord(ev1, stream));
 
@@ -370,55 +390,87 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     }
     const int K = o->screen_every;
     long long iters = 0;
-    // optional per-launch timing of the primal-iteration sweeps
-    std::vector<hipEvent_t> pev;
+    // Passes are enqueued one ahead of the stop check: while the host waits
+    // for pass p's stop counter, pass p+1 is already queued (its kernels return
+    // at once for stopped instances), so the GPU never idles on the host.
+    // Optional per-launch timing of the primal-iteration sweeps.
+    std::vector<hipEvent_t> pev, dev_done(2);
     struct PevGuard {
         std::vector<hipEvent_t>* v;
-        ~PevGuard() { for (auto e : *v) (void)hipEventDestroy(e); }
-    } pguard{&pev};
+        std::vector<hipEvent_t>* w;
+        ~PevGuard() {
+            for (auto e : *v) if (e) (void)hipEventDestroy(e);
+            for (auto e : *w) if (e) (void)hipEventDestroy(e);
+        }
+    } pguard{&pev, &dev_done};
+    for (auto& e : dev_done) { e = nullptr; BXS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
     if (o->profile) {
-        pev.resize(2 * (size_t)K);
+        pev.assign(4 * (size_t)K, nullptr);
         for (auto& e : pev) BXS_HIP(hipEventCreate(&e));
     }
     double sweep_ms = 0.0;
     long sweep_launches = 0;
-    while (true) {
+    long long slot_kk[2] = {0, 0};
+    int slot_final[2] = {0, 0};
+
+    auto enqueue_pass = [&](int slot) -> bxs_status {
         const long long kk = std::min<long long>(K, o->max_iter - iters);
         for (long long k = 0; k < kk; ++k) {
-            if (o->profile) BXS_HIP(hipEventRecord(pev[2 * k], stream));
+            if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k], stream));
             if (o->solver == BXS_PG) {
-                for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModePG, D.items[b], D.n_items[b]));
+                for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModePG, D.items[b], D.n_items[b]));
             } else {
-                for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_cd(c, b, D.lists[b], D.n_list[b], 1));
+                for (int b = 0; b < kNumCdBuckets; ++b) BXS_HIP(launch_cd(c, b, D.lists[b], D.n_list[b], 1));
             }
-            if (o->profile) BXS_HIP(hipEventRecord(pev[2 * k + 1], stream));
+            if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k + 1], stream));
             if (o->solver == BXS_PG) {
                 BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
             } else {
                 // fresh residual from the updated iterate
-                for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
+                for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
                 BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
             }
         }
         iters += kk;
-        for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
+        for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
         const int final_pass = iters >= o->max_iter;
         BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, iters, (int)kk));
         if (o->screening) {
-            for (int b = 0; b < kNumBuckets; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
+            for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));
         }
-        BXS_HIP(hipMemcpyAsync(hdone, D.done_counter, sizeof(int), hipMemcpyDeviceToHost, stream));
-        BXS_HIP(hipStreamSynchronize(stream));
+        BXS_HIP(hipMemcpyAsync(hdone + slot, D.done_counter, sizeof(int), hipMemcpyDeviceToHost, stream));
+        BXS_HIP(hipEventRecord(dev_done[slot], stream));
+        slot_kk[slot] = kk;
+        slot_final[slot] = final_pass;
+        return BXS_OK;
+    };
+
+    int slot = 0;
+    {
+        bxs_status s = enqueue_pass(slot);
+        if (s != BXS_OK) return s;
+    }
+    while (true) {
+        const int nxt = slot ^ 1;
+        bool queued_next = false;
+        if (!slot_final[slot]) {
+            bxs_status s = enqueue_pass(nxt);
+            if (s != BXS_OK) return s;
+            queued_next = true;
+        }
+        BXS_HIP(hipEventSynchronize(dev_done[slot]));
         if (o->profile) {
-            for (long long k = 0; k < kk; ++k) {
+            for (long long k = 0; k < slot_kk[slot]; ++k) {
                 float ms = 0.f;
-                BXS_HIP(hipEventElapsedTime(&ms, pev[2 * k], pev[2 * k + 1]));
+                BXS_HIP(hipEventElapsedTime(&ms, pev[(size_t)slot * 2 * K + 2 * k], pev[(size_t)slot * 2 * K + 2 * k + 1]));
                 sweep_ms += ms;
                 ++sweep_launches;
             }
         }
-        if (*hdone >= count || final_pass) break;
+        if (hdone[slot] >= count || slot_final[slot]) break;
+        if (!queued_next) break;
+        slot = nxt;
     }
     BXS_HIP(hipEventRecord(ev2, stream));
     BXS_HIP(hipMemcpyAsync(hst.data(), D.st, sizeof(State) * count, hipMemcpyDeviceToHost, stream));
@@ -489,6 +541,33 @@ void bxs_default_opts(bxs_opts* o)
 }
 
 const char* bxs_last_error(void) { return g_last_error.c_str(); }
+
+int bxs_num_sweep_variants(void) { return kNumVariants; }
+
+bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi, long* capacity)
+{
+    if (v < 0 || v >= kNumVariants) return fail(BXS_ERR_ARG, "variant %d out of range", v);
+    if (tpc) *tpc = kVariants[v].tpc;
+    if (ng) *ng = kVariants[v].ng;
+    if (rows) *rows = kVariants[v].rows;
+    if (cbi) *cbi = kVariants[v].cbi;
+    if (capacity) *capacity = variant_capacity(v);
+    return BXS_OK;
+}
+
+int bxs_row_class(long m) { return default_variant_for_rows(m); }
+
+bxs_status bxs_set_sweep_variant(int row_class, int v)
+{
+    if (row_class < 0 || row_class >= kNumDefaultVariants) return fail(BXS_ERR_ARG, "row class %d out of range", row_class);
+    if (v < 0) v = row_class;
+    if (v >= kNumVariants) return fail(BXS_ERR_ARG, "variant %d out of range", v);
+    if (variant_capacity(v) < variant_capacity(row_class))
+        return fail(BXS_ERR_ARG, "variant %d holds %ld rows, class %d needs %ld", v, variant_capacity(v), row_class,
+                    variant_capacity(row_class));
+    g_variant_pref[row_class] = v;
+    return BXS_OK;
+}
 
 const char* bxs_version(void) { return "boxscreen 0.1.0 (gfx950)"; }
 

@@ -42,7 +42,7 @@ struct Inst {
     double* fdx;            // [n] bound value minus the iterate before fixing
     double* part;           // [items_cap * m] partial A-products per work item
     double* part2;          // [items_cap * m] second partial (fold pass only)
-    double* iscal;          // [items_cap] per-item scalar (power iteration)
+    double* iscal;          // [items_cap * kItemScalars] per-item scalars (power iteration, screening)
     bxs_pass_record* rec;   // [rec_cap] per-pass records
     int rec_cap;
     int items_cap;          // ceil(n / kCbMin): grid extent reserved for this instance
@@ -71,6 +71,13 @@ struct State {
     double ynorm;           // upper bound of ||y||_2
     double mass_screened;   // sum over screened j of |x_j| * cn_j
 };
+
+// Per-item scalars written by the correlation sweep for the screening pass:
+// sum |x_j| ||a_j||, interior flag of t, largest translation ratio, presence
+// of u_j = +inf columns, gap terms at eps = 0, largest screening score at
+// eps = 0.  The power iteration uses slot 0.
+constexpr int kItemScalars = 8;
+enum ItemScalar : int { kIsMass = 0, kIsTv = 1, kIsEmax = 2, kIsHasInf = 3, kIsGap0 = 4, kIsZmax0 = 5 };
 
 constexpr int kErrNonfinite = 1;
 constexpr int kErrBounds = 2;
@@ -114,20 +121,73 @@ constexpr double kUnit = 1.1102230246251565e-16;
 // therefore at most gamma(kDotDepth) * sum_i |a_ij r_i|.
 constexpr double kDotDepth = 64.0;
 
-// Kernel instantiation buckets, chosen by the number of rows m:
-// TPC threads share one column, NG column groups per workgroup,
-// R rows per thread; capacity TPC * R rows.
-struct BucketSpec { int tpc, ng, rows; };
-constexpr int kNumBuckets = 9;
-constexpr BucketSpec kBuckets[kNumBuckets] = {
-    {64, 4, 1}, {64, 4, 2}, {64, 4, 4}, {64, 4, 8},
-    {256, 1, 4}, {256, 1, 8}, {256, 1, 16},
-    {512, 1, 16}, {1024, 1, 16},
+// Column-sweep kernel variants: TPC threads share one column, NG column
+// groups per workgroup, R rows per thread (capacity TPC * R rows), CBI
+// columns per round, PD rounds of prefetch.  X(id, TPC, NG, R, CBI, PD).
+// Variants 0..8 are the row classes (smallest capacity first); all others
+// are alternatives the tuner may select for a class they can hold.
+#define BXS_SWEEP_VARIANTS(X)   \
+    X(0, 64, 4, 1, 8, 1)        \
+    X(1, 64, 4, 2, 8, 1)        \
+    X(2, 64, 4, 4, 8, 1)        \
+    X(3, 128, 2, 4, 8, 1)       \
+    X(4, 256, 1, 4, 8, 1)       \
+    X(5, 512, 1, 4, 8, 1)       \
+    X(6, 1024, 1, 4, 8, 1)      \
+    X(7, 1024, 1, 8, 4, 1)      \
+    X(8, 1024, 1, 16, 2, 1)     \
+    X(9, 1024, 1, 4, 4, 1)      \
+    X(10, 512, 1, 8, 4, 1)      \
+    X(11, 256, 1, 16, 2, 1)     \
+    X(12, 512, 1, 4, 4, 1)      \
+    X(13, 256, 1, 8, 4, 1)      \
+    X(14, 256, 1, 4, 4, 1)      \
+    X(15, 64, 4, 8, 4, 1)       \
+    X(16, 128, 2, 8, 4, 1)      \
+    X(17, 256, 1, 16, 1, 1)     \
+    X(18, 512, 1, 8, 2, 1)      \
+    X(19, 1024, 1, 4, 2, 1)     \
+    X(20, 256, 1, 8, 2, 1)      \
+    X(21, 512, 1, 4, 2, 1)      \
+    X(22, 512, 1, 8, 2, 2)      \
+    X(23, 1024, 1, 4, 2, 2)     \
+    X(24, 256, 1, 16, 1, 2)     \
+    X(25, 512, 1, 8, 1, 2)      \
+    X(26, 256, 1, 8, 2, 2)      \
+    X(27, 512, 1, 4, 2, 2)      \
+    X(28, 1024, 1, 8, 1, 2)     \
+    X(29, 1024, 1, 16, 1, 2)
+
+struct VariantSpec { int tpc, ng, rows, cbi, pd; };
+constexpr int kNumVariants = 30;
+constexpr int kNumDefaultVariants = 9;
+constexpr VariantSpec kVariants[kNumVariants] = {
+#define BXS_VS(ID, TPC, NG, R, CBI, PD) {TPC, NG, R, CBI, PD},
+    BXS_SWEEP_VARIANTS(BXS_VS)
+#undef BXS_VS
 };
 
-inline int bucket_for_rows(long m) {
-    for (int b = 0; b < kNumBuckets; ++b)
-        if (m <= (long)kBuckets[b].tpc * kBuckets[b].rows) return b;
+inline long variant_capacity(int v) { return (long)kVariants[v].tpc * kVariants[v].rows; }
+
+inline int default_variant_for_rows(long m) {
+    for (int b = 0; b < kNumDefaultVariants; ++b)
+        if (m <= variant_capacity(b)) return b;
+    return -1;
+}
+
+// Resident threads per CU the sweep is sized for (VGPR-limited occupancy).
+constexpr int kThreadsPerCU = 1024;
+
+// Coordinate-descent kernel buckets (one workgroup of TPC threads per
+// instance, R rows per thread).
+struct CdSpec { int tpc, rows; };
+constexpr int kNumCdBuckets = 9;
+constexpr CdSpec kCdBuckets[kNumCdBuckets] = {
+    {64, 1}, {64, 2}, {64, 4}, {64, 8}, {256, 4}, {256, 8}, {256, 16}, {512, 16}, {1024, 16},
+};
+inline int cd_bucket_for_rows(long m) {
+    for (int b = 0; b < kNumCdBuckets; ++b)
+        if (m <= (long)kCdBuckets[b].tpc * kCdBuckets[b].rows) return b;
     return -1;
 }
 
@@ -142,8 +202,8 @@ struct LaunchCtx {
 };
 
 hipError_t launch_init(const LaunchCtx& c, int count, const double* x0_is_given);
-hipError_t launch_colstats(const LaunchCtx& c, int bucket, const Item* items, int n_items);
-hipError_t launch_sweep(const LaunchCtx& c, int bucket, int mode, const Item* items, int n_items);
+hipError_t launch_colstats(const LaunchCtx& c, int variant, const Item* items, int n_items);
+hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items);
 hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems);
 hipError_t launch_pow_init(const LaunchCtx& c, int count);
 hipError_t launch_set_step(const LaunchCtx& c, int count, double step);

@@ -111,22 +111,77 @@ __device__ __forceinline__ void load_pack(const TA* __restrict__ col, int row, i
 }
 
 // ---------------------------------------------------------------------------
+// Wave-level reduce-scatter of CBI per-lane partial sums: after log2(CBI)
+// halving exchanges and the remaining butterfly steps, lane L holds the full
+// 64-lane sum of column col_of_lane(L).  10 shuffles for CBI = 8 instead of 48
+// for eight separate butterflies; the summation order is fixed.
+// ---------------------------------------------------------------------------
+template <int CBI>
+struct Log2C { static constexpr int v = (CBI >= 8) ? 3 : (CBI >= 4) ? 2 : (CBI >= 2) ? 1 : 0; };
+
+// One halving step S of the reduce-scatter, then recurse on the next step;
+// the recursion makes every array index a compile-time constant.
+template <int CBI, int S, bool END = (S >= Log2C<CBI>::v)>
+struct ReduceScatterStep {
+    static __device__ __forceinline__ void run(double (&v)[CBI], int lane) {
+        constexpr int off = 32 >> S;
+        constexpr int half = CBI >> (S + 1);
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double send = upper ? v[i] : v[i + half];
+            const double keep = upper ? v[i + half] : v[i];
+            v[i] = keep + __shfl_xor(send, off, 64);
+        }
+        ReduceScatterStep<CBI, S + 1>::run(v, lane);
+    }
+};
+template <int CBI, int S>
+struct ReduceScatterStep<CBI, S, true> {
+    static __device__ __forceinline__ void run(double (&)[CBI], int) {}
+};
+
+template <int CBI>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[CBI], int lane) {
+    constexpr int LOGC = Log2C<CBI>::v;
+    ReduceScatterStep<CBI, 0>::run(v, lane);
+    double s0 = v[0];
+#pragma unroll
+    for (int off = 32 >> LOGC; off >= 1; off >>= 1) s0 += __shfl_xor(s0, off, 64);
+    return s0;
+}
+
+// An empty register constraint: the compiler must treat the value as new, so
+// a column element is converted to FP64 once for the dot product and again
+// for the update instead of keeping all converted values live in between.
+__device__ __forceinline__ float opaque(float v) { asm volatile("" : "+v"(v)); return v; }
+__device__ __forceinline__ double opaque(double v) { return v; }
+
+template <int CBI>
+__device__ __forceinline__ int col_of_lane(int lane) { return (lane >> (6 - Log2C<CBI>::v)) & (CBI - 1); }
+template <int CBI>
+__device__ __forceinline__ int lane_of_col(int c) { return c << (6 - Log2C<CBI>::v); }
+
+// ---------------------------------------------------------------------------
 // Column sweep.  One workgroup = one work item (instance, block of cb
 // consecutive positions of the preserved-set list, or of the fold list).
-// NG groups of TPC threads each take every NG-th column of the item; thread
-// L of a group owns rows {(k*TPC + L)*V + e}, k < R/V, e < V, and keeps the
-// residual rows and its share of the partial product in registers.
+// NG groups of TPC threads each take every NG-th column of the item, CBI
+// columns per round; thread L of a group owns rows {(k*TPC + L)*V + e},
+// k < R/V, e < V, and keeps those residual rows and its share of the partial
+// product in registers.  Columns of the next round are loaded before the
+// current round's dot products are reduced (software pipeline), so a barrier
+// never drains the memory queue.
 // ---------------------------------------------------------------------------
-template <typename TA, int TPC, int NG, int R, int V, int MODE>
+template <typename TA, int TPC, int NG, int R, int V, int CBI, int PD, int MODE>
 __global__ __launch_bounds__(TPC * NG)
 void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item* __restrict__ items)
 {
     constexpr int RO = R / V;
-    constexpr int CBI = (R >= 16) ? 2 : ((R >= 8) ? 4 : 8);
     constexpr bool DOT = (MODE == kModePG || MODE == kModeCorr || MODE == kModePow);
     constexpr bool ACC = (MODE != kModeCorr);
     constexpr int NW = TPC / 64;
     static_assert(R % V == 0, "rows per thread must be a multiple of the vector width");
+    static_assert(TPC % 64 == 0, "a column group is whole waves");
 
     const Item it = items[blockIdx.x];
     const Inst& I = insts[it.inst];
@@ -141,13 +196,18 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     const int tid = threadIdx.x;
     const int grp = (NG > 1) ? tid / TPC : 0;
     const int L = (NG > 1) ? tid % TPC : tid;
+    const int lane = tid & 63;
+    const int wig = L >> 6;                       // wave index inside the group
+    const int myc = col_of_lane<CBI>(lane);       // column this lane finalises
+    const bool owner = (lane & ((64 >> Log2C<CBI>::v) - 1)) == 0 && wig == 0;
     const int m = I.m;
     const long long lda = I.lda;
     const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
     const int* __restrict__ list = (MODE == kModeFold) ? I.fidx : I.idx;
     const double eta = (MODE == kModePG) ? S.step : 0.0;
+    const double tnorm_c = (MODE == kModeCorr) ? S.tnorm : 0.0;
 
-    double rl[R];
+    double rl[DOT ? R : 1];
     if constexpr (DOT) {
 #pragma unroll
         for (int k = 0; k < RO; ++k)
@@ -157,147 +217,263 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
                 rl[k * V + e] = (row < m) ? I.r[row] : 0.0;
             }
     }
-    double p[R];
+    // CORR: bound on ||r|| (every workgroup sums the same registers in the
+    // same order, so all items of an instance agree bit for bit) and the
+    // per-column screening quantities accumulated by the owner lanes.
+    double rnorm_c = 0.0;
+    double a_mass = 0.0, a_tv = 1.0, a_emax = 0.0, a_inf = 0.0, a_gap = 0.0, a_z = -__builtin_inf();
+    if constexpr (MODE == kModeCorr) {
+        double sq = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) sq = fma(rl[k], rl[k], sq);
+        sq = wave_sum(sq);
+        __shared__ double s_sq[(TPC * NG) / 64];
+        if (lane == 0) s_sq[tid >> 6] = sq;
+        __syncthreads();
+        double tot = 0.0;
+        if (NG == 1) {
+#pragma unroll
+            for (int w = 0; w < (TPC * NG) / 64; ++w) tot += s_sq[w];
+        } else {
+#pragma unroll
+            for (int w = 0; w < TPC / 64; ++w) tot += s_sq[w];   // group 0 holds every row once
+        }
+        rnorm_c = sqrt(tot * (1.0 + gamma_k((double)R + 24.0))) * (1.0 + 2.0 * kUnit);
+    }
+    double p[ACC ? R : 1];
     double p2[(MODE == kModeFold) ? R : 1];
 #pragma unroll
-    for (int k = 0; k < R; ++k) p[k] = 0.0;
-    if constexpr (MODE == kModeFold) {
+    for (int k = 0; k < (ACC ? R : 1); ++k) p[k] = 0.0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) p2[k] = 0.0;
-    }
+    for (int k = 0; k < ((MODE == kModeFold) ? R : 1); ++k) p2[k] = 0.0;
     double gsq = 0.0;
 
-    __shared__ double red[2][(NW > 1) ? NW : 1][CBI];
+    __shared__ double red[2][NG][(NW > 1) ? NW : 1][CBI];
     int buf = 0;
 
-    // software pipeline: columns of the next round (and their per-column
-    // scalars) are loaded while the current round is reduced and applied.
-    // Reading x_j before the round's barrier also orders it before the write
-    // of x_j by lane 0 of the group.
-    TA av[CBI][R];
-    int jc[CBI];
-    bool vc[CBI];
-    double xs[CBI], ls[CBI], us[CBI];
-    auto load_round = [&](int rs, TA (&dst)[CBI][R], int (&jj)[CBI], bool (&vv)[CBI],
-                          double (&xo)[CBI], double (&lo)[CBI], double (&uo)[CBI]) {
+    // Two column buffers used in ping-pong: while one round is reduced and
+    // applied, the next round's columns are already in flight.
+    //  DOT modes keep the scalars of the lane's own column (x, l, u);
+    //  AX / FOLD keep the coefficient of every column of the round.
+    constexpr int NC1 = DOT ? 1 : CBI;
+    constexpr int NC2 = (MODE == kModeFold) ? CBI : 1;
+    TA a0[CBI][R], a1[CBI][R];
+    int j0 = 0, j1 = 0;
+    bool v0 = false, v1 = false;
+    double x0 = 0.0, l0 = 0.0, u0 = 0.0, x1 = 0.0, l1 = 0.0, u1 = 0.0;
+    double c10[NC1], c20[NC2], c11[NC1], c21[NC2];
+
+    // Stage the item's column indices and per-column scalars in LDS once, so
+    // that a round's column loads never wait on a dependent index load.
+    constexpr bool CORR = (MODE == kModeCorr);
+    __shared__ int s_j[kCbMax];
+    __shared__ double s_x[(MODE == kModePG || MODE == kModeAx || MODE == kModeFold || CORR) ? kCbMax : 1];
+    __shared__ double s_l[(MODE == kModePG || MODE == kModeFold || CORR) ? kCbMax : 1];
+    __shared__ double s_u[(MODE == kModePG || CORR) ? kCbMax : 1];
+    __shared__ double s_cn[CORR ? kCbMax : 1];
+    __shared__ double s_w[CORR ? kCbMax : 1];
+    for (int k = tid; k < pos1 - pos0; k += TPC * NG) {
+        const int q = pos0 + k;
+        const int j = list[q];
+        s_j[k] = j;
+        if constexpr (CORR) {
+            s_x[k] = I.x[j];
+            s_l[k] = lo_of(I.l, j);
+            s_u[k] = up_of(I.u, j);
+            s_cn[k] = I.cn[j];
+            s_w[k] = I.w[j];
+        } else if constexpr (MODE == kModePG) {
+            s_x[k] = I.x[j];
+            s_l[k] = lo_of(I.l, j);
+            s_u[k] = up_of(I.u, j);
+        } else if constexpr (MODE == kModeAx) {
+            s_x[k] = I.x[j];
+        } else if constexpr (MODE == kModeFold) {
+            s_x[k] = I.fval[q];
+            s_l[k] = I.fdx[q];
+        }
+    }
+    __syncthreads();
+
+    auto load_round = [&](int rs, TA (&a)[CBI][R], int& jo, bool& vo, double& xo, double& lo, double& uo,
+                          double (&c1)[NC1], double (&c2)[NC2]) {
 #pragma unroll
         for (int c = 0; c < CBI; ++c) {
             const int q = rs + c * NG + grp;
-            vv[c] = q < pos1;
-            jj[c] = vv[c] ? list[q] : 0;
-            xo[c] = 0.0; lo[c] = 0.0; uo[c] = 0.0;
-            if (vv[c]) {
-                if constexpr (MODE == kModePG) {
-                    xo[c] = I.x[jj[c]]; lo[c] = lo_of(I.l, jj[c]); uo[c] = up_of(I.u, jj[c]);
-                } else if constexpr (MODE == kModeAx) {
-                    xo[c] = I.x[jj[c]];
-                } else if constexpr (MODE == kModeFold) {
-                    xo[c] = I.fval[q]; lo[c] = I.fdx[q];
-                }
-            }
-            const TA* col = A + (long long)jj[c] * lda;
+            const bool vv = q < pos1;
+            const int jj = vv ? s_j[q - pos0] : 0;
+            const TA* col = A + (long long)jj * lda;
 #pragma unroll
             for (int k = 0; k < RO; ++k) {
                 TA tmp[V];
-                if (vv[c]) {
+                if (vv) {
                     load_pack<TA, V>(col, (k * TPC + L) * V, m, tmp);
                 } else {
 #pragma unroll
                     for (int e = 0; e < V; ++e) tmp[e] = TA(0);
                 }
 #pragma unroll
-                for (int e = 0; e < V; ++e) dst[c][k * V + e] = tmp[e];
+                for (int e = 0; e < V; ++e) a[c][k * V + e] = tmp[e];
+            }
+            if constexpr (MODE == kModeAx) {
+                c1[c] = vv ? s_x[q - pos0] : 0.0;
+            } else if constexpr (MODE == kModeFold) {
+                c1[c] = vv ? s_x[q - pos0] : 0.0;
+                c2[c] = vv ? s_l[q - pos0] : 0.0;
+            }
+        }
+        if constexpr (DOT) {
+            // jo: slot of the lane's own column in the staged arrays
+            const int q = rs + myc * NG + grp;
+            vo = q < pos1;
+            jo = vo ? q - pos0 : 0;
+            if constexpr (MODE == kModePG) {
+                xo = vo ? s_x[jo] : 0.0;
+                lo = vo ? s_l[jo] : 0.0;
+                uo = vo ? s_u[jo] : 0.0;
             }
         }
     };
 
-    load_round(pos0, av, jc, vc, xs, ls, us);
-    for (int rs = pos0; rs < pos1; rs += NG * CBI) {
-        TA an[CBI][R];
-        int jn[CBI];
-        bool vn[CBI];
-        double xn_[CBI], ln_[CBI], un_[CBI];
-        const int rs_next = rs + NG * CBI;
-        if (rs_next < pos1) {
-            load_round(rs_next, an, jn, vn, xn_, ln_, un_);
-        }
-
-        double coef[CBI], coef2[CBI];
+    auto compute_round = [&](const TA (&a)[CBI][R], int jo, bool vo, double xo, double lo, double uo,
+                             const double (&c1)[NC1], const double (&c2)[NC2]) {
         if constexpr (DOT) {
             double d[CBI];
 #pragma unroll
             for (int c = 0; c < CBI; ++c) {
                 double s = 0.0;
 #pragma unroll
-                for (int k = 0; k < R; ++k) s = fma((double)av[c][k], rl[k], s);
+                for (int k = 0; k < R; ++k) s = fma((double)a[c][k], rl[k], s);
                 d[c] = s;
             }
-#pragma unroll
-            for (int c = 0; c < CBI; ++c) d[c] = wave_sum(d[c]);
+            double tot = wave_reduce_scatter<CBI>(d, lane);
             if constexpr (NW > 1) {
-                const int wv = tid >> 6;
-                if ((tid & 63) == 0) {
-#pragma unroll
-                    for (int c = 0; c < CBI; ++c) red[buf][wv][c] = d[c];
-                }
+                if ((lane & ((64 >> Log2C<CBI>::v) - 1)) == 0) red[buf][grp][wig][myc] = tot;
                 __syncthreads();
+                double s = 0.0;
 #pragma unroll
-                for (int c = 0; c < CBI; ++c) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) s += red[buf][w][c];
-                    d[c] = s;
-                }
+                for (int w = 0; w < NW; ++w) s += red[buf][grp][w][myc];
+                tot = s;
                 buf ^= 1;
             }
-#pragma unroll
-            for (int c = 0; c < CBI; ++c) {
-                coef[c] = 0.0;
-                if (!vc[c]) continue;
-                const int j = jc[c];
+            double cown = 0.0;
+            if (vo) {
                 if constexpr (MODE == kModePG) {
-                    const double xn = fmin(fmax(xs[c] + eta * d[c], ls[c]), us[c]);
-                    coef[c] = xn;
-                    if (L == 0) I.x[j] = xn;
+                    const double xn = fmin(fmax(xo + eta * tot, lo), uo);
+                    cown = xn;
+                    if (owner) I.x[s_j[jo]] = xn;
                 } else if constexpr (MODE == kModeCorr) {
-                    if (L == 0) I.g[j] = d[c];
+                    if (owner) {
+                        I.g[s_j[jo]] = tot;
+                        // screening quantities of this column at eps = 0
+                        const int k = jo;
+                        const double cnj = s_cn[k], wj = s_w[k], xj = s_x[k], lj = s_l[k], uj = s_u[k];
+                        const double gm = gamma_k(kDotDepth);
+                        const double gw = gamma_k((double)(m / 64) + 8.0);
+                        a_mass = fma(fabs(xj), cnj, a_mass);
+                        const double ej = cnj * gm * rnorm_c + 4.0 * kUnit * fabs(tot);
+                        double term = (xj - lj) * fmax(ej - tot, 0.0);
+                        double zs = -(tot + ej);
+                        if (isinf(uj)) {
+                            a_inf = 1.0;
+                            const double ewj = gw * cnj * tnorm_c;
+                            if (!(wj + ewj < 0.0)) a_tv = 0.0;
+                            else a_emax = fmax(a_emax, fmax(tot + cnj * gm * rnorm_c, 0.0) / (-wj - ewj));
+                        } else {
+                            term += (uj - xj) * fmax(tot + ej, 0.0);
+                            zs = fmax(zs, tot - ej);
+                        }
+                        a_gap += term;
+                        if (cnj > 0.0) a_z = fmax(a_z, zs / cnj);
+                    }
                 } else {  // power iteration
-                    coef[c] = d[c];
-                    gsq += d[c] * d[c];
+                    cown = tot;
+                    if (owner) gsq += tot * tot;
+                }
+            }
+            if constexpr (ACC) {
+#pragma unroll
+                for (int c = 0; c < CBI; ++c) {
+                    const double cf = __shfl(cown, lane_of_col<CBI>(c), 64);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) p[k] = fma((double)opaque(a[c][k]), cf, p[k]);
                 }
             }
         } else {
 #pragma unroll
-            for (int c = 0; c < CBI; ++c) {
-                coef[c] = vc[c] ? xs[c] : 0.0;                          // x_j, or b_j for the fold
-                coef2[c] = (MODE == kModeFold && vc[c]) ? ls[c] : 0.0;  // b_j - x_j (fold)
-            }
-        }
-        if constexpr (ACC) {
-#pragma unroll
             for (int c = 0; c < CBI; ++c)
 #pragma unroll
-                for (int k = 0; k < R; ++k) p[k] = fma((double)av[c][k], coef[c], p[k]);
+                for (int k = 0; k < R; ++k) p[k] = fma((double)a[c][k], c1[c], p[k]);
             if constexpr (MODE == kModeFold) {
 #pragma unroll
                 for (int c = 0; c < CBI; ++c)
 #pragma unroll
-                    for (int k = 0; k < R; ++k) p2[k] = fma((double)av[c][k], coef2[c], p2[k]);
+                    for (int k = 0; k < R; ++k) p2[k] = fma((double)a[c][k], c2[c], p2[k]);
             }
         }
-        if (rs_next < pos1) {
-#pragma unroll
-            for (int c = 0; c < CBI; ++c) {
-                jc[c] = jn[c];
-                vc[c] = vn[c];
-                xs[c] = xn_[c]; ls[c] = ln_[c]; us[c] = un_[c];
-#pragma unroll
-                for (int k = 0; k < R; ++k) av[c][k] = an[c][k];
-            }
+    };
+
+    constexpr int STEP = NG * CBI;
+    if constexpr (PD == 1) {
+        // prefetch distance one round: two buffers
+        load_round(pos0, a0, j0, v0, x0, l0, u0, c10, c20);
+        for (int rs = pos0; rs < pos1; rs += 2 * STEP) {
+            if (rs + STEP < pos1) load_round(rs + STEP, a1, j1, v1, x1, l1, u1, c11, c21);
+            compute_round(a0, j0, v0, x0, l0, u0, c10, c20);
+            if (rs + STEP >= pos1) break;
+            if (rs + 2 * STEP < pos1) load_round(rs + 2 * STEP, a0, j0, v0, x0, l0, u0, c10, c20);
+            compute_round(a1, j1, v1, x1, l1, u1, c11, c21);
+        }
+    } else {
+        // prefetch distance two rounds: three buffers in rotation
+        TA a2[CBI][R];
+        int j2 = 0;
+        bool v2 = false;
+        double x2 = 0.0, l2 = 0.0, u2 = 0.0;
+        double c12[NC1], c22[NC2];
+        load_round(pos0, a0, j0, v0, x0, l0, u0, c10, c20);
+        if (pos0 + STEP < pos1) load_round(pos0 + STEP, a1, j1, v1, x1, l1, u1, c11, c21);
+        for (int rs = pos0; rs < pos1; rs += 3 * STEP) {
+            if (rs + 2 * STEP < pos1) load_round(rs + 2 * STEP, a2, j2, v2, x2, l2, u2, c12, c22);
+            compute_round(a0, j0, v0, x0, l0, u0, c10, c20);
+            if (rs + STEP >= pos1) break;
+            if (rs + 3 * STEP < pos1) load_round(rs + 3 * STEP, a0, j0, v0, x0, l0, u0, c10, c20);
+            compute_round(a1, j1, v1, x1, l1, u1, c11, c21);
+            if (rs + 2 * STEP >= pos1) break;
+            if (rs + 4 * STEP < pos1) load_round(rs + 4 * STEP, a1, j1, v1, x1, l1, u1, c11, c21);
+            compute_round(a2, j2, v2, x2, l2, u2, c12, c22);
         }
     }
 
+    if constexpr (MODE == kModeCorr) {
+        // combine the owner lanes' screening quantities over the workgroup
+        constexpr int NWB = (TPC * NG) / 64;
+        __shared__ double s_red[6][NWB];
+        double vals[6] = {a_mass, a_tv, a_emax, a_inf, a_gap, a_z};
+        vals[0] = wave_sum(vals[0]);
+        vals[1] = wave_min(vals[1]);
+        vals[2] = wave_max(vals[2]);
+        vals[3] = wave_max(vals[3]);
+        vals[4] = wave_sum(vals[4]);
+        vals[5] = wave_max(vals[5]);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) s_red[k][tid >> 6] = vals[k];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double r0 = 0.0, r1 = 1.0, r2 = 0.0, r3 = 0.0, r4 = 0.0, r5 = -__builtin_inf();
+            for (int w = 0; w < NWB; ++w) {
+                r0 += s_red[0][w]; r1 = fmin(r1, s_red[1][w]); r2 = fmax(r2, s_red[2][w]);
+                r3 = fmax(r3, s_red[3][w]); r4 += s_red[4][w]; r5 = fmax(r5, s_red[5][w]);
+            }
+            double* o = I.iscal + (size_t)it.t * kItemScalars;
+            o[kIsMass] = r0; o[kIsTv] = r1; o[kIsEmax] = r2; o[kIsHasInf] = r3; o[kIsGap0] = r4; o[kIsZmax0] = r5;
+        }
+    }
     if constexpr (!ACC) return;
+
+    if constexpr (MODE == kModePow) gsq = wave_sum(gsq);   // owners live in wave 0 of each group
 
     // combine the NG groups' partial products (fixed order) and store
     if constexpr (NG > 1) {
@@ -315,9 +491,9 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 #pragma unroll
                 for (int k = 0; k < R; ++k) p[k] += comb[((g2 - 1) * R + k) * TPC + L];
             if (MODE == kModePow && L == 0) {
-                double s = 0.0;
-                for (int g2 = 0; g2 < NG; ++g2) s += gs[g2];
-                gsq = s;
+                double s2 = 0.0;
+                for (int g2 = 0; g2 < NG; ++g2) s2 += gs[g2];
+                gsq = s2;
             }
         }
         if constexpr (MODE == kModeFold) {
@@ -355,17 +531,19 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
             }
     }
     if constexpr (MODE == kModePow) {
-        if (L == 0) I.iscal[it.t] = gsq;
+        if (L == 0) I.iscal[(size_t)it.t * kItemScalars] = gsq;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Partial reduction: 64 rows x 4 item-groups per workgroup, fixed order.
+// Partial reduction: 64 rows x 16 item-groups per workgroup, fixed order.
+// Each thread issues up to 8 independent loads before summing them in order.
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(256)
+__global__ __launch_bounds__(1024)
 void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems)
 {
+    constexpr int TG = 16, U = 8;
     const RItem ri = ritems[blockIdx.x];
     const Inst& I = insts[ri.inst];
     const State& S = st[ri.inst];
@@ -378,21 +556,35 @@ void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RIte
     const int m = I.m;
     double s = 0.0, s2 = 0.0;
     if (row < m) {
-        for (int t = tg; t < T; t += 4) {
-            s += I.part[(size_t)t * m + row];
-            if (MODE == kRedFold) s2 += I.part2[(size_t)t * m + row];
+        for (int t0 = tg; t0 < T; t0 += TG * U) {
+            double v[U], v2[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * TG;
+                v[u] = (t < T) ? I.part[(size_t)t * m + row] : 0.0;
+                if (MODE == kRedFold) v2[u] = (t < T) ? I.part2[(size_t)t * m + row] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                s += v[u];
+                if (MODE == kRedFold) s2 += v2[u];
+            }
         }
     }
-    __shared__ double sh[4][64], sh2[4][64];
+    __shared__ double sh[TG][64], sh2[TG][64];
     sh[tg][rowl] = s;
-    sh2[tg][rowl] = s2;
+    if (MODE == kRedFold) sh2[tg][rowl] = s2;
     __syncthreads();
     if (tg == 0 && row < m) {
-        const double tot = ((sh[0][rowl] + sh[1][rowl]) + sh[2][rowl]) + sh[3][rowl];
+        double tot = 0.0, tot2 = 0.0;
+#pragma unroll
+        for (int g = 0; g < TG; ++g) {
+            tot += sh[g][rowl];
+            if (MODE == kRedFold) tot2 += sh2[g][rowl];
+        }
         if constexpr (MODE == kRedResidual) {
             I.r[row] = I.yp[row] - tot;
         } else if constexpr (MODE == kRedFold) {
-            const double tot2 = ((sh2[0][rowl] + sh2[1][rowl]) + sh2[2][rowl]) + sh2[3][rowl];
             I.yp[row] -= tot;
             I.r[row] -= tot2;
         } else {
@@ -537,7 +729,7 @@ void k_pow_normalize(const Inst* __restrict__ insts, State* __restrict__ st, int
     s = block_sum<256>(s, sh);
     const int T = (S.n_active + S.cb - 1) / S.cb;
     double lam = 0.0;
-    for (int t = threadIdx.x; t < T; t += 256) lam += I.iscal[t];
+    for (int t = threadIdx.x; t < T; t += 256) lam += I.iscal[(size_t)t * kItemScalars];
     lam = block_sum<256>(lam, sh);
     const double inv = (s > 0.0) ? 1.0 / sqrt(s) : 0.0;
     for (int i = threadIdx.x; i < m; i += 256) I.r[i] *= inv;
@@ -569,17 +761,21 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
               double eps_gap, int screening, int final_pass, long long iters, int kk)
 {
     constexpr int NT = 1024;
+    constexpr int E = 4;                       // consecutive preserved positions per thread per chunk
+    constexpr int CH = NT * E;
     __shared__ double sh[NT / 64];
-    __shared__ int wk[NT / 64], ws[NT / 64];
+    __shared__ int wsum[NT / 64];
     const Inst& I = insts[blockIdx.x];
     State& S = st[blockIdx.x];
     if (S.done) return;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int m = I.m, n = I.n;
     const int nA = S.n_active;
     const int passes = S.passes;
     const double tnorm = S.tnorm;
     const double u1 = kUnit;
+    const bool nnls_like = (I.u == nullptr);   // every u_j = +inf
 
     double a = 0.0;
     for (int i = tid; i < m; i += NT) a = fma(I.r[i], I.r[i], a);
@@ -590,63 +786,106 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
     const double gm = gamma_k(kDotDepth);
     const double gw = gamma_k((double)(m / 64) + 8.0);
 
-    // pass 1: interior check of t, translation coefficient, absolute mass
-    double tv = 1.0, emax = 0.0, mass = 0.0, hasinf = 0.0;
-    for (int p = tid; p < nA; p += NT) {
-        const int j = I.idx[p];
-        const double cnj = I.cn[j];
-        mass = fma(fabs(I.x[j]), cnj, mass);
-        if (isinf(up_of(I.u, j))) {
-            hasinf = 1.0;
-            const double ewj = gw * cnj * tnorm;
-            const double egj = gm * cnj * rnorm;
-            const double wj = I.w[j];
-            if (!(wj + ewj < 0.0)) {
-                tv = 0.0;
-            } else {
-                const double num = fmax(I.g[j] + egj, 0.0);
-                const double den = -wj - ewj;
-                emax = fmax(emax, num / den);
-            }
+    // Per-chunk gather of the preserved columns' data: each thread takes E
+    // consecutive positions and issues all of its loads before using them.
+    struct Col { int j; double g, w, cn, x, l, u; };
+    auto gather = [&](int base, Col (&c)[E], bool (&valid)[E]) {
+        int jj[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = base + tid * E + e;
+            valid[e] = p < nA;
+            jj[e] = valid[e] ? I.idx[p] : 0;
         }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = jj[e];
+            c[e].j = j;
+            c[e].g = valid[e] ? I.g[j] : 0.0;
+            c[e].w = valid[e] ? I.w[j] : 0.0;
+            c[e].cn = valid[e] ? I.cn[j] : 0.0;
+            c[e].x = valid[e] ? I.x[j] : 0.0;
+            c[e].l = valid[e] ? lo_of(I.l, j) : 0.0;
+            c[e].u = valid[e] ? up_of(I.u, j) : 0.0;
+        }
+    };
+
+    // Combine the per-item quantities written by the correlation sweep: mass,
+    // interior flag of t, largest translation ratio, presence of u = +inf
+    // columns, gap terms and largest screening score at eps = 0.
+    const int T = (nA + S.cb - 1) / S.cb;
+    double tv = 1.0, emax = 0.0, mass = 0.0, hasinf = 0.0, gap0 = 0.0, z0 = -__builtin_inf();
+    for (int t = tid; t < T; t += NT) {
+        const double* o = I.iscal + (size_t)t * kItemScalars;
+        mass += o[kIsMass];
+        tv = fmin(tv, o[kIsTv]);
+        emax = fmax(emax, o[kIsEmax]);
+        hasinf = fmax(hasinf, o[kIsHasInf]);
+        gap0 += o[kIsGap0];
+        z0 = fmax(z0, o[kIsZmax0]);
     }
     tv = block_min<NT>(tv, sh);
     emax = block_max<NT>(emax, sh);
     mass = block_sum<NT>(mass, sh);
     hasinf = block_max<NT>(hasinf, sh);
+    gap0 = block_sum<NT>(gap0, sh);
+    z0 = block_max<NT>(z0, sh);
     const bool has_inf = hasinf > 0.5;
     const bool fallback = has_inf && !(tv > 0.5);
     const double eps = (has_inf && !fallback) ? emax * (1.0 + 4.0 * u1) : 0.0;
     const double massall = (mass + S.mass_screened) * (1.0 + gamma_k((double)n + 64.0));
     const double delta_r = gamma_k(2.0 * n + 4.0 * passes + 64.0) * (S.ynorm + 2.0 * massall);
 
-    // pass 2: gap
-    double G;
-    if (!fallback) {
-        double acc = 0.0;
-        for (int p = tid; p < nA; p += NT) {
-            const int j = I.idx[p];
-            const double cnj = I.cn[j], gj = I.g[j], wj = I.w[j];
-            const double cj = fma(eps, wj, gj);
-            const double ej = cnj * (gm * rnorm + gw * eps * tnorm) + 4.0 * u1 * (fabs(gj) + eps * fabs(wj));
-            const double xj = I.x[j], lj = lo_of(I.l, j), uj = up_of(I.u, j);
-            double term = (xj - lj) * fmax(ej - cj, 0.0);
-            if (!isinf(uj)) term += (uj - xj) * fmax(cj + ej, 0.0);
-            acc += term;
-        }
-        const double gsum = block_sum<NT>(acc, sh);
-        const double tt = delta_r + eps * tnorm;
-        G = (gsum * (1.0 + 3.0 * u1) + 0.5 * tt * tt * (1.0 + 4.0 * u1)) * (1.0 + gamma_k((double)n + 64.0));
-    } else {
+    // a_j^T theta for theta = r + eps t, and its rounding bound
+    auto corr = [&](const Col& c, double& cj, double& ej) {
+        cj = fma(eps, c.w, c.g);
+        ej = c.cn * (gm * rnorm + gw * eps * tnorm) + 4.0 * u1 * (fabs(c.g) + eps * fabs(c.w));
+    };
+
+    // gap: at eps = 0 the sweep already summed the per-column terms; with a
+    // translation the terms change and are summed here in one more pass
+    double G, zmax = z0;
+    if (fallback) {
         const double tt = rnorm + delta_r;
         G = 0.5 * tt * tt * (1.0 + 4.0 * u1);
+    } else {
+        double gsum = gap0;
+        if (eps > 0.0) {
+            double acc = 0.0, zz = -__builtin_inf();
+            for (int base = 0; base < nA; base += CH) {
+                Col c[E];
+                bool valid[E];
+                gather(base, c, valid);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (!valid[e]) continue;
+                    double cj, ej;
+                    corr(c[e], cj, ej);
+                    double term = (c[e].x - c[e].l) * fmax(ej - cj, 0.0);
+                    double zs = -(cj + ej);
+                    if (!isinf(c[e].u)) {
+                        term += (c[e].u - c[e].x) * fmax(cj + ej, 0.0);
+                        zs = fmax(zs, cj - ej);
+                    }
+                    acc += term;
+                    if (c[e].cn > 0.0) zz = fmax(zz, zs / c[e].cn);
+                }
+            }
+            gsum = block_sum<NT>(acc, sh);
+            zmax = block_max<NT>(zz, sh);
+        }
+        const double tt = delta_r + eps * tnorm;
+        G = (gsum * (1.0 + 3.0 * u1) + 0.5 * tt * tt * (1.0 + 4.0 * u1)) * (1.0 + gamma_k((double)n + 64.0));
     }
     const double rad = sqrt(2.0 * G) * (1.0 + 2.0 * u1);
     const double primal = 0.5 * rsq;
     const bool stop = G < eps_gap;
     if (tid == 0) S.col_iters += (long long)nA * kk;
 
-    if (stop || final_pass || !screening || fallback) {
+    // the largest screening score bounds every column's test: if it stays
+    // below the radius nothing can be screened and the scan is skipped
+    const bool none = !(zmax >= rad);
+    if (stop || final_pass || !screening || fallback || none) {
         if (tid == 0) {
             if (passes < I.rec_cap) {
                 bxs_pass_record& rc = I.rec[passes];
@@ -667,58 +906,67 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
         return;
     }
 
-    // pass 3: safe rule, fix, fold list, in-place compaction of idx
-    const int lane = tid & 63, wave = tid >> 6;
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // pass 3: safe rule, fix, fold list, in-place compaction of idx.
+    // One packed block scan per chunk: low 16 bits count kept columns, high
+    // 16 bits screened ones (at most CH = 4096 of each per chunk).
     int out = 0, fout = 0;
     double nlo = 0.0, nhi = 0.0, smass = 0.0;
-    for (int base = 0; base < nA; base += NT) {
-        const int p = base + tid;
-        bool lower = false, upper = false, keep = false;
-        int j = 0;
-        double xj = 0.0, lj = 0.0, uj = 0.0, cnj = 0.0;
-        if (p < nA) {
-            j = I.idx[p];
-            cnj = I.cn[j];
-            const double gj = I.g[j], wj = I.w[j];
-            const double cj = fma(eps, wj, gj);
-            const double ej = cnj * (gm * rnorm + gw * eps * tnorm) + 4.0 * u1 * (fabs(gj) + eps * fabs(wj));
-            const double thr = rad * cnj * (1.0 + 2.0 * u1);
-            xj = I.x[j]; lj = lo_of(I.l, j); uj = up_of(I.u, j);
-            lower = (cj + ej) < -thr;
-            upper = !lower && !isinf(uj) && (cj - ej) > thr;
-            keep = !(lower || upper);
+    for (int base = 0; base < nA; base += CH) {
+        Col c[E];
+        bool valid[E];
+        gather(base, c, valid);
+        int flag[E];                           // 0 keep, 1 lower, 2 upper, 3 invalid
+        int packed = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            flag[e] = 3;
+            if (!valid[e]) continue;
+            double cj, ej;
+            corr(c[e], cj, ej);
+            const double thr = rad * c[e].cn * (1.0 + 2.0 * u1);
+            const bool lower = (cj + ej) < -thr;
+            const bool upper = !lower && !isinf(c[e].u) && (cj - ej) > thr;
+            flag[e] = lower ? 1 : (upper ? 2 : 0);
+            packed += (flag[e] == 0) ? 1 : (1 << 16);
         }
-        const bool scr = lower || upper;
-        const unsigned long long mk = __ballot(keep);
-        const unsigned long long ms = __ballot(scr);
-        if (lane == 0) {
-            wk[wave] = __popcll(mk);
-            ws[wave] = __popcll(ms);
+        // inclusive wave scan, then wave offsets through LDS
+        int x = packed;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(x, o, 64);
+            if (lane >= o) x += t;
         }
-        __syncthreads();
-        int kb = 0, sb = 0, kt = 0, stot = 0;
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();                       // also orders every idx read of this chunk before the writes
+        int woff = 0, tot = 0;
 #pragma unroll
         for (int w = 0; w < NT / 64; ++w) {
-            if (w < wave) { kb += wk[w]; sb += ws[w]; }
-            kt += wk[w];
-            stot += ws[w];
+            if (w < wave) woff += wsum[w];
+            tot += wsum[w];
         }
-        if (keep) I.idx[out + kb + __popcll(mk & lt)] = j;
-        if (scr) {
-            const int k = fout + sb + __popcll(ms & lt);
-            const double b = lower ? lj : uj;
-            I.fidx[k] = j;
-            I.fval[k] = b;
-            I.fdx[k] = b - xj;
-            I.x[j] = b;
-            I.sat[j] = lower ? (signed char)-1 : (signed char)1;
-            smass = fma(fabs(b), cnj, smass);
-            if (lower) nlo += 1.0; else nhi += 1.0;
+        const int excl = x - packed + woff;
+        int kpos = out + (excl & 0xffff);
+        int spos = fout + (excl >> 16);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (flag[e] == 0) {
+                I.idx[kpos++] = c[e].j;
+            } else if (flag[e] == 1 || flag[e] == 2) {
+                const bool lower = flag[e] == 1;
+                const double b = lower ? c[e].l : c[e].u;
+                I.fidx[spos] = c[e].j;
+                I.fval[spos] = b;
+                I.fdx[spos] = b - c[e].x;
+                ++spos;
+                I.x[c[e].j] = b;
+                I.sat[c[e].j] = lower ? (signed char)-1 : (signed char)1;
+                smass = fma(fabs(b), c[e].cn, smass);
+                if (lower) nlo += 1.0; else nhi += 1.0;
+            }
         }
-        out += kt;
-        fout += stot;
-        __syncthreads();
+        out += tot & 0xffff;
+        fout += tot >> 16;
+        __syncthreads();                       // wsum reuse
     }
     nlo = block_sum<NT>(nlo, sh);
     nhi = block_sum<NT>(nhi, sh);
@@ -839,45 +1087,40 @@ void k_cd(const Inst* __restrict__ insts, State* __restrict__ st, const int* __r
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-template <typename TA, int V>
-static hipError_t sweep_dispatch_v(const LaunchCtx& c, int bucket, int mode, const Item* items, int n_items)
+template <typename TA, int V, int TPC, int NG, int R, int CBI, int PD>
+static hipError_t sweep_launch_t(const LaunchCtx& c, int mode, const Item* items, int n_items)
 {
-#define BXS_SWEEP(TPC, NG, R)                                                                     \
-    {                                                                                             \
-        constexpr int VV = (V < R) ? V : R;                                                       \
-        dim3 grid(n_items), block(TPC * NG);                                                      \
-        switch (mode) {                                                                           \
-        case kModePG: k_sweep<TA, TPC, NG, R, VV, kModePG><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;     \
-        case kModeCorr: k_sweep<TA, TPC, NG, R, VV, kModeCorr><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break; \
-        case kModeAx: k_sweep<TA, TPC, NG, R, VV, kModeAx><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;     \
-        case kModeFold: k_sweep<TA, TPC, NG, R, VV, kModeFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break; \
-        default: k_sweep<TA, TPC, NG, R, VV, kModePow><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;         \
-        }                                                                                         \
-        return hipGetLastError();                                                                 \
+    constexpr int VV = (V < R) ? V : R;
+    dim3 grid(n_items), block(TPC * NG);
+    switch (mode) {
+    case kModePG: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModePG><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
+    case kModeCorr: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModeCorr><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
+    case kModeAx: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModeAx><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
+    case kModeFold: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModeFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
+    default: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModePow><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
     }
-    switch (bucket) {
-    case 0: BXS_SWEEP(64, 4, 1)
-    case 1: BXS_SWEEP(64, 4, 2)
-    case 2: BXS_SWEEP(64, 4, 4)
-    case 3: BXS_SWEEP(64, 4, 8)
-    case 4: BXS_SWEEP(256, 1, 4)
-    case 5: BXS_SWEEP(256, 1, 8)
-    case 6: BXS_SWEEP(256, 1, 16)
-    case 7: BXS_SWEEP(512, 1, 16)
-    case 8: BXS_SWEEP(1024, 1, 16)
-    default: return hipErrorInvalidValue;
-    }
-#undef BXS_SWEEP
+    return hipGetLastError();
 }
 
-hipError_t launch_sweep(const LaunchCtx& c, int bucket, int mode, const Item* items, int n_items)
+template <typename TA, int V>
+static hipError_t sweep_dispatch_v(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items)
+{
+    switch (variant) {
+#define BXS_V(ID, TPC, NG, R, CBI, PD) case ID: return sweep_launch_t<TA, V, TPC, NG, R, CBI, PD>(c, mode, items, n_items);
+    BXS_SWEEP_VARIANTS(BXS_V)
+#undef BXS_V
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items)
 {
     if (n_items <= 0) return hipSuccess;
     if (c.dtype == BXS_F32)
-        return c.vec ? sweep_dispatch_v<float, 4>(c, bucket, mode, items, n_items)
-                     : sweep_dispatch_v<float, 1>(c, bucket, mode, items, n_items);
-    return c.vec ? sweep_dispatch_v<double, 2>(c, bucket, mode, items, n_items)
-                 : sweep_dispatch_v<double, 1>(c, bucket, mode, items, n_items);
+        return c.vec ? sweep_dispatch_v<float, 4>(c, variant, mode, items, n_items)
+                     : sweep_dispatch_v<float, 1>(c, variant, mode, items, n_items);
+    return c.vec ? sweep_dispatch_v<double, 2>(c, variant, mode, items, n_items)
+                 : sweep_dispatch_v<double, 1>(c, variant, mode, items, n_items);
 }
 
 template <typename TA, int V>
@@ -917,7 +1160,7 @@ hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n
 hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems)
 {
     if (n_ritems <= 0) return hipSuccess;
-    dim3 grid(n_ritems), block(256);
+    dim3 grid(n_ritems), block(1024);
     switch (mode) {
     case kRedResidual: k_reduce<kRedResidual><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems); break;
     case kRedFold: k_reduce<kRedFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems); break;

@@ -55,7 +55,8 @@ class Problem(C.Structure):
 
 
 EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls",
-            "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version"]
+            "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
+            "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant"]
 
 _lib = None
 
@@ -88,6 +89,14 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     lib.bxs_last_error.restype = C.c_char_p
     lib.bxs_version.argtypes = []
     lib.bxs_version.restype = C.c_char_p
+    lib.bxs_num_sweep_variants.argtypes = []
+    lib.bxs_num_sweep_variants.restype = C.c_int
+    lib.bxs_sweep_variant_info.argtypes = [C.c_int] + [C.POINTER(C.c_int)] * 4 + [C.POINTER(C.c_long)]
+    lib.bxs_sweep_variant_info.restype = C.c_int
+    lib.bxs_row_class.argtypes = [C.c_long]
+    lib.bxs_row_class.restype = C.c_int
+    lib.bxs_set_sweep_variant.argtypes = [C.c_int, C.c_int]
+    lib.bxs_set_sweep_variant.restype = C.c_int
     _lib = lib
     return lib
 
@@ -263,3 +272,28 @@ def solve_bvls_varbatch(problems: list[dict], **kw):
 
 def version() -> str:
     return load().bxs_version().decode()
+
+
+def sweep_variants() -> list[dict]:
+    """The compiled column-sweep shapes (id, threads per column, groups per
+    workgroup, rows per thread, columns per round, row capacity)."""
+    lib = load()
+    out = []
+    for v in range(lib.bxs_num_sweep_variants()):
+        a, b, c, d = (C.c_int() for _ in range(4))
+        cap = C.c_long()
+        lib.bxs_sweep_variant_info(v, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(cap))
+        out.append({"id": v, "tpc": a.value, "ng": b.value, "rows": c.value, "cbi": d.value,
+                    "capacity": cap.value})
+    return out
+
+
+def row_class(m: int) -> int:
+    return load().bxs_row_class(int(m))
+
+
+def set_sweep_variant(row_class_: int, variant: int) -> None:
+    lib = load()
+    st = lib.bxs_set_sweep_variant(int(row_class_), int(variant))
+    if st != BXS_OK:
+        _raise(lib, st)
