@@ -60,6 +60,9 @@ typedef enum {
 
 typedef enum { BXS_PG = 0, BXS_CD = 1 } bxs_solver;   /* projected gradient / cyclic coordinate descent */
 typedef enum { BXS_F64 = 0, BXS_F32 = 1 } bxs_dtype;  /* storage type of A                               */
+/* Arithmetic of the primal iterations of the batched shared-matrix solver
+ * (the certification pass is FP64 in both cases). */
+typedef enum { BXS_ITER_F64 = 0, BXS_ITER_BF16X3 = 1 } bxs_iter_precision;
 
 /* Largest number of rows a single instance may have. */
 #define BXS_MAX_ROWS 16384
@@ -96,6 +99,7 @@ typedef struct {
     long    history_cap;     /* capacity of history (records beyond it are dropped)            */
     int     profile;         /* 1: time every primal-iteration sweep with HIP events recorded on
                                 opts->stream and report it in info.sweep_ms / sweep_launches  */
+    int     iter_precision;  /* bxs_iter_precision; only the batched shared-matrix solver      */
 } bxs_opts;
 
 typedef struct {
@@ -175,6 +179,25 @@ int        bxs_num_sweep_variants(void);
 bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi, long* capacity);
 int        bxs_row_class(long m);            /* -1 if m > BXS_MAX_ROWS */
 bxs_status bxs_set_sweep_variant(int row_class, int v);
+
+/* Batched non-negative LS with one shared matrix (Alg. 2 for every column
+ * y_b of Y):  min 1/2 ||A x_b - y_b||^2  s.t. x_b >= 0,  b = 0..B-1.
+ * Projected gradient for all right-hand sides at once, the matrix products
+ * as GEMMs: FP64 (opts->iter_precision = BXS_ITER_F64) or hand-written
+ * gfx950 MFMA GEMMs on bf16 hi/lo splits of the FP32 operands with FP32
+ * accumulation and fused residual / projected-step epilogues
+ * (BXS_ITER_BF16X3).  Every screen_every iterations an FP64 pass computes
+ * the residuals and correlations from the stored matrix, the translated
+ * dual point (along opts->t, default -1), the certified gap per right-hand
+ * side, the safe radius and the saturation test; right-hand sides whose
+ * gap is below eps_gap stop and leave the active set.
+ *   A [lda*n] (a_dtype)   Y [ldy*B] FP64   X [ldx*B] FP64 in: x0, out: x
+ *   sat [ldsat*B] out (-1 screened at 0, else 0)   infos host [B] or NULL
+ * Requires m, n, B >= 1 and lda >= m, ldy >= m, ldx >= n, ldsat >= n. */
+bxs_status solve_nnls_batched_shared(long m, long n, long B, int a_dtype, const void* A, long lda,
+                                     const double* Y, long ldy, double* X, long ldx,
+                                     signed char* sat, long ldsat, const bxs_opts* opts, bxs_info* infos);
+bxs_status bxs_workspace_size_batched(long m, long n, long B, const bxs_opts* opts, size_t* bytes);
 
 /* Thread-local description of the last error (empty string if none). */
 const char* bxs_last_error(void);

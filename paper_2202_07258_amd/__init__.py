@@ -6,6 +6,6 @@ Importing the package does not load the library; the first solver call does,
 and raises if it is missing (there is no CPU fallback).
 """
 from .native import (  # noqa: F401
-    BoxscreenError, colmajor, load, solve_bvls, solve_bvls_varbatch, solve_nnls, version,
-    LIBRARY_PATH, EXPORTED, MAX_ROWS,
+    BoxscreenError, colmajor, load, solve_bvls, solve_bvls_varbatch, solve_nnls, solve_nnls_batched_shared,
+    version, LIBRARY_PATH, EXPORTED, MAX_ROWS,
 )

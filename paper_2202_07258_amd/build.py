@@ -8,7 +8,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libboxscreen.so")
-SOURCES = ["kernels.hip", "api.hip"]
+SOURCES = ["kernels.hip", "batched.hip", "api.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 HIPCC_FLAGS = [
@@ -30,7 +30,8 @@ def build_library(verbose: bool = False) -> str:
     srcs = [os.path.join(PKG, "csrc", s) for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(PKG, "csrc"), "-o", tmp, *srcs]
+           "-I", os.path.join(PKG, "csrc"), "-o", tmp, *srcs, "-L/opt/rocm/lib", "-lrocblas",
+           "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -38,6 +38,12 @@ static bxs_status fail(bxs_status s, const char* fmt, ...)
     return s;
 }
 
+bxs_status set_error(bxs_status s, const char* msg) { return fail(s, "%s", msg); }
+
+size_t batched_workspace_bytes(long m, long n, long B, int iter_precision);
+bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
+                            double* X, long ldx, signed char* sat, long ldsat, const bxs_opts* o, bxs_info* infos);
+
 #define BXS_HIP(call)                                                                     \
     do {                                                                                  \
         hipError_t e_ = (call);                                                           \
@@ -145,6 +151,8 @@ static bxs_status check_opts(const bxs_opts* o)
     if (isnan(o->step) || isinf(o->step)) return fail(BXS_ERR_ARG, "step must be finite");
     if (o->workspace && o->workspace_bytes == 0) return fail(BXS_ERR_ARG, "workspace given with 0 bytes");
     if (o->history && o->history_cap < 0) return fail(BXS_ERR_ARG, "history_cap < 0");
+    if (o->iter_precision != BXS_ITER_F64 && o->iter_precision != BXS_ITER_BF16X3)
+        return fail(BXS_ERR_ARG, "unknown iter_precision %d", o->iter_precision);
     return BXS_OK;
 }
 
@@ -627,6 +635,40 @@ bxs_status solve_nnls(long m, long n, int a_dtype, const void* A, long lda, cons
     std::vector<InstSpec> specs(1);
     specs[0] = InstSpec{m, n, lda, A, y, nullptr, nullptr, x, sat};
     return solve_common(specs, a_dtype, opts, info);
+}
+
+static bxs_status check_batched(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y,
+                                long ldy, const double* X, long ldx, const signed char* sat, long ldsat,
+                                const bxs_opts* opts)
+{
+    bxs_status s = check_opts(opts);
+    if (s != BXS_OK) return s;
+    if (opts->solver != BXS_PG) return fail(BXS_ERR_ARG, "the batched shared-matrix solver runs projected gradient");
+    if (a_dtype != BXS_F64 && a_dtype != BXS_F32) return fail(BXS_ERR_ARG, "unknown a_dtype %d", a_dtype);
+    if (m < 1 || n < 1 || B < 1) return fail(BXS_ERR_SHAPE, "m=%ld n=%ld B=%ld must be >= 1", m, n, B);
+    if (lda < m || ldy < m || ldx < n || ldsat < n) return fail(BXS_ERR_SHAPE, "a leading dimension is too small");
+    if ((double)m * (double)B > 2e9 || (double)n * (double)B > 2e9 || (double)m * (double)n > 2e9)
+        return fail(BXS_ERR_SHAPE, "batched problem too large for 32-bit GEMM sizes");
+    if (!A || !Y || !X || !sat) return fail(BXS_ERR_ARG, "NULL array argument");
+    return BXS_OK;
+}
+
+bxs_status bxs_workspace_size_batched(long m, long n, long B, const bxs_opts* opts, size_t* bytes)
+{
+    if (!opts || !bytes) return fail(BXS_ERR_ARG, "NULL argument");
+    if (m < 1 || n < 1 || B < 1) return fail(BXS_ERR_SHAPE, "m=%ld n=%ld B=%ld must be >= 1", m, n, B);
+    *bytes = batched_workspace_bytes(m, n, B, opts->iter_precision);
+    return BXS_OK;
+}
+
+bxs_status solve_nnls_batched_shared(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y,
+                                     long ldy, double* X, long ldx, signed char* sat, long ldsat, const bxs_opts* opts,
+                                     bxs_info* infos)
+{
+    g_last_error.clear();
+    bxs_status s = check_batched(m, n, B, a_dtype, A, lda, Y, ldy, X, ldx, sat, ldsat, opts);
+    if (s != BXS_OK) return s;
+    return batched_nnls_run(m, n, B, a_dtype, A, lda, Y, ldy, X, ldx, sat, ldsat, opts, infos);
 }
 
 bxs_status solve_bvls_varbatch(long count, int a_dtype, const bxs_problem* probs, const bxs_opts* opts,

@@ -36,7 +36,8 @@ class Opts(C.Structure):
                 ("max_iter", C.c_long), ("eps_gap", C.c_double), ("step", C.c_double),
                 ("power_iters", C.c_int), ("t", C.c_void_p), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("history", C.POINTER(PassRecord)), ("history_cap", C.c_long), ("profile", C.c_int)]
+                ("history", C.POINTER(PassRecord)), ("history_cap", C.c_long), ("profile", C.c_int),
+                ("iter_precision", C.c_int)]
 
 
 class Info(C.Structure):
@@ -56,7 +57,8 @@ class Problem(C.Structure):
 
 EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls",
             "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
-            "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant"]
+            "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant",
+            "solve_nnls_batched_shared", "bxs_workspace_size_batched"]
 
 _lib = None
 
@@ -97,6 +99,12 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     lib.bxs_row_class.restype = C.c_int
     lib.bxs_set_sweep_variant.argtypes = [C.c_int, C.c_int]
     lib.bxs_set_sweep_variant.restype = C.c_int
+    lib.solve_nnls_batched_shared.argtypes = [C.c_long, C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long,
+                                              C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p, C.c_long,
+                                              C.POINTER(Opts), C.POINTER(Info)]
+    lib.solve_nnls_batched_shared.restype = C.c_int
+    lib.bxs_workspace_size_batched.argtypes = [C.c_long, C.c_long, C.c_long, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+    lib.bxs_workspace_size_batched.restype = C.c_int
     _lib = lib
     return lib
 
@@ -141,7 +149,7 @@ def colmajor(A: Any, device="cuda", dtype=None) -> torch.Tensor:
 
 def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, eps_gap=1e-6, step=0.0,
               power_iters=20, t: torch.Tensor | None = None, history=0, stream=None,
-              profile=False) -> tuple[Opts, Any]:
+              profile=False, iter_precision="f64") -> tuple[Opts, Any]:
     lib = load()
     o = Opts()
     lib.bxs_default_opts(C.byref(o))
@@ -155,6 +163,7 @@ def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, 
     o.t = _ptr(t)
     o.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
     o.profile = 1 if profile else 0
+    o.iter_precision = {"f64": 0, "bf16x3": 1}[iter_precision] if isinstance(iter_precision, str) else int(iter_precision)
     hist = None
     if history:
         hist = (PassRecord * int(history))()
@@ -297,3 +306,35 @@ def set_sweep_variant(row_class_: int, variant: int) -> None:
     st = lib.bxs_set_sweep_variant(int(row_class_), int(variant))
     if st != BXS_OK:
         _raise(lib, st)
+
+
+def solve_nnls_batched_shared(A, Y, X0=None, **kw):
+    """Batched NNLS with one shared matrix.  A (m, n) column-major GPU tensor
+    (float32/float64); Y (m, B) column-major float64 GPU tensor (column b is
+    right-hand side b).  Returns (X (n, B) column-major float64, sat (n, B)
+    int8, infos list)."""
+    lib = load()
+    m, n, lda, dt = _check_matrix(A)
+    if not (Y.is_cuda and Y.dtype == torch.float64 and Y.dim() == 2 and Y.shape[0] == m and Y.stride(0) == 1):
+        raise ValueError("Y must be an (m, B) column-major float64 GPU tensor")
+    B = Y.shape[1]
+    ldy = Y.stride(1) if B > 1 else m
+    dev = A.device
+    X = torch.zeros((B, n), dtype=torch.float64, device=dev) if X0 is None else X0.t().contiguous().clone()
+    sat = torch.empty((B, n), dtype=torch.int8, device=dev)
+    t = _vec(kw.pop("t", None), m, "t")
+    kw.pop("history", None)
+    opts, _ = make_opts(t=t, **kw)
+    b = C.c_size_t(0)
+    st = lib.bxs_workspace_size_batched(m, n, B, C.byref(opts), C.byref(b))
+    if st != BXS_OK:
+        _raise(lib, st)
+    wst = torch.empty(int(b.value), dtype=torch.uint8, device=dev)
+    opts.workspace = wst.data_ptr()
+    opts.workspace_bytes = int(b.value)
+    infos = (Info * B)()
+    st = lib.solve_nnls_batched_shared(m, n, B, dt, A.data_ptr(), lda, Y.data_ptr(), ldy, X.data_ptr(), n,
+                                       sat.data_ptr(), n, C.byref(opts), infos)
+    if st not in (BXS_OK, BXS_MAXITER):
+        _raise(lib, st)
+    return X.t(), sat.t(), [_info_dict(infos[i]) for i in range(B)]

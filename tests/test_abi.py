@@ -92,3 +92,15 @@ def test_workspace_query_shape_check(lib):
     o = _opts(lib)
     b = C.c_size_t(0)
     assert lib.bxs_workspace_size(0, 10, C.byref(o), C.byref(b)) == N.BXS_ERR_SHAPE
+
+
+def test_batched_argument_errors(lib):
+    o = _opts(lib)
+    f = lib.solve_nnls_batched_shared
+    assert f(0, 5, 3, 0, FAKE, 1, FAKE, 1, FAKE, 5, FAKE, 5, C.byref(o), None) == N.BXS_ERR_SHAPE
+    assert f(5, 5, 3, 0, FAKE, 4, FAKE, 5, FAKE, 5, FAKE, 5, C.byref(o), None) == N.BXS_ERR_SHAPE
+    assert f(5, 5, 3, 0, None, 5, FAKE, 5, FAKE, 5, FAKE, 5, C.byref(o), None) == N.BXS_ERR_ARG
+    o2 = _opts(lib, iter_precision=9)
+    assert f(5, 5, 3, 0, FAKE, 5, FAKE, 5, FAKE, 5, FAKE, 5, C.byref(o2), None) == N.BXS_ERR_ARG
+    o3 = _opts(lib, solver=1)
+    assert f(5, 5, 3, 0, FAKE, 5, FAKE, 5, FAKE, 5, FAKE, 5, C.byref(o3), None) == N.BXS_ERR_ARG

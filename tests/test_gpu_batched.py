@@ -1,0 +1,124 @@
+"""GPU parity of the batched shared-matrix NNLS solver (C ABI
+solve_nnls_batched_shared) against the FP64 oracle, per right-hand side.
+
+FP64 engine: trajectory parity (same step, schedule and dual points as the
+oracle run on each column of Y).  BF16x3 MFMA engine: the iterates differ
+from the oracle's at the 2^-16 level, so each right-hand side is checked for
+what is unique: the certified gap is below the tolerance and is confirmed by
+the oracle's own gap at the returned x, every screened coordinate is zero at
+the exact optimum (SciPy's active-set NNLS), and x is close to that optimum."""
+import numpy as np
+import pytest
+import torch
+from scipy.optimize import nnls
+
+from oracle import boxls as ob
+from synth import workloads as W
+from tests.gpu_helpers import parity_vs_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(seed, m, n, B, signed=False):
+    rng = W.rng_for(95, seed, m, n)
+    G = rng.standard_normal((m, n))
+    if not signed:
+        G = np.abs(G)
+    A = np.asfortranarray(W.unit_columns(G).astype(np.float32))
+    Y = np.asfortranarray(rng.standard_normal((m, B)) + A.astype(np.float64) @ np.abs(rng.standard_normal((n, B))) * 0.2)
+    return A, Y
+
+
+def _run(A, Y, **kw):
+    import paper_2202_07258_amd as bx
+    dA = bx.colmajor(A)
+    dY = torch.tensor(Y.T.copy(), dtype=torch.float64, device="cuda").t()
+    t = kw.pop("t", None)
+    if t is not None:
+        kw["t"] = torch.tensor(t, dtype=torch.float64, device="cuda")
+    X, sat, infos = bx.solve_nnls_batched_shared(dA, dY, **kw)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), sat.cpu().numpy(), infos
+
+
+@pytest.mark.parametrize("m,n,B", [(60, 150, 5), (130, 333, 70)])
+def test_batched_f64_trajectory_parity(m, n, B):
+    A, Y = _problem(0, m, n, B)
+    A64 = A.astype(np.float64)
+    eta = 1.0 / (1.05 * ob.lipschitz(A64))
+    kw = dict(screen_every=10, eps_gap=1e-8, max_iter=20000, step=eta)
+    X, S, infos = _run(A, Y, iter_precision="f64", **kw)
+    for b in range(B):
+        P = W.Problem(A, Y[:, b].copy(), np.zeros(n), np.full(n, np.inf))
+        parity_vs_oracle(P, X[:, b], S[:, b], infos[b], **kw)
+
+
+def _check_certified(A, Y, X, S, infos, eps_gap, t=None):
+    A64 = A.astype(np.float64)
+    m, n = A.shape
+    tt = -np.ones(m) if t is None else t
+    for b in range(Y.shape[1]):
+        y = Y[:, b]
+        x = X[:, b]
+        info = infos[b]
+        assert info["status_name"] == "ok", info
+        assert info["gap"] < eps_gap
+        # the oracle's own gap at the returned point, on the reduced problem
+        P = S[:, b] == 0
+        theta, eps, ok = ob.dual_point(A64[:, P], y, np.full(P.sum(), np.inf), x[P], tt)
+        g_ora = ob.duality_gap(A64[:, P], y, np.zeros(P.sum()), np.full(P.sum(), np.inf), x[P], theta)
+        assert g_ora <= info["gap"] * (1 + 1e-6) + 1e-12 * (1 + y @ y)
+        # safety: screened coordinates vanish at the exact optimum
+        xs, _ = nnls(A64, y, maxiter=50 * n)
+        assert np.all(xs[S[:, b] == -1] == 0.0)
+        assert np.all(x[S[:, b] == -1] == 0.0)
+        # primal suboptimality is bounded by the gap
+        assert ob.primal(A64, y, x) - ob.primal(A64, y, xs) <= info["gap"] + 1e-9
+
+
+def _well(seed, m, n, B):
+    rng = W.rng_for(96, seed, m, n)
+    A = np.asfortranarray(W.unit_columns(rng.standard_normal((m, n))).astype(np.float32))
+    Y = np.asfortranarray(rng.standard_normal((m, B)))
+    return A, Y
+
+
+def test_batched_bf16x3_certified():
+    A, Y = _well(0, 200, 120, 70)
+    t = W.interior_direction(A)
+    assert t is not None
+    A64 = A.astype(np.float64)
+    eta = 1.0 / (1.05 * ob.lipschitz(A64))
+    X, S, infos = _run(A, Y, iter_precision="bf16x3", screen_every=10, eps_gap=1e-8, max_iter=20000, step=eta, t=t)
+    _check_certified(A, Y, X, S, infos, 1e-8, t=t)
+    assert sum(int(np.count_nonzero(S[:, b])) for b in range(Y.shape[1])) > 0
+
+
+def test_batched_bf16x3_tracks_f64_engine():
+    # the increment form keeps the BF16x3 iterates on the FP64 trajectory
+    A, Y = _problem(1, 96, 256, 16)
+    eta = 1.0 / (1.05 * ob.lipschitz(A.astype(np.float64)))
+    kw = dict(screen_every=10, eps_gap=0.0, max_iter=3000, step=eta)
+    X1, S1, i1 = _run(A, Y, iter_precision="f64", **kw)
+    X3, S3, i3 = _run(A, Y, iter_precision="bf16x3", **kw)
+    for b in range(Y.shape[1]):
+        assert i3[b]["gap"] == pytest.approx(i1[b]["gap"], rel=1e-3)
+        assert np.max(np.abs(X3[:, b] - X1[:, b])) <= 1e-5 * max(1.0, np.max(np.abs(X1[:, b])))
+
+
+def test_batched_bf16x3_signed_matrix_with_direction():
+    # signed Gaussian matrix (the differentiable-layer setting): t from an LP
+    A, Y = _problem(2, 80, 60, 40, signed=True)
+    t = W.interior_direction(A)
+    assert t is not None
+    X, S, infos = _run(A, Y, iter_precision="bf16x3", screen_every=5, eps_gap=1e-8, max_iter=50000, t=t)
+    _check_certified(A, Y, X, S, infos, 1e-8, t=t)
+
+
+def test_batched_power_step_and_maxiter():
+    A, Y = _problem(3, 40, 90, 9)
+    X, S, infos = _run(A, Y, iter_precision="f64", screen_every=7, eps_gap=0.0, max_iter=30)
+    L = ob.lipschitz(A.astype(np.float64))
+    for info in infos:
+        assert info["status_name"] == "maxiter" and info["iters"] == 30
+        assert 0.9 * L <= info["lipschitz"] <= L * (1 + 1e-12)
