@@ -199,6 +199,25 @@ bxs_status solve_nnls_batched_shared(long m, long n, long B, int a_dtype, const 
                                      signed char* sat, long ldsat, const bxs_opts* opts, bxs_info* infos);
 bxs_status bxs_workspace_size_batched(long m, long n, long B, const bxs_opts* opts, size_t* bytes);
 
+/* Adjoint of the batched NNLS solution map by implicit differentiation.
+ * With F_b = {j : X_jb > 0} the free set of right-hand side b, the optimality
+ * conditions (Sec. 3.2, eq. optimality2) give x_F = (A_F^T A_F)^{-1} A_F^T y_b,
+ * so for an upstream gradient dL/dX:
+ *     v_b = (A_F^T A_F)^{-1} (dL/dx_b)_F   (masked conjugate gradients, FP64)
+ *     dL/dY = A V,   dL/dA = (Y - A X) V^T - (dL/dY) X^T   (summed over b)
+ * Coordinates at 0 are treated as saturated (one-sided derivative where a
+ * coordinate is weakly active).  opts->max_iter bounds the CG iterations and
+ * opts->eps_gap is the CG tolerance relative to ||(dL/dx_b)_F||.
+ *   A [lda*n] (a_dtype)  Y [ldy*B]  X [ldx*B] (forward solution)
+ *   dX [ldg*B] in   dY [lddy*B] out   dA [ldda*n] out or NULL
+ *   cg_iters host out or NULL.  Returns BXS_OK, or BXS_MAXITER if CG did not
+ *   reach the tolerance for every right-hand side. */
+bxs_status nnls_adjoint(long m, long n, long B, int a_dtype, const void* A, long lda,
+                        const double* Y, long ldy, const double* X, long ldx,
+                        const double* dX, long ldg, double* dY, long lddy, double* dA, long ldda,
+                        const bxs_opts* opts, long* cg_iters);
+bxs_status bxs_workspace_size_adjoint(long m, long n, long B, size_t* bytes);
+
 /* Thread-local description of the last error (empty string if none). */
 const char* bxs_last_error(void);
 

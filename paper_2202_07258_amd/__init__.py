@@ -7,5 +7,6 @@ and raises if it is missing (there is no CPU fallback).
 """
 from .native import (  # noqa: F401
     BoxscreenError, colmajor, load, solve_bvls, solve_bvls_varbatch, solve_nnls, solve_nnls_batched_shared,
-    version, LIBRARY_PATH, EXPORTED, MAX_ROWS,
+    nnls_adjoint, version, LIBRARY_PATH, EXPORTED, MAX_ROWS,
 )
+from .layer import nnls_layer  # noqa: F401

@@ -714,3 +714,202 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
 }
 
 }  // namespace bxs
+
+// ---------------------------------------------------------------------------
+// Adjoint of the batched NNLS solution map (implicit differentiation).
+// At an optimum with free set F_b = {j : x_jb > 0} the optimality conditions
+// (Sec. 3.2, eq. optimality2: a_j^T (y_b - A x_b) = 0 on F_b) give
+// x_F = (A_F^T A_F)^{-1} A_F^T y_b, hence for dL/dX:
+//     v_b      = (A_F^T A_F)^{-1} (dL/dx_b)_F      (batched masked CG, FP64)
+//     dL/dy_b  = A v_b  (v_b = 0 off F_b)
+//     dL/dA    = R V^T - (dL/dY) X^T,   R = Y - A X
+// ---------------------------------------------------------------------------
+namespace bxs {
+
+__global__ void k_adj_init(const double* __restrict__ X, long long ldx, const double* __restrict__ dX, long long ldg,
+                           int n, int B, double* __restrict__ V, double* __restrict__ Rc, double* __restrict__ P,
+                           signed char* __restrict__ F)
+{
+    const long long tot = (long long)n * B;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(k % n);
+        const long long b = k / n;
+        const bool free_ = X[j + b * ldx] > 0.0;
+        const double d = free_ ? dX[j + b * ldg] : 0.0;
+        F[k] = free_ ? 1 : 0;
+        V[k] = 0.0;
+        Rc[k] = d;
+        P[k] = d;
+    }
+}
+
+// per right-hand side dot products of two n x B blocks (one workgroup each)
+__global__ __launch_bounds__(256)
+void k_adj_dot(const double* __restrict__ U, const double* __restrict__ W, int n, double* __restrict__ out)
+{
+    __shared__ double sh[4];
+    const long long b = blockIdx.x;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) s = fma(U[j + b * n], W[j + b * n], s);
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// S <- mask(S); alpha = rs / (p.S); V += alpha P; Rc -= alpha S
+__global__ void k_adj_step(double* __restrict__ S, const signed char* __restrict__ F, const double* __restrict__ rs,
+                           const double* __restrict__ pq, double* __restrict__ V, double* __restrict__ Rc,
+                           const double* __restrict__ P, int n, int B)
+{
+    const long long tot = (long long)n * B;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
+        const long long b = k / n;
+        const double alpha = (pq[b] > 0.0) ? rs[b] / pq[b] : 0.0;
+        const double sv = F[k] ? S[k] : 0.0;
+        V[k] += alpha * P[k];
+        Rc[k] -= alpha * sv;
+    }
+}
+
+__global__ void k_adj_mask(double* __restrict__ S, const signed char* __restrict__ F, long long tot)
+{
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x)
+        if (!F[k]) S[k] = 0.0;
+}
+
+// P = Rc + (rs_new / rs_old) P; rs_old <- rs_new
+__global__ void k_adj_dir(double* __restrict__ P, const double* __restrict__ Rc, const double* __restrict__ rs_new,
+                          const double* __restrict__ rs_old, int n, int B)
+{
+    const long long tot = (long long)n * B;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
+        const long long b = k / n;
+        const double beta = (rs_old[b] > 0.0) ? rs_new[b] / rs_old[b] : 0.0;
+        P[k] = Rc[k] + beta * P[k];
+    }
+}
+
+__global__ void k_adj_conv(const double* __restrict__ rs, const double* __restrict__ rs0, int B, double tol2,
+                           int* __restrict__ notconv)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x)
+        if (rs[b] > tol2 * rs0[b]) atomicAdd(notconv, 1);
+}
+
+__global__ void k_adj_copy2(const double* __restrict__ src, long long lds, double* __restrict__ dst, long long ldd,
+                            int rows, int cols)
+{
+    const long long tot = (long long)rows * cols;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(k % rows);
+        const long long c = k / rows;
+        dst[i + c * ldd] = src[i + c * lds];
+    }
+}
+
+size_t adjoint_workspace_bytes(long m, long n, long B)
+{
+    size_t b = 0;
+    b += al(sizeof(double) * m * n);       // A64
+    b += al(sizeof(double) * n * B) * 5;   // X, V, Rc, P, S
+    b += al(sizeof(double) * m * B) * 2;   // Q, R
+    b += al(sizeof(signed char) * n * B);  // F
+    b += al(sizeof(double) * B) * 4;       // rs, rs0, pq, rs_new
+    b += al(sizeof(int) * 16);
+    return b + 1024;
+}
+
+bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
+                       const double* X, long ldx, const double* dX, long ldg, double* dY, long lddy, double* dA,
+                       long ldda, const bxs_opts* o, long* cg_iters)
+{
+    hipStream_t s = (hipStream_t)o->stream;
+    const size_t need = adjoint_workspace_bytes(m, n, B);
+    void* ws = o->workspace;
+    bool owned = false;
+    if (ws) {
+        if (o->workspace_bytes < need) return set_error(BXS_ERR_NOMEM, "workspace too small for the adjoint");
+    } else {
+        if (hipMalloc(&ws, need) != hipSuccess) return set_error(BXS_ERR_NOMEM, "hipMalloc failed for the adjoint workspace");
+        owned = true;
+    }
+    struct Guard { void* p; bool own; hipStream_t s; ~Guard() { if (own) { (void)hipStreamSynchronize(s); (void)hipFree(p); } } } guard{ws, owned, s};
+    char* cur = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+    auto take = [&](size_t bytes) { char* p = cur; cur += al(bytes); return p; };
+    double* A64 = (double*)take(sizeof(double) * m * n);
+    double* Xc = (double*)take(sizeof(double) * n * B);
+    double* V = (double*)take(sizeof(double) * n * B);
+    double* Rc = (double*)take(sizeof(double) * n * B);
+    double* P = (double*)take(sizeof(double) * n * B);
+    double* S = (double*)take(sizeof(double) * n * B);
+    double* Q = (double*)take(sizeof(double) * m * B);
+    double* R = (double*)take(sizeof(double) * m * B);
+    signed char* F = (signed char*)take(sizeof(signed char) * n * B);
+    double* rs = (double*)take(sizeof(double) * B);
+    double* rs0 = (double*)take(sizeof(double) * B);
+    double* pq = (double*)take(sizeof(double) * B);
+    double* rsn = (double*)take(sizeof(double) * B);
+    int* notconv = (int*)take(sizeof(int) * 16);
+
+    rocblas_handle h;
+    bxs_status bs = blas_handle(s, &h);
+    if (bs != BXS_OK) return bs;
+    const int grid = 2048;
+    if (a_dtype == BXS_F32)
+        k_b_convert_a<float><<<grid, 256, 0, s>>>((const float*)A, lda, (int)m, (int)n, A64, nullptr);
+    else
+        k_b_convert_a<double><<<grid, 256, 0, s>>>((const double*)A, lda, (int)m, (int)n, A64, nullptr);
+    k_adj_copy2<<<grid, 256, 0, s>>>(X, ldx, Xc, n, (int)n, (int)B);
+    k_adj_init<<<grid, 256, 0, s>>>(X, ldx, dX, ldg, (int)n, (int)B, V, Rc, P, F);
+    k_adj_dot<<<(int)B, 256, 0, s>>>(Rc, Rc, (int)n, rs);
+    k_b_copy<<<64, 256, 0, s>>>(rs, rs0, B);
+    BXS_HIPB(hipGetLastError());
+    const double one = 1.0, zero = 0.0, mone = -1.0;
+    const double tol = o->eps_gap > 0.0 ? o->eps_gap : 1e-12;
+    const long maxit = o->max_iter;
+    int* hflag = nullptr;
+    BXS_HIPB(hipHostMalloc((void**)&hflag, sizeof(int), hipHostMallocDefault));
+    struct HG { int* p; ~HG() { (void)hipHostFree(p); } } hg{hflag};
+    long it = 0;
+    for (; it < maxit; ++it) {
+        // S = mask(A^T (A P))
+        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)m, (int)B, (int)n, &one, A64,
+                               (int)m, P, (int)n, &zero, Q, (int)m));
+        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, (int)n, (int)B, (int)m, &one,
+                               A64, (int)m, Q, (int)m, &zero, S, (int)n));
+        k_adj_mask<<<grid, 256, 0, s>>>(S, F, (long long)n * B);
+        k_adj_dot<<<(int)B, 256, 0, s>>>(P, S, (int)n, pq);
+        k_adj_step<<<grid, 256, 0, s>>>(S, F, rs, pq, V, Rc, P, (int)n, (int)B);
+        k_adj_dot<<<(int)B, 256, 0, s>>>(Rc, Rc, (int)n, rsn);
+        k_adj_dir<<<grid, 256, 0, s>>>(P, Rc, rsn, rs, (int)n, (int)B);
+        k_b_copy<<<64, 256, 0, s>>>(rsn, rs, B);
+        if ((it % 8) == 7 || it + 1 == maxit) {
+            BXS_HIPB(hipMemsetAsync(notconv, 0, sizeof(int), s));
+            k_adj_conv<<<16, 256, 0, s>>>(rs, rs0, (int)B, tol * tol, notconv);
+            BXS_HIPB(hipMemcpyAsync(hflag, notconv, sizeof(int), hipMemcpyDeviceToHost, s));
+            BXS_HIPB(hipStreamSynchronize(s));
+            if (*hflag == 0) { ++it; break; }
+        }
+    }
+    BXS_HIPB(hipGetLastError());
+    // dL/dY = A V
+    BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)m, (int)B, (int)n, &one, A64, (int)m,
+                           V, (int)n, &zero, Q, (int)m));
+    k_adj_copy2<<<grid, 256, 0, s>>>(Q, m, dY, lddy, (int)m, (int)B);
+    if (dA) {
+        // R = Y - A X, then dL/dA = R V^T - (dL/dY) X^T
+        k_adj_copy2<<<grid, 256, 0, s>>>(Y, ldy, R, m, (int)m, (int)B);
+        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)m, (int)B, (int)n, &mone, A64,
+                               (int)m, Xc, (int)n, &one, R, (int)m));
+        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (int)m, (int)n, (int)B, &one, R,
+                               (int)m, V, (int)n, &zero, dA, (int)ldda));
+        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (int)m, (int)n, (int)B, &mone, Q,
+                               (int)m, Xc, (int)n, &one, dA, (int)ldda));
+    }
+    BXS_HIPB(hipStreamSynchronize(s));
+    if (cg_iters) *cg_iters = it;
+    return (*hflag == 0) ? BXS_OK : BXS_MAXITER;
+}
+
+}  // namespace bxs

@@ -1,0 +1,51 @@
+"""Differentiable batched NNLS layer: X = argmin_{X >= 0} 1/2 ||A X - Y||_F^2.
+
+Forward: solve_nnls_batched_shared (projected gradient with Gap-safe
+screening, certified gap per column).  Backward: nnls_adjoint (implicit
+differentiation on each column's free set).  Both run in libboxscreen.so; this
+module only converts tensor layouts and dtypes around the two calls.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import native
+
+
+class _NNLSLayer(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, A, Y, t, opts, adj_opts):
+        Ac = A.detach().t().contiguous().t()            # column-major copy
+        Y64 = Y.detach().to(torch.float64).t().contiguous().t()
+        X, sat, infos = native.solve_nnls_batched_shared(Ac, Y64, t=t, **opts)
+        ctx.save_for_backward(Ac, Y64, X)
+        ctx.adj_opts = adj_opts
+        ctx.infos = infos
+        return X.to(Y.dtype)
+
+    @staticmethod
+    def backward(ctx, gX):
+        Ac, Y64, X = ctx.saved_tensors
+        need_dA = ctx.needs_input_grad[0]
+        dY, dA, iters, status = native.nnls_adjoint(Ac, Y64, X, gX.to(torch.float64), need_dA=need_dA,
+                                                    **ctx.adj_opts)
+        ctx.cg_iterations = iters
+        gA = dA.to(Ac.dtype) if (need_dA and dA is not None) else None
+        gY = dY.to(gX.dtype) if ctx.needs_input_grad[1] else None
+        return gA, gY, None, None, None
+
+
+def nnls_layer(A: torch.Tensor, Y: torch.Tensor, t: torch.Tensor | None = None, *,
+               eps_gap: float = 1e-8, max_iter: int = 100000, screen_every: int = 10,
+               iter_precision: str = "f64", step: float = 0.0, cg_max_iter: int = 10000,
+               cg_tol: float = 1e-12) -> torch.Tensor:
+    """Non-negative least-squares layer on the GPU.
+
+    A (m, n) float32/float64, Y (m, B): column b of the result solves
+    min_{x >= 0} 1/2 ||A x - Y[:, b]||^2.  t (m,) float64 is the dual
+    translation direction (default -1, valid for non-negative A; for a signed
+    A supply a direction with A^T t < 0)."""
+    opts = dict(eps_gap=eps_gap, max_iter=max_iter, screen_every=screen_every, iter_precision=iter_precision,
+                step=step)
+    adj = dict(max_iter=cg_max_iter, tol=cg_tol)
+    return _NNLSLayer.apply(A, Y, t, opts, adj)

@@ -58,7 +58,8 @@ class Problem(C.Structure):
 EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls",
             "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
             "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant",
-            "solve_nnls_batched_shared", "bxs_workspace_size_batched"]
+            "solve_nnls_batched_shared", "bxs_workspace_size_batched", "nnls_adjoint",
+            "bxs_workspace_size_adjoint"]
 
 _lib = None
 
@@ -105,6 +106,12 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     lib.solve_nnls_batched_shared.restype = C.c_int
     lib.bxs_workspace_size_batched.argtypes = [C.c_long, C.c_long, C.c_long, C.POINTER(Opts), C.POINTER(C.c_size_t)]
     lib.bxs_workspace_size_batched.restype = C.c_int
+    lib.nnls_adjoint.argtypes = [C.c_long, C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long, C.c_void_p, C.c_long,
+                                 C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p,
+                                 C.c_long, C.POINTER(Opts), C.POINTER(C.c_long)]
+    lib.nnls_adjoint.restype = C.c_int
+    lib.bxs_workspace_size_adjoint.argtypes = [C.c_long, C.c_long, C.c_long, C.POINTER(C.c_size_t)]
+    lib.bxs_workspace_size_adjoint.restype = C.c_int
     _lib = lib
     return lib
 
@@ -338,3 +345,38 @@ def solve_nnls_batched_shared(A, Y, X0=None, **kw):
     if st not in (BXS_OK, BXS_MAXITER):
         _raise(lib, st)
     return X.t(), sat.t(), [_info_dict(infos[i]) for i in range(B)]
+
+
+def _colmajor64(T: torch.Tensor, rows: int, name: str) -> torch.Tensor:
+    if not (T.is_cuda and T.dim() == 2 and T.shape[0] == rows):
+        raise ValueError(f"{name} must be a 2-D GPU tensor with {rows} rows")
+    return T.to(torch.float64).t().contiguous().t()
+
+
+def nnls_adjoint(A, Y, X, dX, *, max_iter=10000, tol=1e-12, need_dA=True, stream=None):
+    """Implicit-differentiation adjoint of the batched NNLS map (C ABI
+    nnls_adjoint).  A (m, n) column-major GPU tensor; Y (m, B), X (n, B),
+    dX (n, B) GPU tensors.  Returns (dY (m, B) float64, dA (m, n) float64 or
+    None, cg_iterations, status)."""
+    lib = load()
+    m, n, lda, dt = _check_matrix(A)
+    Y64 = _colmajor64(Y, m, "Y")
+    B = Y64.shape[1]
+    X64 = _colmajor64(X, n, "X")
+    G64 = _colmajor64(dX, n, "dX")
+    dY = torch.empty((B, m), dtype=torch.float64, device=A.device).t()
+    dA = torch.empty((n, m), dtype=torch.float64, device=A.device).t() if need_dA else None
+    o, _ = make_opts(max_iter=max_iter, eps_gap=tol, stream=stream)
+    b = C.c_size_t(0)
+    st = lib.bxs_workspace_size_adjoint(m, n, B, C.byref(b))
+    if st != BXS_OK:
+        _raise(lib, st)
+    wst = torch.empty(int(b.value), dtype=torch.uint8, device=A.device)
+    o.workspace = wst.data_ptr()
+    o.workspace_bytes = int(b.value)
+    it = C.c_long(0)
+    st = lib.nnls_adjoint(m, n, B, dt, A.data_ptr(), lda, Y64.data_ptr(), m, X64.data_ptr(), n, G64.data_ptr(), n,
+                          dY.data_ptr(), m, dA.data_ptr() if dA is not None else None, m, C.byref(o), C.byref(it))
+    if st not in (BXS_OK, BXS_MAXITER):
+        _raise(lib, st)
+    return dY, dA, int(it.value), STATUS_NAMES[st]

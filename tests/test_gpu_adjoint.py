@@ -1,0 +1,87 @@
+"""GPU checks of the implicit-differentiation adjoint (C ABI nnls_adjoint) and
+the differentiable NNLS layer: against the oracle's analytic adjoint at the
+same exact solution, and against FP64 central finite differences of SciPy's
+exact active-set NNLS on the 32 x 64 subproblem of the layer workload."""
+import numpy as np
+import pytest
+import torch
+from scipy.optimize import nnls
+
+from oracle import adjoint as oa
+from oracle import boxls as ob
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _exact(A64, y):
+    x, _ = nnls(A64, y, maxiter=100 * A64.shape[1])
+    return x
+
+
+def _instance(seed, m, n, B):
+    rng = W.rng_for(97, seed, m, n)
+    A = rng.standard_normal((m, n))
+    Y = rng.random((m, B))
+    T = np.abs(rng.standard_normal((n, B))) * (rng.random((n, B)) < 0.1)
+    return A, Y, T
+
+
+@pytest.mark.parametrize("m,n,B", [(40, 30, 6), (64, 100, 9)])
+def test_adjoint_matches_oracle_formula(m, n, B):
+    import paper_2202_07258_amd as bx
+    A, Y, T = _instance(0, m, n, B)
+    X = np.stack([_exact(A, Y[:, b]) for b in range(B)], axis=1)
+    G = 2.0 * (X - T)
+    dA = torch.tensor(A.T.copy(), device="cuda").t()
+    dY, dAgrad, iters, status = bx.nnls_adjoint(dA, torch.tensor(Y, device="cuda"), torch.tensor(X, device="cuda"),
+                                                torch.tensor(G, device="cuda"))
+    assert status == "ok"
+    dY = dY.cpu().numpy()
+    dAg = dAgrad.cpu().numpy()
+    dA_ref = np.zeros_like(A)
+    for b in range(B):
+        gy, gA, _, _ = oa.solution_grad(A, Y[:, b], np.zeros(n), np.full(n, np.inf), X[:, b], G[:, b])
+        np.testing.assert_allclose(dY[:, b], gy, rtol=1e-8, atol=1e-9 * (1 + np.abs(gy).max()))
+        dA_ref += gA
+    np.testing.assert_allclose(dAg, dA_ref, rtol=1e-8, atol=1e-9 * (1 + np.abs(dA_ref).max()))
+
+
+def test_layer_gradient_finite_differences():
+    import paper_2202_07258_amd as bx
+    # the 32 x 64 subproblem of the layer workload, one right-hand side whose
+    # matrix admits a translation direction and whose solution is strictly
+    # complementary
+    for rep in range(40):
+        A, Y, T = W.c5_layer(rep)
+        A, y, tg = A[:32, :64].copy(), Y[:32, 0].copy(), T[:64, 0].copy()
+        t = W.interior_direction(A)
+        if t is None:
+            continue
+        x = _exact(A, y)
+        F = x > 0
+        g = A.T @ (y - A @ x)
+        if 0 < F.sum() < 32 and np.min(x[F]) > 1e-4 and np.max(g[~F]) < -1e-4:
+            break
+    else:
+        pytest.skip("no strictly complementary subproblem")
+    At = torch.tensor(A, device="cuda", requires_grad=True)
+    Yt = torch.tensor(y[:, None], device="cuda", requires_grad=True)
+    tt = torch.tensor(t, device="cuda")
+    X = bx.nnls_layer(At, Yt, tt, eps_gap=1e-11, max_iter=400000, screen_every=10)
+    loss = ((X[:, 0] - torch.tensor(tg, device="cuda")) ** 2).sum()
+    loss.backward()
+    gy = Yt.grad.cpu().numpy()[:, 0]
+    gA = At.grad.cpu().numpy()
+    L = lambda xx: float(np.sum((xx - tg) ** 2))
+    h = 1e-6
+    for i in range(32):
+        e = np.zeros(32); e[i] = h
+        fd = (L(_exact(A, y + e)) - L(_exact(A, y - e))) / (2 * h)
+        assert fd == pytest.approx(gy[i], rel=1e-4, abs=1e-6)
+    rng = np.random.default_rng(0)
+    for _ in range(30):
+        i, j = rng.integers(32), rng.integers(64)
+        E = np.zeros_like(A); E[i, j] = h
+        fd = (L(_exact(A + E, y)) - L(_exact(A - E, y))) / (2 * h)
+        assert fd == pytest.approx(gA[i, j], rel=1e-4, abs=1e-6)
