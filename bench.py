@@ -85,9 +85,17 @@ def sweep_roofline(infos, m, elem_bytes):
             traffic = None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_sweep<float,256,1,16,4,kModePG> (fused A^T r / projected step / A x)",
+            "kernel": sweep_kernel_name(m),
             "algorithmic_bytes_per_launch": int(per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
             "launches": launches}
+
+
+def sweep_kernel_name(m):
+    """Shape of the fused PG sweep the library runs for m rows."""
+    from paper_2202_07258_amd import native as N
+    v = N.sweep_variants()[N.variant_for_rows(m)]
+    return (f"k_sweep<float,{v['tpc']},{v['ng']},{v['rows']},4,{v['cbi']},{v['pd']},kModePG> "
+            "(fused A^T r / projected step / A x)")
 
 
 def cpu_baseline(P, budget_iters=None):
@@ -120,6 +128,12 @@ def main():
     ap.add_argument("--no-unscreened", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="bound the oracle baseline to this many iterations (0: full solve)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "table2"],
+                    help="c2 (default): the headline workload; the others are measured separately")
+    ap.add_argument("--c3-rhs", type=int, default=8192)
+    ap.add_argument("--c3-iters", type=int, default=200)
+    ap.add_argument("--c4-count", type=int, default=2048)
+    ap.add_argument("--c5-iters", type=int, default=20000)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -139,6 +153,11 @@ def main():
     bx.load()
     device = "cuda:0"
     torch.cuda.set_device(0)
+    if args.workload != "c2":
+        import bench_workloads
+        out = bench_workloads.run(args.workload, args, device)
+        print(json.dumps(out), flush=True)
+        return
 
     log("[bench] generating C2 (4000x16000 fp32 BVLS)")
     P = W.c2_bvls(0)
@@ -165,11 +184,6 @@ def main():
         "roofline": roof,
     }
 
-    # independent check of the result with the oracle's definitions (FP64, host)
-    from oracle import boxls as ob
-    A64 = P.A64()
-    theta = ob.residual_dual_point(A64, P.y, xg)
-    result["solve"]["gap_oracle_at_x"] = ob.duality_gap(A64, P.y, P.l, P.u, xg, theta)
 
     if not args.no_unscreened:
         log("[bench] unscreened solves")
@@ -216,6 +230,11 @@ def main():
                       f"{info['iters']}-iteration solve")
         result["cpu_baseline"] = {"value": round(val, 5), "unit": "solves/s", "cores": cores, "kind": "oracle",
                                   "sample": sample, "seconds": round(dtc, 2)}
+        # the oracle's own FP64 gap (eq. Dual_Gap) at the GPU's returned x
+        from oracle import boxls as ob
+        A64 = P.A64()
+        theta = ob.residual_dual_point(A64, P.y, xg)
+        result["solve"]["gap_oracle_at_x"] = ob.duality_gap(A64, P.y, P.l, P.u, xg, theta)
     print(json.dumps(result), flush=True)
 
 

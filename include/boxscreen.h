@@ -55,7 +55,8 @@ typedef enum {
     BXS_ERR_BOUNDS    = 4,  /* l_j = -inf, u_j = -inf or l_j > u_j                 */
     BXS_ERR_DEVICE    = 5,  /* HIP runtime error (message in bxs_last_error)       */
     BXS_ERR_NOMEM     = 6,  /* workspace too small or allocation failure           */
-    BXS_MAXITER       = 7   /* max_iter reached first: x = last iterate, info set  */
+    BXS_MAXITER       = 7,  /* max_iter reached first: x = last iterate, info set  */
+    BXS_SINGULAR      = 8   /* adjoint: a free-set normal matrix is singular       */
 } bxs_status;
 
 typedef enum { BXS_PG = 0, BXS_CD = 1 } bxs_solver;   /* projected gradient / cyclic coordinate descent */
@@ -120,7 +121,8 @@ typedef struct {
     double ms_solve;    /* device time of the iterations and screening passes           */
     long   col_iters;   /* sum over primal iterations of the preserved-set size         */
     double sweep_ms;    /* opts->profile: summed duration of the primal-iteration sweep
-                           launches (PG: fused A^T r / update / A x; CD: the sweep)      */
+                           launches (PG: fused A^T r / update / A x; CD: the sweep;
+                           batched solver: the pair of iteration GEMMs)               */
     long   sweep_launches; /* opts->profile: number of timed sweep launches             */
 } bxs_info;
 
@@ -176,8 +178,9 @@ bxs_status solve_bvls_varbatch(long count, int a_dtype, const bxs_problem* probs
  * default).  These settings are process-wide and must not change while a
  * solve is running.  Used by the autotuner, which times the candidates. */
 int        bxs_num_sweep_variants(void);
-bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi, long* capacity);
+bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi, int* pd, long* capacity);
 int        bxs_row_class(long m);            /* -1 if m > BXS_MAX_ROWS */
+int        bxs_sweep_variant_for_rows(long m); /* variant later calls use for m rows, -1 if none */
 bxs_status bxs_set_sweep_variant(int row_class, int v);
 
 /* Batched non-negative LS with one shared matrix (Alg. 2 for every column
@@ -210,8 +213,13 @@ bxs_status bxs_workspace_size_batched(long m, long n, long B, const bxs_opts* op
  * opts->eps_gap is the CG tolerance relative to ||(dL/dx_b)_F||.
  *   A [lda*n] (a_dtype)  Y [ldy*B]  X [ldx*B] (forward solution)
  *   dX [ldg*B] in   dY [lddy*B] out   dA [ldda*n] out or NULL
- *   cg_iters host out or NULL.  Returns BXS_OK, or BXS_MAXITER if CG did not
- *   reach the tolerance for every right-hand side. */
+ *   cg_iters host out or NULL.  Each right-hand side runs CG until its
+ *   residual is below the tolerance or p^T A_F^T A_F p <= 0 (A_F rank
+ *   deficient, e.g. more free coordinates than rows: the forward solution is
+ *   not an isolated optimum there); such a column keeps its last CG iterate.
+ *   Returns BXS_OK; BXS_SINGULAR if at least one column broke down;
+ *   BXS_MAXITER if CG did not reach the tolerance for every right-hand side;
+ *   or an error code (outputs unset). */
 bxs_status nnls_adjoint(long m, long n, long B, int a_dtype, const void* A, long lda,
                         const double* Y, long ldy, const double* X, long ldx,
                         const double* dX, long ldg, double* dY, long lddy, double* dA, long ldda,

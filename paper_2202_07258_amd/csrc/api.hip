@@ -556,9 +556,10 @@ const char* bxs_last_error(void) { return g_last_error.c_str(); }
 
 int bxs_num_sweep_variants(void) { return kNumVariants; }
 
-bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi, long* capacity)
+bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi, int* pd, long* capacity)
 {
     if (v < 0 || v >= kNumVariants) return fail(BXS_ERR_ARG, "variant %d out of range", v);
+    if (pd) *pd = kVariants[v].pd;
     if (tpc) *tpc = kVariants[v].tpc;
     if (ng) *ng = kVariants[v].ng;
     if (rows) *rows = kVariants[v].rows;
@@ -568,6 +569,8 @@ bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi,
 }
 
 int bxs_row_class(long m) { return default_variant_for_rows(m); }
+
+int bxs_sweep_variant_for_rows(long m) { return choose_variant(m); }
 
 bxs_status bxs_set_sweep_variant(int row_class, int v)
 {

@@ -657,18 +657,31 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     struct HG { int* p; ~HG() { (void)hipHostFree(p); } } hg{hdone};
     const int K = o->screen_every;
     long long iters = 0;
+    // optional HIP-event timing of the iteration GEMM pairs
+    std::vector<hipEvent_t> pev;
+    struct PG2 { std::vector<hipEvent_t>* v; ~PG2() { for (auto e : *v) if (e) (void)hipEventDestroy(e); } } pg2{&pev};
+    if (o->profile) {
+        pev.assign(2 * (size_t)K, nullptr);
+        for (auto& e : pev) BXS_HIPB(hipEventCreate(&e));
+    }
+    double gemm_ms = 0.0;
+    long gemm_pairs = 0;
     while (true) {
         const long long kk = std::min<long long>(K, o->max_iter - iters);
         for (long long k = 0; k < kk; ++k) {
             if (prec == 1) {
                 k_b_step_mixed<<<grid, 256, 0, s>>>(X64, D32, G32, (int)n, act, nact, sat, ldsat, eta);
+                if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k], s));
                 dim3 g0((unsigned)((m + 63) / 64), (unsigned)((B + 63) / 64));
                 k_gemm_bf16x3<0><<<g0, 256, 0, s>>>(A32, lda32, (int)m, (int)n, act, nact, D32, n, U32, m);
                 dim3 g1((unsigned)((n + 63) / 64), (unsigned)((B + 63) / 64));
                 k_gemm_bf16x3<1><<<g1, 256, 0, s>>>(A32, lda32, (int)m, (int)n, act, nact, U32, m, G32, n);
+                if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k + 1], s));
             } else {
+                if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k], s));
                 bs = residual_and_corr();
                 if (bs != BXS_OK) return bs;
+                if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k + 1], s));
                 k_b_update64<<<grid, 256, 0, s>>>(X64, G64, (int)n, (int)B, sat, ldsat, st, eta);
             }
         }
@@ -684,6 +697,14 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
         BXS_HIPB(hipGetLastError());
         BXS_HIPB(hipMemcpyAsync(hdone, done_counter, sizeof(int), hipMemcpyDeviceToHost, s));
         BXS_HIPB(hipStreamSynchronize(s));
+        if (o->profile) {
+            for (long long k = 0; k < kk; ++k) {
+                float ms = 0.f;
+                BXS_HIPB(hipEventElapsedTime(&ms, pev[2 * k], pev[2 * k + 1]));
+                gemm_ms += ms;
+                ++gemm_pairs;
+            }
+        }
         if (*hdone >= B || final_pass) break;
     }
     k_b_output<<<grid, 256, 0, s>>>(X64, X, ldx, (int)n, (int)B);
@@ -708,6 +729,8 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
             f.gap = S.gap; f.primal = S.primal; f.radius = S.radius; f.eps = S.eps;
             f.step = eta; f.lipschitz = lam_h; f.ms_setup = ms_setup; f.ms_solve = ms_solve;
             f.col_iters = S.col_iters;
+            f.sweep_ms = gemm_ms;
+            f.sweep_launches = gemm_pairs;
         }
     }
     return worst;
@@ -757,15 +780,18 @@ void k_adj_dot(const double* __restrict__ U, const double* __restrict__ W, int n
     if (threadIdx.x == 0) out[b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-// S <- mask(S); alpha = rs / (p.S); V += alpha P; Rc -= alpha S
+// S <- mask(S); alpha = rs / (p.S); V += alpha P; Rc -= alpha S.  A column
+// whose flag is set (converged, or p^T S <= 0: the masked normal matrix is
+// singular along p) is frozen.
 __global__ void k_adj_step(double* __restrict__ S, const signed char* __restrict__ F, const double* __restrict__ rs,
-                           const double* __restrict__ pq, double* __restrict__ V, double* __restrict__ Rc,
-                           const double* __restrict__ P, int n, int B)
+                           const double* __restrict__ pq, const int* __restrict__ done, double* __restrict__ V,
+                           double* __restrict__ Rc, const double* __restrict__ P, int n, int B)
 {
     const long long tot = (long long)n * B;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
         const long long b = k / n;
-        const double alpha = (pq[b] > 0.0) ? rs[b] / pq[b] : 0.0;
+        if (done[b] || !(pq[b] > 0.0)) continue;
+        const double alpha = rs[b] / pq[b];
         const double sv = F[k] ? S[k] : 0.0;
         V[k] += alpha * P[k];
         Rc[k] -= alpha * sv;
@@ -778,23 +804,42 @@ __global__ void k_adj_mask(double* __restrict__ S, const signed char* __restrict
         if (!F[k]) S[k] = 0.0;
 }
 
-// P = Rc + (rs_new / rs_old) P; rs_old <- rs_new
+// P = Rc + (rs_new / rs_old) P for the columns still running
 __global__ void k_adj_dir(double* __restrict__ P, const double* __restrict__ Rc, const double* __restrict__ rs_new,
-                          const double* __restrict__ rs_old, int n, int B)
+                          const double* __restrict__ rs_old, const int* __restrict__ done, int n, int B)
 {
     const long long tot = (long long)n * B;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
         const long long b = k / n;
+        if (done[b]) continue;
         const double beta = (rs_old[b] > 0.0) ? rs_new[b] / rs_old[b] : 0.0;
         P[k] = Rc[k] + beta * P[k];
     }
 }
 
-__global__ void k_adj_conv(const double* __restrict__ rs, const double* __restrict__ rs0, int B, double tol2,
-                           int* __restrict__ notconv)
+// Per column bookkeeping after a CG step: rs <- rs_new; a column is done when
+// its residual fell below tol^2 * rs0 (done = 1) or when p^T A_F^T A_F p <= 0
+// or a non-finite value appeared (done = 2, breakdown).
+__global__ void k_adj_track(double* __restrict__ rs, const double* __restrict__ rsn, const double* __restrict__ rs0,
+                            const double* __restrict__ pq, int* __restrict__ done, int B, double tol2)
 {
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x)
-        if (rs[b] > tol2 * rs0[b]) atomicAdd(notconv, 1);
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+        if (done[b]) continue;
+        const double r = rsn[b];
+        if (!(pq[b] > 0.0) || !isfinite(r)) { done[b] = 2; continue; }
+        rs[b] = r;
+        if (r <= tol2 * rs0[b]) done[b] = 1;
+    }
+}
+
+// counters[0] = columns not converged, counters[1] = breakdowns
+__global__ void k_adj_count(const int* __restrict__ done, int B, int* __restrict__ counters)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+        const int d = done[b];
+        if (d != 1) atomicAdd(&counters[0], 1);
+        if (d == 2) atomicAdd(&counters[1], 1);
+    }
 }
 
 __global__ void k_adj_copy2(const double* __restrict__ src, long long lds, double* __restrict__ dst, long long ldd,
@@ -816,6 +861,7 @@ size_t adjoint_workspace_bytes(long m, long n, long B)
     b += al(sizeof(double) * m * B) * 2;   // Q, R
     b += al(sizeof(signed char) * n * B);  // F
     b += al(sizeof(double) * B) * 4;       // rs, rs0, pq, rs_new
+    b += al(sizeof(int) * B);              // done
     b += al(sizeof(int) * 16);
     return b + 1024;
 }
@@ -850,7 +896,8 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     double* rs0 = (double*)take(sizeof(double) * B);
     double* pq = (double*)take(sizeof(double) * B);
     double* rsn = (double*)take(sizeof(double) * B);
-    int* notconv = (int*)take(sizeof(int) * 16);
+    int* done = (int*)take(sizeof(int) * B);
+    int* counters = (int*)take(sizeof(int) * 16);
 
     rocblas_handle h;
     bxs_status bs = blas_handle(s, &h);
@@ -864,13 +911,16 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     k_adj_init<<<grid, 256, 0, s>>>(X, ldx, dX, ldg, (int)n, (int)B, V, Rc, P, F);
     k_adj_dot<<<(int)B, 256, 0, s>>>(Rc, Rc, (int)n, rs);
     k_b_copy<<<64, 256, 0, s>>>(rs, rs0, B);
+    BXS_HIPB(hipMemsetAsync(done, 0, sizeof(int) * B, s));
     BXS_HIPB(hipGetLastError());
     const double one = 1.0, zero = 0.0, mone = -1.0;
     const double tol = o->eps_gap > 0.0 ? o->eps_gap : 1e-12;
     const long maxit = o->max_iter;
     int* hflag = nullptr;
-    BXS_HIPB(hipHostMalloc((void**)&hflag, sizeof(int), hipHostMallocDefault));
+    BXS_HIPB(hipHostMalloc((void**)&hflag, 2 * sizeof(int), hipHostMallocDefault));
     struct HG { int* p; ~HG() { (void)hipHostFree(p); } } hg{hflag};
+    hflag[0] = 1;
+    hflag[1] = 0;
     long it = 0;
     for (; it < maxit; ++it) {
         // S = mask(A^T (A P))
@@ -880,16 +930,16 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
                                A64, (int)m, Q, (int)m, &zero, S, (int)n));
         k_adj_mask<<<grid, 256, 0, s>>>(S, F, (long long)n * B);
         k_adj_dot<<<(int)B, 256, 0, s>>>(P, S, (int)n, pq);
-        k_adj_step<<<grid, 256, 0, s>>>(S, F, rs, pq, V, Rc, P, (int)n, (int)B);
+        k_adj_step<<<grid, 256, 0, s>>>(S, F, rs, pq, done, V, Rc, P, (int)n, (int)B);
         k_adj_dot<<<(int)B, 256, 0, s>>>(Rc, Rc, (int)n, rsn);
-        k_adj_dir<<<grid, 256, 0, s>>>(P, Rc, rsn, rs, (int)n, (int)B);
-        k_b_copy<<<64, 256, 0, s>>>(rsn, rs, B);
+        k_adj_dir<<<grid, 256, 0, s>>>(P, Rc, rsn, rs, done, (int)n, (int)B);
+        k_adj_track<<<(int)((B + 255) / 256), 256, 0, s>>>(rs, rsn, rs0, pq, done, (int)B, tol * tol);
         if ((it % 8) == 7 || it + 1 == maxit) {
-            BXS_HIPB(hipMemsetAsync(notconv, 0, sizeof(int), s));
-            k_adj_conv<<<16, 256, 0, s>>>(rs, rs0, (int)B, tol * tol, notconv);
-            BXS_HIPB(hipMemcpyAsync(hflag, notconv, sizeof(int), hipMemcpyDeviceToHost, s));
+            BXS_HIPB(hipMemsetAsync(counters, 0, 2 * sizeof(int), s));
+            k_adj_count<<<16, 256, 0, s>>>(done, (int)B, counters);
+            BXS_HIPB(hipMemcpyAsync(hflag, counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
             BXS_HIPB(hipStreamSynchronize(s));
-            if (*hflag == 0) { ++it; break; }
+            if (hflag[0] == hflag[1]) { ++it; break; }   // every column converged or broke down
         }
     }
     BXS_HIPB(hipGetLastError());
@@ -909,7 +959,8 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     }
     BXS_HIPB(hipStreamSynchronize(s));
     if (cg_iters) *cg_iters = it;
-    return (*hflag == 0) ? BXS_OK : BXS_MAXITER;
+    if (hflag[1] > 0) return BXS_SINGULAR;
+    return (hflag[0] == 0) ? BXS_OK : BXS_MAXITER;
 }
 
 }  // namespace bxs

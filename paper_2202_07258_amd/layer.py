@@ -14,13 +14,15 @@ from . import native
 
 class _NNLSLayer(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, A, Y, t, opts, adj_opts):
+    def forward(ctx, A, Y, t, opts, adj_opts, stats):
         Ac = A.detach().t().contiguous().t()            # column-major copy
         Y64 = Y.detach().to(torch.float64).t().contiguous().t()
         X, sat, infos = native.solve_nnls_batched_shared(Ac, Y64, t=t, **opts)
         ctx.save_for_backward(Ac, Y64, X)
         ctx.adj_opts = adj_opts
-        ctx.infos = infos
+        ctx.stats = stats
+        if stats is not None:
+            stats["forward"] = infos
         return X.to(Y.dtype)
 
     @staticmethod
@@ -29,23 +31,28 @@ class _NNLSLayer(torch.autograd.Function):
         need_dA = ctx.needs_input_grad[0]
         dY, dA, iters, status = native.nnls_adjoint(Ac, Y64, X, gX.to(torch.float64), need_dA=need_dA,
                                                     **ctx.adj_opts)
-        ctx.cg_iterations = iters
+        if ctx.stats is not None:
+            ctx.stats["cg_iters"] = iters
+            ctx.stats["cg_status"] = status
         gA = dA.to(Ac.dtype) if (need_dA and dA is not None) else None
         gY = dY.to(gX.dtype) if ctx.needs_input_grad[1] else None
-        return gA, gY, None, None, None
+        return gA, gY, None, None, None, None
 
 
 def nnls_layer(A: torch.Tensor, Y: torch.Tensor, t: torch.Tensor | None = None, *,
                eps_gap: float = 1e-8, max_iter: int = 100000, screen_every: int = 10,
                iter_precision: str = "f64", step: float = 0.0, cg_max_iter: int = 10000,
-               cg_tol: float = 1e-12) -> torch.Tensor:
+               cg_tol: float = 1e-12, stats: dict | None = None) -> torch.Tensor:
     """Non-negative least-squares layer on the GPU.
 
     A (m, n) float32/float64, Y (m, B): column b of the result solves
     min_{x >= 0} 1/2 ||A x - Y[:, b]||^2.  t (m,) float64 is the dual
     translation direction (default -1, valid for non-negative A; for a signed
-    A supply a direction with A^T t < 0)."""
+    A supply a direction with A^T t < 0).  If ``stats`` is a dict it receives
+    the per-column forward infos ("forward": status, certified gap, iterations)
+    and, after backward, the CG iteration count and status ("cg_iters",
+    "cg_status": "ok", "maxiter" or "singular")."""
     opts = dict(eps_gap=eps_gap, max_iter=max_iter, screen_every=screen_every, iter_precision=iter_precision,
                 step=step)
     adj = dict(max_iter=cg_max_iter, tol=cg_tol)
-    return _NNLSLayer.apply(A, Y, t, opts, adj)
+    return _NNLSLayer.apply(A, Y, t, opts, adj, stats)

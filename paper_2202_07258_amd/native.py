@@ -18,9 +18,10 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIBRARY_PATH = os.path.join(_PKG, "libboxscreen.so")
 
-BXS_OK, BXS_ERR_ARG, BXS_ERR_SHAPE, BXS_ERR_NONFINITE, BXS_ERR_BOUNDS, BXS_ERR_DEVICE, BXS_ERR_NOMEM, BXS_MAXITER = range(8)
+BXS_OK, BXS_ERR_ARG, BXS_ERR_SHAPE, BXS_ERR_NONFINITE, BXS_ERR_BOUNDS, BXS_ERR_DEVICE, BXS_ERR_NOMEM, BXS_MAXITER, \
+    BXS_SINGULAR = range(9)
 STATUS_NAMES = {0: "ok", 1: "err_arg", 2: "err_shape", 3: "err_nonfinite", 4: "err_bounds",
-                5: "err_device", 6: "err_nomem", 7: "maxiter"}
+                5: "err_device", 6: "err_nomem", 7: "maxiter", 8: "singular"}
 BXS_PG, BXS_CD = 0, 1
 BXS_F64, BXS_F32 = 0, 1
 MAX_ROWS = 16384
@@ -58,6 +59,7 @@ class Problem(C.Structure):
 EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls",
             "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
             "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant",
+            "bxs_sweep_variant_for_rows",
             "solve_nnls_batched_shared", "bxs_workspace_size_batched", "nnls_adjoint",
             "bxs_workspace_size_adjoint"]
 
@@ -94,7 +96,9 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     lib.bxs_version.restype = C.c_char_p
     lib.bxs_num_sweep_variants.argtypes = []
     lib.bxs_num_sweep_variants.restype = C.c_int
-    lib.bxs_sweep_variant_info.argtypes = [C.c_int] + [C.POINTER(C.c_int)] * 4 + [C.POINTER(C.c_long)]
+    lib.bxs_sweep_variant_info.argtypes = [C.c_int] + [C.POINTER(C.c_int)] * 5 + [C.POINTER(C.c_long)]
+    lib.bxs_sweep_variant_for_rows.argtypes = [C.c_long]
+    lib.bxs_sweep_variant_for_rows.restype = C.c_int
     lib.bxs_sweep_variant_info.restype = C.c_int
     lib.bxs_row_class.argtypes = [C.c_long]
     lib.bxs_row_class.restype = C.c_int
@@ -296,16 +300,20 @@ def sweep_variants() -> list[dict]:
     lib = load()
     out = []
     for v in range(lib.bxs_num_sweep_variants()):
-        a, b, c, d = (C.c_int() for _ in range(4))
+        a, b, c, d, e = (C.c_int() for _ in range(5))
         cap = C.c_long()
-        lib.bxs_sweep_variant_info(v, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(cap))
-        out.append({"id": v, "tpc": a.value, "ng": b.value, "rows": c.value, "cbi": d.value,
+        lib.bxs_sweep_variant_info(v, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(e), C.byref(cap))
+        out.append({"id": v, "tpc": a.value, "ng": b.value, "rows": c.value, "cbi": d.value, "pd": e.value,
                     "capacity": cap.value})
     return out
 
 
 def row_class(m: int) -> int:
     return load().bxs_row_class(int(m))
+
+
+def variant_for_rows(m: int) -> int:
+    return load().bxs_sweep_variant_for_rows(int(m))
 
 
 def set_sweep_variant(row_class_: int, variant: int) -> None:
@@ -377,6 +385,6 @@ def nnls_adjoint(A, Y, X, dX, *, max_iter=10000, tol=1e-12, need_dA=True, stream
     it = C.c_long(0)
     st = lib.nnls_adjoint(m, n, B, dt, A.data_ptr(), lda, Y64.data_ptr(), m, X64.data_ptr(), n, G64.data_ptr(), n,
                           dY.data_ptr(), m, dA.data_ptr() if dA is not None else None, m, C.byref(o), C.byref(it))
-    if st not in (BXS_OK, BXS_MAXITER):
+    if st not in (BXS_OK, BXS_MAXITER, BXS_SINGULAR):
         _raise(lib, st)
     return dY, dA, int(it.value), STATUS_NAMES[st]
