@@ -29,7 +29,8 @@ if ROOT not in sys.path:
 
 METRIC = "solves/sec to gap 1e-6 (screened vs unscreened), HBM GB/s % of peak"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pg_sweep_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pg_sweep_c2_traffic.md")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2202_07258_amd", "csrc", "kernels.hip")
 
 
 def log(*a):
@@ -65,7 +66,9 @@ def time_solves(dev_inputs, steps, warmup, **kw):
 def sweep_roofline(infos, m, elem_bytes):
     """Algorithmic bytes of one fused PG sweep launch: every preserved column
     once (m * elem_bytes), its x read and write, l, u and index (36 B), plus
-    the residual m-vector (8 m).  Duration: HIP events around each launch."""
+    the residual m-vector (8 m).  Duration: HIP events recorded on the solve's
+    stream around each launch, less the same events' elapsed time around an
+    empty kernel (dispatch latency)."""
     col_iters = sum(i["col_iters"] for i in infos)
     launches = sum(i["sweep_launches"] for i in infos)
     ms = sum(i["sweep_ms"] for i in infos)
@@ -73,21 +76,58 @@ def sweep_roofline(infos, m, elem_bytes):
         return None
     bytes_total = col_iters * (m * elem_bytes + 36) + launches * 8 * m
     per_launch = bytes_total / launches
-    avg_s = ms * 1e-3 / launches
+    avg_events = ms * 1e-3 / launches
+    # the event pair around a launch also spans its dispatch; the same pair
+    # around an empty kernel measures that part, which is taken off
+    overhead = max(i.get("event_overhead_ms", 0.0) for i in infos) * 1e-3
+    avg_s = avg_events - overhead if avg_events > 2 * overhead else avg_events
     achieved = per_launch / avg_s / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            with open(TRAFFIC_FILE) as f:
-                tr = json.load(f)
-            traffic = tr.get("bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
+    traffic = measured_traffic(sweep_kernel_name(m), m)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": sweep_kernel_name(m),
             "algorithmic_bytes_per_launch": int(per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
+            "avg_events_us": round(avg_events * 1e6, 2), "event_overhead_us": round(overhead * 1e6, 2),
             "launches": launches}
+
+
+def _source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, m):
+    """HBM bytes per launch of the sweep from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when the summary is missing or was taken on another version of
+    the kernel source, another kernel shape or another row count."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f.read().splitlines()
+                      if ":" in line and not line.startswith(("#", " ", "|", "`")))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        if kv.get("kernel_source_sha256") != _source_digest(SWEEP_SOURCE):
+            return None
+        if kv.get("kernel") != kernel or int(kv.get("rows", -1)) != m:
+            return None
+        return int(float(kv["bytes_per_launch"]))
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def copy_calibration(device):
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters (FETCH_SIZE / WRITE_SIZE) read on the sweep."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}
 
 
 def sweep_kernel_name(m):
@@ -134,6 +174,8 @@ def main():
     ap.add_argument("--c3-iters", type=int, default=200)
     ap.add_argument("--c4-count", type=int, default=2048)
     ap.add_argument("--c5-iters", type=int, default=20000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (for scaling rocprofv3 byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -153,6 +195,9 @@ def main():
     bx.load()
     device = "cuda:0"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration(device)), flush=True)
+        return
     if args.workload != "c2":
         import bench_workloads
         out = bench_workloads.run(args.workload, args, device)

@@ -180,6 +180,9 @@ def bench_c4(args, device):
                         "l": torch.zeros(n, dtype=torch.float64, device=device),
                         "u": torch.ones(n, dtype=torch.float64, device=device)}
     log(f"[c4] generated in {time.perf_counter() - t0:.1f}s")
+    classes = sorted({N.row_class(int(m)) for m in ms})
+    log(f"[c4] autotuning the sweep shapes of row classes {classes}")
+    tuned = bx.autotune.tune(device=device, classes=classes, iters=30, reps=1)
     kw = dict(screen_every=10, eps_gap=1e-6, max_iter=20000, profile=True)
     _sync()
     t0 = time.perf_counter()
@@ -199,7 +202,10 @@ def bench_c4(args, device):
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4) if achieved else None,
                          "traffic": None, "kernel": "k_sweep PG launches over all unfinished instances",
-                         "launch_groups": launches}}
+                         "launch_groups": launches},
+            "autotune": {"seconds": tuned["seconds"],
+                         "best": {int(c): r["best"] for c, r in tuned["classes"].items()},
+                         "previous": {int(c): r["previous"] for c, r in tuned["classes"].items()}}}
 
 
 # --------------------------------------------------------------------------
@@ -242,6 +248,7 @@ def bench_c5(args, device):
                      "converged": int(sum(i["status_name"] == "ok" for i in fw)), "batch": len(fw),
                      "gap_median": float(np.median(gaps)), "gap_max": float(gaps.max()),
                      "free_median": int(np.median(nfree)), "free_max": int(nfree.max()),
+                     "free_gt_m": int((nfree > A.shape[0]).sum()),
                      "cg_iters": stats.get("cg_iters"), "cg_status": stats.get("cg_status"),
                      "grad_A_norm": float(At.grad.norm()), "grad_Y_norm": float(Yt.grad.norm()),
                      "grads_finite": bool(torch.isfinite(At.grad).all() and torch.isfinite(Yt.grad).all())}

@@ -124,6 +124,9 @@ typedef struct {
                            launches (PG: fused A^T r / update / A x; CD: the sweep;
                            batched solver: the pair of iteration GEMMs)               */
     long   sweep_launches; /* opts->profile: number of timed sweep launches             */
+    double event_overhead_ms; /* opts->profile: average HIP-event elapsed time around an
+                           empty kernel on the same stream (dispatch latency included in
+                           every timed launch); measured once per process and device    */
 } bxs_info;
 
 /* Fill *opts with defaults: PG, screening on, K = 10, max_iter = 100000,
@@ -214,9 +217,11 @@ bxs_status bxs_workspace_size_batched(long m, long n, long B, const bxs_opts* op
  *   A [lda*n] (a_dtype)  Y [ldy*B]  X [ldx*B] (forward solution)
  *   dX [ldg*B] in   dY [lddy*B] out   dA [ldda*n] out or NULL
  *   cg_iters host out or NULL.  Each right-hand side runs CG until its
- *   residual is below the tolerance or p^T A_F^T A_F p <= 0 (A_F rank
- *   deficient, e.g. more free coordinates than rows: the forward solution is
- *   not an isolated optimum there); such a column keeps its last CG iterate.
+ *   residual is below the tolerance, or until it breaks down: p^T A_F^T A_F p
+ *   at or below the rounding level 2 gamma_{m+2} ||p||^2 ||A||_F^2 of its
+ *   FP64 evaluation (A_F rank deficient, e.g. more free coordinates than
+ *   rows, so the forward solution is not an isolated optimum).  The
+ *   columns of dY and the terms of dA of a broken-down right-hand side are 0.
  *   Returns BXS_OK; BXS_SINGULAR if at least one column broke down;
  *   BXS_MAXITER if CG did not reach the tolerance for every right-hand side;
  *   or an error code (outputs unset). */

@@ -10,3 +10,4 @@ from .native import (  # noqa: F401
     nnls_adjoint, version, LIBRARY_PATH, EXPORTED, MAX_ROWS,
 )
 from .layer import nnls_layer  # noqa: F401
+from . import autotune  # noqa: F401

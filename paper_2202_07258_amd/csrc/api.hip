@@ -57,6 +57,45 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Dispatch overhead seen by a pair of HIP events around one launch: the
+// average elapsed time around an empty kernel on the caller's stream, taken
+// once per process and device (profile mode only).
+__global__ void k_noop() {}
+
+static double g_event_overhead_ms[64];
+static bool g_event_overhead_done[64];
+
+bxs_status event_overhead(hipStream_t s, double* out)
+{
+    int dev = 0;
+    BXS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) { *out = 0.0; return BXS_OK; }
+    if (!g_event_overhead_done[dev]) {
+        constexpr int kReps = 32;
+        hipEvent_t e[2 * kReps];
+        for (auto& x : e) BXS_HIP(hipEventCreate(&x));
+        struct G { hipEvent_t* e; ~G() { for (int i = 0; i < 2 * kReps; ++i) (void)hipEventDestroy(e[i]); } } g{e};
+        k_noop<<<1, 64, 0, s>>>();                       // warm-up
+        for (int i = 0; i < kReps; ++i) {
+            BXS_HIP(hipEventRecord(e[2 * i], s));
+            k_noop<<<1, 64, 0, s>>>();
+            BXS_HIP(hipEventRecord(e[2 * i + 1], s));
+        }
+        BXS_HIP(hipGetLastError());
+        BXS_HIP(hipEventSynchronize(e[2 * kReps - 1]));
+        double tot = 0.0;
+        for (int i = 0; i < kReps; ++i) {
+            float ms = 0.f;
+            BXS_HIP(hipEventElapsedTime(&ms, e[2 * i], e[2 * i + 1]));
+            tot += ms;
+        }
+        g_event_overhead_ms[dev] = tot / kReps;
+        g_event_overhead_done[dev] = true;
+    }
+    *out = g_event_overhead_ms[dev];
+    return BXS_OK;
+}
+
 struct InstSpec {
     long m, n, lda;
     const void* A;
@@ -362,6 +401,11 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         hipEvent_t a, b, c;
         ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); }
     } eg{ev0, ev1, ev2};
+    double ev_over = 0.0;
+    if (o->profile) {
+        bxs_status es = event_overhead(stream, &ev_over);
+        if (es != BXS_OK) return es;
+    }
     BXS_HIP(hipEventRecord(ev0, stream));
 
     // ---- setup ----
@@ -524,6 +568,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             f.col_iters = S.col_iters;
             f.sweep_ms = sweep_ms;
             f.sweep_launches = sweep_launches;
+            f.event_overhead_ms = ev_over;
         }
     }
     if (history && count == 1) {

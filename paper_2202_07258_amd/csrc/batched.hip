@@ -36,6 +36,7 @@
 namespace bxs {
 
 bxs_status set_error(bxs_status s, const char* msg);   // api.hip
+bxs_status event_overhead(hipStream_t s, double* out); // api.hip
 
 typedef __attribute__((ext_vector_type(4))) float f4;
 typedef __attribute__((ext_vector_type(4))) short s4;
@@ -65,108 +66,202 @@ __device__ __forceinline__ void split_bf16(float v, short& hi, short& lo) {
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3 MFMA GEMM on the active right-hand sides.  Output tile 64 x 64 per
-// workgroup (4 waves, 32 x 32 each = 2 x 2 MFMA 16x16 blocks), K step 32.
-//  EPI 0:  U[:, act[c]]  = (A D[:, act])[:, c]        (M = m, K = n)
-//  EPI 1:  G[:, act[c]] -= (A^T U[:, act])[:, c]      (M = n, K = m)
-// A is column-major m x n; act lists the active right-hand sides.
+// BF16x3 MFMA GEMM on the active right-hand sides (gfx950,
+// v_mfma_f32_16x16x32_bf16).  Both products of an iteration have the form
+//     C[M x ncols] = Aop[M x K] * Bop[K x ncols]
+// with Aop row-major (K contiguous, rows and K zero-padded to multiples of
+// 128) and every column of Bop K-contiguous; each operand comes as a bf16 hi
+// part and a bf16 lo part, and the three leading partial products
+// lo*hi + hi*lo + hi*hi are accumulated in FP32.
+//  EPI 0:  U = A D            (Aop = A row-major copy, Bop = D, M = m, K = n);
+//          U is written as its bf16 hi/lo split for the next product.
+//  EPI 1:  G -= A^T U         (Aop = A column-major copy, Bop = U, M = n,
+//          K = m), then the projected step on the same tile:
+//          x <- max(0, x + eta g) in FP64 (0 where screened), D = x_new - x
+//          written as its bf16 hi/lo split.
+// Workgroup tile 128 x 128, K step 32, 4 waves of 64 x 64 (4 x 4 MFMA
+// blocks); the next K step is loaded into registers while the current one is
+// multiplied out of LDS.  Consecutive workgroup ids go round-robin over the
+// 8 XCDs, so the tile order is permuted to give each XCD a contiguous block
+// of column tiles (each Bop column panel is then read by one XCD's L2).
 // ---------------------------------------------------------------------------
+typedef unsigned short u16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf8v;
+
+constexpr int kG3M = 128, kG3N = 128, kG3K = 32, kG3Ld = 40;   // LDS row: 32 bf16 + 16 B pad
+
+struct G3Args {
+    const u16* Ahi; const u16* Alo; long long lda;     // Aop, lda = padded K
+    int tiles_m, tiles_n, K;                            // K = padded K (multiple of 32)
+    const int* act; int nact;                           // active right-hand sides
+    const u16* Bhi; const u16* Blo; long long ldb;     // Bop column b at b * ldb
+    u16* Ohi; u16* Olo; long long ldo;                 // EPI 0 output split (U), EPI 1: D
+    float* G; double* X; const signed char* sat; long long ldsat;   // EPI 1 (n x B, ld n)
+    int n; double eta;
+};
+
+__device__ __forceinline__ unsigned pack2(u16 a, u16 b) { return (unsigned)a | ((unsigned)b << 16); }
+
 template <int EPI>
 __global__ __launch_bounds__(256)
-void k_gemm_bf16x3(const float* __restrict__ A, long long lda, int m, int n,
-                   const int* __restrict__ act, const int* __restrict__ nact_ptr,
-                   const float* __restrict__ Bsrc, long long ldb,
-                   float* __restrict__ Out, long long ldo)
+void k_gemm3(G3Args p)
 {
-    const int M = (EPI == 0) ? m : n;
-    const int K = (EPI == 0) ? n : m;
-    const int nact = *nact_ptr;
-    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
-    if (col0 >= nact || row0 >= M) return;
-    __shared__ float As[64][33];   // [row][k]
-    __shared__ float Bs[32][65];   // [k][col]
-    __shared__ int s_act[64];
+    // LDS: the two K-step operand tiles, reused by the epilogue for one half
+    // (64 columns) of the FP32 result tile at a time
+    constexpr int kOpBytes = 2 * (kG3M + kG3N) * kG3Ld * (int)sizeof(u16);
+    constexpr int kCLd = kG3M + 4;
+    constexpr int kCBytes = 64 * kCLd * (int)sizeof(float);
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes > kCBytes ? kOpBytes : kCBytes];
+    u16 (*sA)[kG3M * kG3Ld] = (u16 (*)[kG3M * kG3Ld])smem;
+    u16 (*sB)[kG3N * kG3Ld] = (u16 (*)[kG3N * kG3Ld])(smem + 2 * kG3M * kG3Ld * sizeof(u16));
+    float* sC = (float*)smem;
+    __shared__ int s_act[kG3N];
+    const int tiles = p.tiles_m * p.tiles_n;
+    const int id = blockIdx.x;
+    const int t = (tiles % 8 == 0) ? (id % 8) * (tiles / 8) + id / 8 : id;
+    const int row0 = (t % p.tiles_m) * kG3M, col0 = (t / p.tiles_m) * kG3N;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    if (tid < 64) s_act[tid] = (col0 + tid < nact) ? act[col0 + tid] : -1;
+    if (tid < kG3N) s_act[tid] = (col0 + tid < p.nact) ? p.act[col0 + tid] : -1;
     __syncthreads();
-    f4 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    // global -> register slots: 2 x 16 B of each of Ahi, Alo, Bhi, Blo per
+    // thread.  Columns past the active count read column 0 of Bop: each
+    // output column depends on its own Bop column only, and those outputs
+    // are never stored.
+    const int kq = 8 * (tid & 3);
+    const int r0 = tid >> 2, r1 = r0 + 64;
+    const int srow0 = r0 * kG3Ld + kq, srow1 = r1 * kG3Ld + kq;
+    const u16* pa0h = p.Ahi + (long long)(row0 + r0) * p.lda + kq;
+    const u16* pa1h = p.Ahi + (long long)(row0 + r1) * p.lda + kq;
+    const u16* pa0l = p.Alo + (long long)(row0 + r0) * p.lda + kq;
+    const u16* pa1l = p.Alo + (long long)(row0 + r1) * p.lda + kq;
+    const long long bo0 = (long long)max(s_act[r0], 0) * p.ldb + kq;
+    const long long bo1 = (long long)max(s_act[r1], 0) * p.ldb + kq;
+    const u16* pb0h = p.Bhi + bo0;
+    const u16* pb1h = p.Bhi + bo1;
+    const u16* pb0l = p.Blo + bo0;
+    const u16* pb1l = p.Blo + bo1;
+    uint4 ga0h = *(const uint4*)pa0h, ga1h = *(const uint4*)pa1h;
+    uint4 ga0l = *(const uint4*)pa0l, ga1l = *(const uint4*)pa1l;
+    uint4 gb0h = *(const uint4*)pb0h, gb1h = *(const uint4*)pb1h;
+    uint4 gb0l = *(const uint4*)pb0l, gb1l = *(const uint4*)pb1l;
+
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lk = 8 * (lane >> 4);
+    f4 acc[4][4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid + e * 256;
-            int r, kk;
-            if (EPI == 0) { r = idx & 63; kk = idx >> 6; }     // A[row + k*lda]: contiguous rows
-            else { r = idx >> 5; kk = idx & 31; }              // A^T: A[k + row*lda]: contiguous k
-            const int gr = row0 + r, gk = k0 + kk;
-            float v = 0.f;
-            if (gr < M && gk < K) v = (EPI == 0) ? A[gr + (long long)gk * lda] : A[gk + (long long)gr * lda];
-            As[r][kk] = v;
-        }
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid + e * 256;
-            const int kk = idx & 31, c = idx >> 5;
-            const int gk = k0 + kk, b = s_act[c];
-            Bs[kk][c] = (b >= 0 && gk < K) ? Bsrc[gk + (long long)b * ldb] : 0.f;
-        }
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < p.K; k0 += kG3K) {
+        __syncthreads();                      // every wave is done with the previous K step
+        *(uint4*)&sA[0][srow0] = ga0h;
+        *(uint4*)&sA[0][srow1] = ga1h;
+        *(uint4*)&sA[1][srow0] = ga0l;
+        *(uint4*)&sA[1][srow1] = ga1l;
+        *(uint4*)&sB[0][srow0] = gb0h;
+        *(uint4*)&sB[0][srow1] = gb1h;
+        *(uint4*)&sB[1][srow0] = gb0l;
+        *(uint4*)&sB[1][srow1] = gb1l;
         __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const int kb = ks * 16 + 4 * (lane >> 4);
-            s4 ahi[2], alo[2], bhi[2], blo[2];
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                const int row = wr * 32 + rb * 16 + (lane & 15);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    short h, l;
-                    split_bf16(As[row][kb + v], h, l);
-                    ahi[rb][v] = h;
-                    alo[rb][v] = l;
-                }
-            }
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                const int col = wc * 32 + cb * 16 + (lane & 15);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    short h, l;
-                    split_bf16(Bs[kb + v][col], h, l);
-                    bhi[cb][v] = h;
-                    blo[cb][v] = l;
-                }
-            }
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[rb], bhi[cb], acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rb], blo[cb], acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rb], bhi[cb], acc[rb][cb], 0, 0, 0);
-                }
+        const int kn = k0 + kG3K;
+        if (kn < p.K) {                       // next K step in flight during the MFMAs
+            ga0h = *(const uint4*)(pa0h + kn); ga1h = *(const uint4*)(pa1h + kn);
+            ga0l = *(const uint4*)(pa0l + kn); ga1l = *(const uint4*)(pa1l + kn);
+            gb0h = *(const uint4*)(pb0h + kn); gb1h = *(const uint4*)(pb1h + kn);
+            gb0l = *(const uint4*)(pb0l + kn); gb1l = *(const uint4*)(pb1l + kn);
         }
-        __syncthreads();
+        bf8v ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ra_ = (wr * 64 + q * 16 + lr) * kG3Ld + lk;
+            const int rb_ = (wc * 64 + q * 16 + lr) * kG3Ld + lk;
+            ah[q] = *(const bf8v*)&sA[0][ra_];
+            al[q] = *(const bf8v*)&sA[1][ra_];
+            bh[q] = *(const bf8v*)&sB[0][rb_];
+            bl[q] = *(const bf8v*)&sB[1][rb_];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+            }
     }
+
+    // Epilogue, one half of the columns at a time: the waves owning those
+    // columns put their accumulators into LDS (column-major, a lane holds rows
+    // r..r+3 of one column of each 16 x 16 block), then all 256 threads walk
+    // the columns with consecutive lanes on consecutive rows.
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();                      // LDS free (operand tiles or previous half)
+        if (wc == h) {
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+            for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = row0 + wr * 32 + rb * 16 + 4 * (lane >> 4) + v;
-                const int c = wc * 32 + cb * 16 + (lane & 15);
-                const int b = s_act[c];
-                if (row >= M || b < 0) continue;
-                const float val = acc[rb][cb][v];
-                if (EPI == 0) Out[row + (long long)b * ldo] = val;
-                else Out[row + (long long)b * ldo] -= val;
+                for (int a = 0; a < 4; ++a)
+                    *(f4*)&sC[(cb * 16 + lr) * kCLd + wr * 64 + a * 16 + 4 * (lane >> 4)] = acc[a][cb];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < 64 * kG3M; idx += 256) {
+            const int cl = idx / kG3M, rl = idx % kG3M;
+            const int b = s_act[h * 64 + cl];
+            if (b < 0) break;                 // inactive columns are the last ones of the tile
+            const int j = row0 + rl;
+            const float val = sC[cl * kCLd + rl];
+            if (EPI == 0) {
+                short hh, ll;
+                split_bf16(val, hh, ll);
+                p.Ohi[(long long)b * p.ldo + j] = (u16)hh;
+                p.Olo[(long long)b * p.ldo + j] = (u16)ll;
+            } else if (j < p.n) {
+                const long long e = j + (long long)b * p.n;
+                const float g = p.G[e] - val;
+                p.G[e] = g;
+                const double xo = p.X[e];
+                const double xn = (p.sat[j + (long long)b * p.ldsat] != 0) ? 0.0 : fmax(0.0, xo + p.eta * (double)g);
+                p.X[e] = xn;
+                short hh, ll;
+                split_bf16((float)(xn - xo), hh, ll);
+                p.Ohi[(long long)b * p.ldo + j] = (u16)hh;
+                p.Olo[(long long)b * p.ldo + j] = (u16)ll;
             }
+        }
+    }
+}
+
+// bf16 hi/lo splits of the FP32 matrix in both K-contiguous layouts:
+//   AR (row-major, mpad x npad): AR[i * npad + j] = A[i, j]
+//   AC (column-major, npad x mpad): AC[j * mpad + i] = A[i, j]
+// zero outside m x n.  32 x 32 tiles through LDS for the transposed write.
+__global__ __launch_bounds__(256)
+void k_b_split_a(const float* __restrict__ A, long long lda, int m, int n, int mpad, int npad,
+                 u16* __restrict__ ARh, u16* __restrict__ ARl, u16* __restrict__ ACh, u16* __restrict__ ACl)
+{
+    __shared__ float tile[32][33];
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int jj = ty; jj < 32; jj += 8) {
+        const int i = i0 + tx, j = j0 + jj;
+        const float v = (i < m && j < n) ? A[i + (long long)j * lda] : 0.f;
+        tile[jj][tx] = v;
+        short h, l;
+        split_bf16(v, h, l);
+        ACh[(long long)j * mpad + i] = (u16)h;
+        ACl[(long long)j * mpad + i] = (u16)l;
+    }
+    __syncthreads();
+    for (int ii = ty; ii < 32; ii += 8) {
+        const int i = i0 + ii, j = j0 + tx;
+        short h, l;
+        split_bf16(tile[tx][ii], h, l);
+        ARh[(long long)i * npad + j] = (u16)h;
+        ARl[(long long)i * npad + j] = (u16)l;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -268,10 +363,13 @@ __global__ void k_b_update64(double* __restrict__ X64, const double* __restrict_
 
 // projected step of the BF16x3 engine on the active right-hand sides.  The
 // iterate stays in FP64 (an FP32 iterate stalls once eta g drops below half
-// an ulp of x); the increment D = x_new - x feeds the GEMMs in FP32.
-__global__ void k_b_step_mixed(double* __restrict__ X64, float* __restrict__ D32, const float* __restrict__ G32,
-                               int n, const int* __restrict__ act, const int* __restrict__ nact_ptr,
-                               const signed char* __restrict__ sat, long long ldsat, double eta)
+// an ulp of x); the increment D = x_new - x feeds the GEMMs as its bf16 hi/lo
+// split.  This kernel takes the first step of a pass, from the exact
+// gradient; the later steps are fused into the epilogue of k_gemm3<1>.
+__global__ void k_b_step_split(double* __restrict__ X64, const float* __restrict__ G32, int n,
+                               const int* __restrict__ act, const int* __restrict__ nact_ptr,
+                               const signed char* __restrict__ sat, long long ldsat, double eta,
+                               u16* __restrict__ Dhi, u16* __restrict__ Dlo, long long ldd)
 {
     const long long tot = (long long)n * (*nact_ptr);
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
@@ -281,7 +379,10 @@ __global__ void k_b_step_mixed(double* __restrict__ X64, float* __restrict__ D32
         const double xo = X64[e];
         const double xn = (sat[j + b * ldsat] != 0) ? 0.0 : fmax(0.0, xo + eta * (double)G32[e]);
         X64[e] = xn;
-        D32[e] = (float)(xn - xo);
+        short h, l;
+        split_bf16((float)(xn - xo), h, l);
+        Dhi[j + b * ldd] = (u16)h;
+        Dlo[j + b * ldd] = (u16)l;
     }
 }
 
@@ -527,6 +628,7 @@ static bxs_status blas_handle(hipStream_t s, rocblas_handle* out)
     } while (0)
 
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
+static size_t pad128(long v) { return (size_t)((v + 127) / 128 * 128); }
 
 size_t batched_workspace_bytes(long m, long n, long B, int iter_precision)
 {
@@ -538,8 +640,10 @@ size_t batched_workspace_bytes(long m, long n, long B, int iter_precision)
     b += al(sizeof(double) * n * B);          // G64
     b += al(sizeof(double) * m * B);          // Y64
     if (iter_precision == 1) {
-        b += al(sizeof(float) * n * B);       // D32 (step)
-        b += al(sizeof(float) * m * B);       // U32 = A D
+        const size_t mp = pad128(m), np = pad128(n);
+        b += al(sizeof(u16) * mp * np) * 4;   // bf16 hi/lo splits of A, row- and column-major
+        b += al(sizeof(u16) * np * B) * 2;    // D hi/lo (step increment)
+        b += al(sizeof(u16) * mp * B) * 2;    // U hi/lo = A D
         b += al(sizeof(float) * n * B);       // G32
     }
     b += al(sizeof(double) * (4 * (size_t)n + m + 16));   // cn, w, power vectors, scalars
@@ -572,10 +676,19 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     double* R64 = (double*)take(sizeof(double) * m * B);
     double* G64 = (double*)take(sizeof(double) * n * B);
     double* Y64 = (double*)take(sizeof(double) * m * B);
-    float *X32 = nullptr, *D32 = nullptr, *U32 = nullptr, *G32 = nullptr, *Y32 = nullptr;
+    float *X32 = nullptr, *G32 = nullptr, *Y32 = nullptr;
+    const long mp = (long)pad128(m), np = (long)pad128(n);
+    u16 *ARh = nullptr, *ARl = nullptr, *ACh = nullptr, *ACl = nullptr;
+    u16 *Dh = nullptr, *Dl = nullptr, *Uh = nullptr, *Ul = nullptr;
     if (prec == 1) {
-        D32 = (float*)take(sizeof(float) * n * B);
-        U32 = (float*)take(sizeof(float) * m * B);
+        ARh = (u16*)take(sizeof(u16) * mp * np);
+        ARl = (u16*)take(sizeof(u16) * mp * np);
+        ACh = (u16*)take(sizeof(u16) * mp * np);
+        ACl = (u16*)take(sizeof(u16) * mp * np);
+        Dh = (u16*)take(sizeof(u16) * np * B);
+        Dl = (u16*)take(sizeof(u16) * np * B);
+        Uh = (u16*)take(sizeof(u16) * mp * B);
+        Ul = (u16*)take(sizeof(u16) * mp * B);
         G32 = (float*)take(sizeof(float) * n * B);
     }
     double* sc = (double*)take(sizeof(double) * (4 * (size_t)n + m + 16));
@@ -601,6 +714,11 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     BXS_HIPB(hipEventCreate(&e1));
     BXS_HIPB(hipEventCreate(&e2));
     struct EG { hipEvent_t a, b, c; ~EG() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); } } eg{e0, e1, e2};
+    double ev_over = 0.0;
+    if (o->profile) {
+        bxs_status bs_ev = event_overhead(s, &ev_over);
+        if (bs_ev != BXS_OK) return bs_ev;
+    }
     BXS_HIPB(hipEventRecord(e0, s));
 
     BXS_HIPB(hipMemsetAsync(st, 0, sizeof(BState) * B, s));
@@ -614,6 +732,12 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     k_b_init<<<grid, 256, 0, s>>>(Y, ldy, X, ldx, (int)m, (int)n, (int)B, X64, X32, Y64, Y32, sat, ldsat, err);
     k_b_colstats<<<(int)((n + 3) / 4), 256, 0, s>>>(A64, (int)m, (int)n, o->t, cn, w, scal, err);
     k_b_iota<<<64, 256, 0, s>>>(act, (int)B, nact);
+    if (prec == 1) {
+        dim3 gs((unsigned)(mp / 32), (unsigned)(np / 32));
+        k_b_split_a<<<gs, 256, 0, s>>>(A32, lda32, (int)m, (int)n, (int)mp, (int)np, ARh, ARl, ACh, ACl);
+        BXS_HIPB(hipMemsetAsync(Dh, 0, sizeof(u16) * np * B, s));
+        BXS_HIPB(hipMemsetAsync(Dl, 0, sizeof(u16) * np * B, s));
+    }
     BXS_HIPB(hipGetLastError());
 
     // step: power iteration on A^T A with FP64 GEMVs (unless given)
@@ -653,7 +777,8 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
         k_b_g64_to_32<<<grid, 256, 0, s>>>(G64, G32, (int)n, act, nact);
     }
     int* hdone = nullptr;
-    BXS_HIPB(hipHostMalloc((void**)&hdone, sizeof(int), hipHostMallocDefault));
+    BXS_HIPB(hipHostMalloc((void**)&hdone, 2 * sizeof(int), hipHostMallocDefault));
+    int hnact = (int)B;
     struct HG { int* p; ~HG() { (void)hipHostFree(p); } } hg{hdone};
     const int K = o->screen_every;
     long long iters = 0;
@@ -668,16 +793,27 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     long gemm_pairs = 0;
     while (true) {
         const long long kk = std::min<long long>(K, o->max_iter - iters);
-        for (long long k = 0; k < kk; ++k) {
-            if (prec == 1) {
-                k_b_step_mixed<<<grid, 256, 0, s>>>(X64, D32, G32, (int)n, act, nact, sat, ldsat, eta);
+        if (prec == 1) {
+            // step 1 from the exact gradient, then kk-1 x [U = A D; G -= A^T U and step]
+            if (kk > 0)
+                k_b_step_split<<<grid, 256, 0, s>>>(X64, G32, (int)n, act, nact, sat, ldsat, eta, Dh, Dl, np);
+            G3Args g0{};
+            g0.Ahi = ARh; g0.Alo = ARl; g0.lda = np; g0.tiles_m = (int)(mp / kG3M);
+            g0.tiles_n = (hnact + kG3N - 1) / kG3N; g0.K = (int)np; g0.act = act; g0.nact = hnact;
+            g0.Bhi = Dh; g0.Blo = Dl; g0.ldb = np; g0.Ohi = Uh; g0.Olo = Ul; g0.ldo = mp;
+            G3Args g1{};
+            g1.Ahi = ACh; g1.Alo = ACl; g1.lda = mp; g1.tiles_m = (int)(np / kG3M);
+            g1.tiles_n = g0.tiles_n; g1.K = (int)mp; g1.act = act; g1.nact = hnact;
+            g1.Bhi = Uh; g1.Blo = Ul; g1.ldb = mp; g1.Ohi = Dh; g1.Olo = Dl; g1.ldo = np;
+            g1.G = G32; g1.X = X64; g1.sat = sat; g1.ldsat = ldsat; g1.n = (int)n; g1.eta = eta;
+            for (long long k = 1; k < kk && hnact > 0; ++k) {
                 if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k], s));
-                dim3 g0((unsigned)((m + 63) / 64), (unsigned)((B + 63) / 64));
-                k_gemm_bf16x3<0><<<g0, 256, 0, s>>>(A32, lda32, (int)m, (int)n, act, nact, D32, n, U32, m);
-                dim3 g1((unsigned)((n + 63) / 64), (unsigned)((B + 63) / 64));
-                k_gemm_bf16x3<1><<<g1, 256, 0, s>>>(A32, lda32, (int)m, (int)n, act, nact, U32, m, G32, n);
+                k_gemm3<0><<<g0.tiles_m * g0.tiles_n, 256, 0, s>>>(g0);
+                k_gemm3<1><<<g1.tiles_m * g1.tiles_n, 256, 0, s>>>(g1);
                 if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k + 1], s));
-            } else {
+            }
+        } else {
+            for (long long k = 0; k < kk; ++k) {
                 if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k], s));
                 bs = residual_and_corr();
                 if (bs != BXS_OK) return bs;
@@ -695,17 +831,18 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
         // the next pass of the BF16x3 engine restarts from the exact gradient
         if (prec == 1) k_b_g64_to_32<<<grid, 256, 0, s>>>(G64, G32, (int)n, act, nact);
         BXS_HIPB(hipGetLastError());
-        BXS_HIPB(hipMemcpyAsync(hdone, done_counter, sizeof(int), hipMemcpyDeviceToHost, s));
+        BXS_HIPB(hipMemcpyAsync(hdone, nact, 2 * sizeof(int), hipMemcpyDeviceToHost, s));   // nact, done count
         BXS_HIPB(hipStreamSynchronize(s));
+        hnact = hdone[0];
         if (o->profile) {
-            for (long long k = 0; k < kk; ++k) {
+            for (long long k = (prec == 1) ? 1 : 0; k < kk; ++k) {
                 float ms = 0.f;
                 BXS_HIPB(hipEventElapsedTime(&ms, pev[2 * k], pev[2 * k + 1]));
                 gemm_ms += ms;
                 ++gemm_pairs;
             }
         }
-        if (*hdone >= B || final_pass) break;
+        if (hdone[1] >= B || final_pass) break;
     }
     k_b_output<<<grid, 256, 0, s>>>(X64, X, ldx, (int)n, (int)B);
     BXS_HIPB(hipEventRecord(e2, s));
@@ -731,6 +868,7 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
             f.col_iters = S.col_iters;
             f.sweep_ms = gemm_ms;
             f.sweep_launches = gemm_pairs;
+            f.event_overhead_ms = ev_over;
         }
     }
     return worst;
@@ -780,17 +918,62 @@ void k_adj_dot(const double* __restrict__ U, const double* __restrict__ W, int n
     if (threadIdx.x == 0) out[b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
+// p^T S and p^T p per right-hand side
+__global__ __launch_bounds__(256)
+void k_adj_dot2(const double* __restrict__ P, const double* __restrict__ S, int n, double* __restrict__ pq,
+                double* __restrict__ pp)
+{
+    __shared__ double sh[2][4];
+    const long long b = blockIdx.x;
+    double s = 0.0, q = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const double v = P[j + b * n];
+        s = fma(v, S[j + b * n], s);
+        q = fma(v, v, q);
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        q += __shfl_xor(q, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = s; sh[1][threadIdx.x >> 6] = q; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pq[b] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+        pp[b] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    }
+}
+
+// sum of squares of the m x n matrix (an upper bound of the largest
+// eigenvalue of every masked normal matrix A_F^T A_F); one workgroup
+__global__ __launch_bounds__(1024)
+void k_adj_frob(const double* __restrict__ A, long long count, double* __restrict__ out)
+{
+    __shared__ double sh[16];
+    double s = 0.0;
+    for (long long k = threadIdx.x; k < count; k += 1024) s = fma(A[k], A[k], s);
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += sh[w];
+        *out = t;
+    }
+}
+
 // S <- mask(S); alpha = rs / (p.S); V += alpha P; Rc -= alpha S.  A column
-// whose flag is set (converged, or p^T S <= 0: the masked normal matrix is
-// singular along p) is frozen.
+// whose flag is set (converged or broken down) is frozen, and so is one whose
+// p^T S is at the rounding level (it is flagged by k_adj_track next).
 __global__ void k_adj_step(double* __restrict__ S, const signed char* __restrict__ F, const double* __restrict__ rs,
-                           const double* __restrict__ pq, const int* __restrict__ done, double* __restrict__ V,
+                           const double* __restrict__ pq, const double* __restrict__ pp, const double* __restrict__ frob,
+                           int m, const int* __restrict__ done, double* __restrict__ V,
                            double* __restrict__ Rc, const double* __restrict__ P, int n, int B)
 {
+    const double floor_ = 2.0 * gamma_k((double)m + 2.0) * (*frob);
     const long long tot = (long long)n * B;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
         const long long b = k / n;
-        if (done[b] || !(pq[b] > 0.0)) continue;
+        if (done[b] || !(pq[b] > floor_ * pp[b])) continue;
         const double alpha = rs[b] / pq[b];
         const double sv = F[k] ? S[k] : 0.0;
         V[k] += alpha * P[k];
@@ -818,18 +1001,30 @@ __global__ void k_adj_dir(double* __restrict__ P, const double* __restrict__ Rc,
 }
 
 // Per column bookkeeping after a CG step: rs <- rs_new; a column is done when
-// its residual fell below tol^2 * rs0 (done = 1) or when p^T A_F^T A_F p <= 0
-// or a non-finite value appeared (done = 2, breakdown).
+// its residual fell below tol^2 * rs0 (done = 1), or broke down (done = 2):
+// p^T A_F^T A_F p at or below the rounding level of its FP64 evaluation,
+// taken as 2 gamma_m |p|^2 ||A||_F^2 (A_F rank deficient along p), or a
+// non-finite value.
 __global__ void k_adj_track(double* __restrict__ rs, const double* __restrict__ rsn, const double* __restrict__ rs0,
-                            const double* __restrict__ pq, int* __restrict__ done, int B, double tol2)
+                            const double* __restrict__ pq, const double* __restrict__ pp, const double* __restrict__ frob,
+                            int m, int* __restrict__ done, int B, double tol2)
 {
+    const double floor_ = 2.0 * gamma_k((double)m + 2.0) * (*frob);
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
         if (done[b]) continue;
         const double r = rsn[b];
-        if (!(pq[b] > 0.0) || !isfinite(r)) { done[b] = 2; continue; }
+        if (!(pq[b] > floor_ * pp[b]) || !isfinite(r)) { done[b] = 2; continue; }
         rs[b] = r;
         if (r <= tol2 * rs0[b]) done[b] = 1;
     }
+}
+
+// the gradient of a broken-down column is set to 0 (no valid solve)
+__global__ void k_adj_zero_broken(double* __restrict__ V, const int* __restrict__ done, int n, int B)
+{
+    const long long tot = (long long)n * B;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x)
+        if (done[k / n] == 2) V[k] = 0.0;
 }
 
 // counters[0] = columns not converged, counters[1] = breakdowns
@@ -860,7 +1055,8 @@ size_t adjoint_workspace_bytes(long m, long n, long B)
     b += al(sizeof(double) * n * B) * 5;   // X, V, Rc, P, S
     b += al(sizeof(double) * m * B) * 2;   // Q, R
     b += al(sizeof(signed char) * n * B);  // F
-    b += al(sizeof(double) * B) * 4;       // rs, rs0, pq, rs_new
+    b += al(sizeof(double) * B) * 5;       // rs, rs0, pq, rs_new, pp
+    b += al(sizeof(double) * 4);           // ||A||_F^2
     b += al(sizeof(int) * B);              // done
     b += al(sizeof(int) * 16);
     return b + 1024;
@@ -896,6 +1092,8 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     double* rs0 = (double*)take(sizeof(double) * B);
     double* pq = (double*)take(sizeof(double) * B);
     double* rsn = (double*)take(sizeof(double) * B);
+    double* pp = (double*)take(sizeof(double) * B);
+    double* frob = (double*)take(sizeof(double) * 4);
     int* done = (int*)take(sizeof(int) * B);
     int* counters = (int*)take(sizeof(int) * 16);
 
@@ -911,6 +1109,7 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     k_adj_init<<<grid, 256, 0, s>>>(X, ldx, dX, ldg, (int)n, (int)B, V, Rc, P, F);
     k_adj_dot<<<(int)B, 256, 0, s>>>(Rc, Rc, (int)n, rs);
     k_b_copy<<<64, 256, 0, s>>>(rs, rs0, B);
+    k_adj_frob<<<1, 1024, 0, s>>>(A64, (long long)m * n, frob);
     BXS_HIPB(hipMemsetAsync(done, 0, sizeof(int) * B, s));
     BXS_HIPB(hipGetLastError());
     const double one = 1.0, zero = 0.0, mone = -1.0;
@@ -929,11 +1128,12 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
         BXS_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, (int)n, (int)B, (int)m, &one,
                                A64, (int)m, Q, (int)m, &zero, S, (int)n));
         k_adj_mask<<<grid, 256, 0, s>>>(S, F, (long long)n * B);
-        k_adj_dot<<<(int)B, 256, 0, s>>>(P, S, (int)n, pq);
-        k_adj_step<<<grid, 256, 0, s>>>(S, F, rs, pq, done, V, Rc, P, (int)n, (int)B);
+        k_adj_dot2<<<(int)B, 256, 0, s>>>(P, S, (int)n, pq, pp);
+        k_adj_step<<<grid, 256, 0, s>>>(S, F, rs, pq, pp, frob, (int)m, done, V, Rc, P, (int)n, (int)B);
         k_adj_dot<<<(int)B, 256, 0, s>>>(Rc, Rc, (int)n, rsn);
         k_adj_dir<<<grid, 256, 0, s>>>(P, Rc, rsn, rs, done, (int)n, (int)B);
-        k_adj_track<<<(int)((B + 255) / 256), 256, 0, s>>>(rs, rsn, rs0, pq, done, (int)B, tol * tol);
+        k_adj_track<<<(int)((B + 255) / 256), 256, 0, s>>>(rs, rsn, rs0, pq, pp, frob, (int)m, done, (int)B,
+                                                           tol * tol);
         if ((it % 8) == 7 || it + 1 == maxit) {
             BXS_HIPB(hipMemsetAsync(counters, 0, 2 * sizeof(int), s));
             k_adj_count<<<16, 256, 0, s>>>(done, (int)B, counters);
@@ -942,6 +1142,7 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
             if (hflag[0] == hflag[1]) { ++it; break; }   // every column converged or broke down
         }
     }
+    k_adj_zero_broken<<<grid, 256, 0, s>>>(V, done, (int)n, (int)B);
     BXS_HIPB(hipGetLastError());
     // dL/dY = A V
     BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)m, (int)B, (int)n, &one, A64, (int)m,

@@ -47,7 +47,7 @@ class Info(C.Structure):
                 ("gap", C.c_double), ("primal", C.c_double), ("radius", C.c_double), ("eps", C.c_double),
                 ("step", C.c_double), ("lipschitz", C.c_double), ("ms_setup", C.c_double),
                 ("ms_solve", C.c_double), ("col_iters", C.c_long), ("sweep_ms", C.c_double),
-                ("sweep_launches", C.c_long)]
+                ("sweep_launches", C.c_long), ("event_overhead_ms", C.c_double)]
 
 
 class Problem(C.Structure):
