@@ -67,6 +67,35 @@ def bench_c1(args, device):
         x, sat, info = bx.solve_nnls(A, y, **kw)
     _sync()
     dt = (time.perf_counter() - t0) / args.steps
+    # the same solve with direct launches instead of graph replay of a pass
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bx.solve_nnls(A, y, graph=False, **kw)
+    _sync()
+    dt_direct = (time.perf_counter() - t0) / args.steps
+    # coordinate descent (one sweep per iteration, screening every 10 sweeps)
+    bx.solve_nnls(A, y, solver="cd", **kw)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, info_cd = bx.solve_nnls(A, y, solver="cd", **kw)
+    _sync()
+    dt_cd = (time.perf_counter() - t0) / args.steps
+    # the non-negative companion (t = -1 interior: screening fires)
+    Pc = W.c1_companion(0)
+    Ac, yc, _, _ = _upload(Pc, device)
+    comp = {}
+    for solver in ["pg", "cd"]:
+        for screening in [True, False]:
+            bx.solve_nnls(Ac, yc, solver=solver, screening=screening, **kw)
+            _sync()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, _, ic = bx.solve_nnls(Ac, yc, solver=solver, screening=screening, **kw)
+            _sync()
+            comp[f"{solver}_{'screened' if screening else 'unscreened'}"] = {
+                "ms_per_solve": round(1e3 * (time.perf_counter() - t0) / args.steps, 3), "iters": ic["iters"],
+                "n_screened": ic["n_lower"], "status": ic["status_name"], "gap": ic["gap"]}
     # many instances of the same law in one batch call
     count = 1024
     probs = []
@@ -82,7 +111,11 @@ def bench_c1(args, device):
     dtb = time.perf_counter() - t0
     out = {"workload": "C1: NNLS 200x500 N(0,1) unit columns FP64, PG K=10, gap 1e-9",
            "single": {"solves_per_s": round(1 / dt, 2), "ms_per_solve": round(1e3 * dt, 3), "iters": info["iters"],
-                      "t_valid": info["t_valid"], "n_screened": info["n_lower"], "status": info["status_name"]},
+                      "t_valid": info["t_valid"], "n_screened": info["n_lower"], "status": info["status_name"],
+                      "ms_per_solve_direct_launches": round(1e3 * dt_direct, 3)},
+           "single_cd": {"solves_per_s": round(1 / dt_cd, 2), "ms_per_solve": round(1e3 * dt_cd, 3),
+                         "sweeps": info_cd["iters"], "status": info_cd["status_name"]},
+           "companion_nonneg_A": comp,
            "batch": {"instances": count, "solves_per_s": round(count / dtb, 1), "seconds": round(dtb, 3),
                      "status": status, "max_iters": max(i["iters"] for i in infos)}}
     if not args.no_cpu_baseline:

@@ -101,6 +101,10 @@ typedef struct {
     int     profile;         /* 1: time every primal-iteration sweep with HIP events recorded on
                                 opts->stream and report it in info.sweep_ms / sweep_launches  */
     int     iter_precision;  /* bxs_iter_precision; only the batched shared-matrix solver      */
+    int     graph;           /* 1 (default): every regular screening pass (K iterations, not the
+                                last) of solve_bvls / solve_nnls / solve_bvls_varbatch is
+                                captured once as a HIP graph and replayed; 0: direct launches.
+                                Profile mode always launches directly.                         */
 } bxs_opts;
 
 typedef struct {

@@ -333,11 +333,46 @@ static bxs_status pinned(size_t bytes, void** out)
     return BXS_OK;
 }
 
+// A library-owned stream per device (non-blocking, default priority) for
+// callers that pass the null stream: a graph cannot be captured on it.
+static hipStream_t g_side_stream[64];
+
+static bxs_status side_stream(hipStream_t* out)
+{
+    int dev = 0;
+    BXS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(BXS_ERR_DEVICE, "device index %d out of range", dev);
+    if (!g_side_stream[dev]) BXS_HIP(hipStreamCreateWithFlags(&g_side_stream[dev], hipStreamNonBlocking));
+    *out = g_side_stream[dev];
+    return BXS_OK;
+}
+
 static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bxs_info* infos,
                       bxs_pass_record* history, long history_cap)
 {
     const long count = (long)P.specs.size();
     hipStream_t stream = (hipStream_t)o->stream;
+    const bool want_graph = o->graph && !o->profile && o->max_iter >= 3LL * o->screen_every;
+    // With the null stream and graph replay, the solve runs on the side
+    // stream, ordered after the caller's earlier work; every path below ends
+    // with that stream synchronised, so the caller needs no further wait.
+    struct SideGuard {
+        hipStream_t s = nullptr;
+        ~SideGuard() { if (s) (void)hipStreamSynchronize(s); }
+    } side_guard;
+    if (want_graph && stream == nullptr) {
+        hipStream_t side = nullptr;
+        const bxs_status ss = side_stream(&side);
+        if (ss != BXS_OK) return ss;
+        hipEvent_t ev;
+        BXS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        const hipError_t e1 = hipEventRecord(ev, stream);
+        const hipError_t e2 = (e1 == hipSuccess) ? hipStreamWaitEvent(side, ev, 0) : e1;
+        (void)hipEventDestroy(ev);
+        BXS_HIP(e2);
+        stream = side;
+        side_guard.s = side;
+    }
     void* ws = o->workspace;
     bool owned = false;
     if (ws) {
@@ -469,8 +504,9 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     long long slot_kk[2] = {0, 0};
     int slot_final[2] = {0, 0};
 
-    auto enqueue_pass = [&](int slot) -> bxs_status {
-        const long long kk = std::min<long long>(K, o->max_iter - iters);
+    // The kernels of one pass: kk primal iterations, the correlation sweep,
+    // the screening kernel and the fold.  `slot` selects the profile events.
+    auto enqueue_kernels = [&](int slot, long long kk, int final_pass) -> bxs_status {
         for (long long k = 0; k < kk; ++k) {
             if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k], stream));
             if (o->solver == BXS_PG) {
@@ -487,13 +523,45 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
                 BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
             }
         }
-        iters += kk;
         for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
-        const int final_pass = iters >= o->max_iter;
-        BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, iters, (int)kk));
+        BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));
+        }
+        return BXS_OK;
+    };
+
+    // A regular pass (K iterations, not the last) has the same launches and
+    // arguments every time: capture it once as a graph and replay it.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphGuard {
+        hipGraph_t* g;
+        hipGraphExec_t* e;
+        ~GraphGuard() {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            if (*g) (void)hipGraphDestroy(*g);
+        }
+    } gguard{&graph, &gexec};
+    if (want_graph) {
+        BXS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        const bxs_status cs = enqueue_kernels(0, K, 0);
+        const hipError_t ce = hipStreamEndCapture(stream, &graph);
+        if (cs != BXS_OK) return cs;
+        BXS_HIP(ce);
+        BXS_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
+
+    auto enqueue_pass = [&](int slot) -> bxs_status {
+        const long long kk = std::min<long long>(K, o->max_iter - iters);
+        iters += kk;
+        const int final_pass = iters >= o->max_iter;
+        if (gexec && kk == K && !final_pass) {
+            BXS_HIP(hipGraphLaunch(gexec, stream));
+        } else {
+            const bxs_status es = enqueue_kernels(slot, kk, final_pass);
+            if (es != BXS_OK) return es;
         }
         BXS_HIP(hipMemcpyAsync(hdone + slot, D.done_counter, sizeof(int), hipMemcpyDeviceToHost, stream));
         BXS_HIP(hipEventRecord(dev_done[slot], stream));
@@ -595,6 +663,7 @@ void bxs_default_opts(bxs_opts* o)
     o->eps_gap = 1e-6;
     o->step = 0.0;
     o->power_iters = 20;
+    o->graph = 1;
 }
 
 const char* bxs_last_error(void) { return g_last_error.c_str(); }

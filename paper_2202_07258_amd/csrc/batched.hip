@@ -88,7 +88,7 @@ __device__ __forceinline__ void split_bf16(float v, short& hi, short& lo) {
 typedef unsigned short u16;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf8v;
 
-constexpr int kG3M = 128, kG3N = 128, kG3K = 32, kG3Ld = 40;   // LDS row: 32 bf16 + 16 B pad
+constexpr int kG3K = 32, kG3Ld = 40;   // K step; LDS row of 32 bf16 + 16 B pad
 
 struct G3Args {
     const u16* Ahi; const u16* Alo; long long lda;     // Aop, lda = padded K
@@ -102,90 +102,109 @@ struct G3Args {
 
 __device__ __forceinline__ unsigned pack2(u16 a, u16 b) { return (unsigned)a | ((unsigned)b << 16); }
 
-template <int EPI>
+template <int EPI, int TM>
 __global__ __launch_bounds__(256)
 void k_gemm3(G3Args p)
 {
-    // LDS: the two K-step operand tiles, reused by the epilogue for one half
-    // (64 columns) of the FP32 result tile at a time
-    constexpr int kOpBytes = 2 * (kG3M + kG3N) * kG3Ld * (int)sizeof(u16);
-    constexpr int kCLd = kG3M + 4;
-    constexpr int kCBytes = 64 * kCLd * (int)sizeof(float);
+    constexpr int WT = TM / 2;                 // wave tile (2 x 2 waves)
+    constexpr int NB = WT / 16;                // 16 x 16 blocks per wave and dimension
+    constexpr int NL = TM / 64;                // 16-byte loads per thread and operand part (1 or 2)
+    static_assert(TM == 64 || TM == 128, "tile of 64 or 128");
+    // LDS: the operand tiles of one K step, reused by the epilogue for one
+    // half (WT columns) of the FP32 result tile at a time
+    constexpr int kOpBytes = 4 * TM * kG3Ld * (int)sizeof(u16);
+    constexpr int kCLd = TM + 4;
+    constexpr int kCBytes = WT * kCLd * (int)sizeof(float);
     __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes > kCBytes ? kOpBytes : kCBytes];
-    u16 (*sA)[kG3M * kG3Ld] = (u16 (*)[kG3M * kG3Ld])smem;
-    u16 (*sB)[kG3N * kG3Ld] = (u16 (*)[kG3N * kG3Ld])(smem + 2 * kG3M * kG3Ld * sizeof(u16));
-    float* sC = (float*)smem;
-    __shared__ int s_act[kG3N];
+    u16* const sAh = (u16*)smem;
+    u16* const sAl = sAh + TM * kG3Ld;
+    u16* const sBh = sAl + TM * kG3Ld;
+    u16* const sBl = sBh + TM * kG3Ld;
+    float* const sC = (float*)smem;
+    __shared__ int s_act[TM];
     const int tiles = p.tiles_m * p.tiles_n;
     const int id = blockIdx.x;
     const int t = (tiles % 8 == 0) ? (id % 8) * (tiles / 8) + id / 8 : id;
-    const int row0 = (t % p.tiles_m) * kG3M, col0 = (t / p.tiles_m) * kG3N;
+    const int row0 = (t % p.tiles_m) * TM, col0 = (t / p.tiles_m) * TM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < kG3N) s_act[tid] = (col0 + tid < p.nact) ? p.act[col0 + tid] : -1;
+    if (tid < TM) s_act[tid] = (col0 + tid < p.nact) ? p.act[col0 + tid] : -1;
     __syncthreads();
 
-    // global -> register slots: 2 x 16 B of each of Ahi, Alo, Bhi, Blo per
+    // global -> register slots: NL x 16 B of each of Ahi, Alo, Bhi, Blo per
     // thread.  Columns past the active count read column 0 of Bop: each
     // output column depends on its own Bop column only, and those outputs
     // are never stored.
     const int kq = 8 * (tid & 3);
-    const int r0 = tid >> 2, r1 = r0 + 64;
+    const int r0 = tid >> 2, r1 = r0 + 64;     // second slot only for TM = 128
     const int srow0 = r0 * kG3Ld + kq, srow1 = r1 * kG3Ld + kq;
-    const u16* pa0h = p.Ahi + (long long)(row0 + r0) * p.lda + kq;
-    const u16* pa1h = p.Ahi + (long long)(row0 + r1) * p.lda + kq;
-    const u16* pa0l = p.Alo + (long long)(row0 + r0) * p.lda + kq;
-    const u16* pa1l = p.Alo + (long long)(row0 + r1) * p.lda + kq;
+    const u16* const pa0h = p.Ahi + (long long)(row0 + r0) * p.lda + kq;
+    const u16* const pa0l = p.Alo + (long long)(row0 + r0) * p.lda + kq;
     const long long bo0 = (long long)max(s_act[r0], 0) * p.ldb + kq;
-    const long long bo1 = (long long)max(s_act[r1], 0) * p.ldb + kq;
-    const u16* pb0h = p.Bhi + bo0;
-    const u16* pb1h = p.Bhi + bo1;
-    const u16* pb0l = p.Blo + bo0;
-    const u16* pb1l = p.Blo + bo1;
-    uint4 ga0h = *(const uint4*)pa0h, ga1h = *(const uint4*)pa1h;
-    uint4 ga0l = *(const uint4*)pa0l, ga1l = *(const uint4*)pa1l;
-    uint4 gb0h = *(const uint4*)pb0h, gb1h = *(const uint4*)pb1h;
-    uint4 gb0l = *(const uint4*)pb0l, gb1l = *(const uint4*)pb1l;
+    const u16* const pb0h = p.Bhi + bo0;
+    const u16* const pb0l = p.Blo + bo0;
+    const u16* pa1h = pa0h;
+    const u16* pa1l = pa0l;
+    const u16* pb1h = pb0h;
+    const u16* pb1l = pb0l;
+    if constexpr (NL > 1) {
+        pa1h = p.Ahi + (long long)(row0 + r1) * p.lda + kq;
+        pa1l = p.Alo + (long long)(row0 + r1) * p.lda + kq;
+        const long long bo1 = (long long)max(s_act[r1], 0) * p.ldb + kq;
+        pb1h = p.Bhi + bo1;
+        pb1l = p.Blo + bo1;
+    }
+    uint4 ga0h = *(const uint4*)pa0h, ga0l = *(const uint4*)pa0l;
+    uint4 gb0h = *(const uint4*)pb0h, gb0l = *(const uint4*)pb0l;
+    uint4 ga1h, ga1l, gb1h, gb1l;
+    if constexpr (NL > 1) {
+        ga1h = *(const uint4*)pa1h; ga1l = *(const uint4*)pa1l;
+        gb1h = *(const uint4*)pb1h; gb1l = *(const uint4*)pb1l;
+    }
 
     const int wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 15, lk = 8 * (lane >> 4);
-    f4 acc[4][4];
+    f4 acc[NB][NB];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < NB; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = 0; k0 < p.K; k0 += kG3K) {
         __syncthreads();                      // every wave is done with the previous K step
-        *(uint4*)&sA[0][srow0] = ga0h;
-        *(uint4*)&sA[0][srow1] = ga1h;
-        *(uint4*)&sA[1][srow0] = ga0l;
-        *(uint4*)&sA[1][srow1] = ga1l;
-        *(uint4*)&sB[0][srow0] = gb0h;
-        *(uint4*)&sB[0][srow1] = gb1h;
-        *(uint4*)&sB[1][srow0] = gb0l;
-        *(uint4*)&sB[1][srow1] = gb1l;
+        *(uint4*)&sAh[srow0] = ga0h;
+        *(uint4*)&sAl[srow0] = ga0l;
+        *(uint4*)&sBh[srow0] = gb0h;
+        *(uint4*)&sBl[srow0] = gb0l;
+        if constexpr (NL > 1) {
+            *(uint4*)&sAh[srow1] = ga1h;
+            *(uint4*)&sAl[srow1] = ga1l;
+            *(uint4*)&sBh[srow1] = gb1h;
+            *(uint4*)&sBl[srow1] = gb1l;
+        }
         __syncthreads();
         const int kn = k0 + kG3K;
         if (kn < p.K) {                       // next K step in flight during the MFMAs
-            ga0h = *(const uint4*)(pa0h + kn); ga1h = *(const uint4*)(pa1h + kn);
-            ga0l = *(const uint4*)(pa0l + kn); ga1l = *(const uint4*)(pa1l + kn);
-            gb0h = *(const uint4*)(pb0h + kn); gb1h = *(const uint4*)(pb1h + kn);
-            gb0l = *(const uint4*)(pb0l + kn); gb1l = *(const uint4*)(pb1l + kn);
+            ga0h = *(const uint4*)(pa0h + kn); ga0l = *(const uint4*)(pa0l + kn);
+            gb0h = *(const uint4*)(pb0h + kn); gb0l = *(const uint4*)(pb0l + kn);
+            if constexpr (NL > 1) {
+                ga1h = *(const uint4*)(pa1h + kn); ga1l = *(const uint4*)(pa1l + kn);
+                gb1h = *(const uint4*)(pb1h + kn); gb1l = *(const uint4*)(pb1l + kn);
+            }
         }
-        bf8v ah[4], al[4], bh[4], bl[4];
+        bf8v ah[NB], al[NB], bh[NB], bl[NB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int ra_ = (wr * 64 + q * 16 + lr) * kG3Ld + lk;
-            const int rb_ = (wc * 64 + q * 16 + lr) * kG3Ld + lk;
-            ah[q] = *(const bf8v*)&sA[0][ra_];
-            al[q] = *(const bf8v*)&sA[1][ra_];
-            bh[q] = *(const bf8v*)&sB[0][rb_];
-            bl[q] = *(const bf8v*)&sB[1][rb_];
+        for (int q = 0; q < NB; ++q) {
+            const int ra_ = (wr * WT + q * 16 + lr) * kG3Ld + lk;
+            const int rb_ = (wc * WT + q * 16 + lr) * kG3Ld + lk;
+            ah[q] = *(const bf8v*)&sAh[ra_];
+            al[q] = *(const bf8v*)&sAl[ra_];
+            bh[q] = *(const bf8v*)&sBh[rb_];
+            bl[q] = *(const bf8v*)&sBl[rb_];
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < NB; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < NB; ++b) {
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
@@ -201,15 +220,15 @@ void k_gemm3(G3Args p)
         __syncthreads();                      // LDS free (operand tiles or previous half)
         if (wc == h) {
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
+            for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
-                    *(f4*)&sC[(cb * 16 + lr) * kCLd + wr * 64 + a * 16 + 4 * (lane >> 4)] = acc[a][cb];
+                for (int a = 0; a < NB; ++a)
+                    *(f4*)&sC[(cb * 16 + lr) * kCLd + wr * WT + a * 16 + 4 * (lane >> 4)] = acc[a][cb];
         }
         __syncthreads();
-        for (int idx = tid; idx < 64 * kG3M; idx += 256) {
-            const int cl = idx / kG3M, rl = idx % kG3M;
-            const int b = s_act[h * 64 + cl];
+        for (int idx = tid; idx < WT * TM; idx += 256) {
+            const int cl = idx / TM, rl = idx % TM;
+            const int b = s_act[h * WT + cl];
             if (b < 0) break;                 // inactive columns are the last ones of the tile
             const int j = row0 + rl;
             const float val = sC[cl * kCLd + rl];
@@ -231,6 +250,23 @@ void k_gemm3(G3Args p)
                 p.Olo[(long long)b * p.ldo + j] = (u16)ll;
             }
         }
+    }
+}
+
+// Launch one GEMM of an iteration with 128 x 128 tiles, or 64 x 64 tiles when
+// the larger ones would leave most of the chip idle (fewer tiles than CUs).
+template <int EPI>
+static void launch_gemm3(G3Args g, long Mpad, int nact, int cus, hipStream_t s)
+{
+    const int t128 = (int)(Mpad / 128) * ((nact + 127) / 128);
+    if (t128 >= cus) {
+        g.tiles_m = (int)(Mpad / 128);
+        g.tiles_n = (nact + 127) / 128;
+        k_gemm3<EPI, 128><<<g.tiles_m * g.tiles_n, 256, 0, s>>>(g);
+    } else {
+        g.tiles_m = (int)(Mpad / 64);
+        g.tiles_n = (nact + 63) / 64;
+        k_gemm3<EPI, 64><<<g.tiles_m * g.tiles_n, 256, 0, s>>>(g);
     }
 }
 
@@ -776,6 +812,12 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
         if (bs != BXS_OK) return bs;
         k_b_g64_to_32<<<grid, 256, 0, s>>>(G64, G32, (int)n, act, nact);
     }
+    int cus = 256;
+    {
+        int dev = 0;
+        BXS_HIPB(hipGetDevice(&dev));
+        BXS_HIPB(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     int* hdone = nullptr;
     BXS_HIPB(hipHostMalloc((void**)&hdone, 2 * sizeof(int), hipHostMallocDefault));
     int hnact = (int)B;
@@ -798,18 +840,16 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
             if (kk > 0)
                 k_b_step_split<<<grid, 256, 0, s>>>(X64, G32, (int)n, act, nact, sat, ldsat, eta, Dh, Dl, np);
             G3Args g0{};
-            g0.Ahi = ARh; g0.Alo = ARl; g0.lda = np; g0.tiles_m = (int)(mp / kG3M);
-            g0.tiles_n = (hnact + kG3N - 1) / kG3N; g0.K = (int)np; g0.act = act; g0.nact = hnact;
+            g0.Ahi = ARh; g0.Alo = ARl; g0.lda = np; g0.K = (int)np; g0.act = act; g0.nact = hnact;
             g0.Bhi = Dh; g0.Blo = Dl; g0.ldb = np; g0.Ohi = Uh; g0.Olo = Ul; g0.ldo = mp;
             G3Args g1{};
-            g1.Ahi = ACh; g1.Alo = ACl; g1.lda = mp; g1.tiles_m = (int)(np / kG3M);
-            g1.tiles_n = g0.tiles_n; g1.K = (int)mp; g1.act = act; g1.nact = hnact;
+            g1.Ahi = ACh; g1.Alo = ACl; g1.lda = mp; g1.K = (int)mp; g1.act = act; g1.nact = hnact;
             g1.Bhi = Uh; g1.Blo = Ul; g1.ldb = mp; g1.Ohi = Dh; g1.Olo = Dl; g1.ldo = np;
             g1.G = G32; g1.X = X64; g1.sat = sat; g1.ldsat = ldsat; g1.n = (int)n; g1.eta = eta;
             for (long long k = 1; k < kk && hnact > 0; ++k) {
                 if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k], s));
-                k_gemm3<0><<<g0.tiles_m * g0.tiles_n, 256, 0, s>>>(g0);
-                k_gemm3<1><<<g1.tiles_m * g1.tiles_n, 256, 0, s>>>(g1);
+                launch_gemm3<0>(g0, mp, hnact, cus, s);
+                launch_gemm3<1>(g1, np, hnact, cus, s);
                 if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k + 1], s));
             }
         } else {

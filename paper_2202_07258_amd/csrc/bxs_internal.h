@@ -209,7 +209,7 @@ hipError_t launch_pow_init(const LaunchCtx& c, int count);
 hipError_t launch_set_step(const LaunchCtx& c, int count, double step);
 hipError_t launch_pow_normalize(const LaunchCtx& c, int count, int last, double user_step);
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening,
-                         int final_pass, long long iters, int kk);
+                         int final_pass, int K, int kk);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
 
 }  // namespace bxs

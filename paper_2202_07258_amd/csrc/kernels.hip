@@ -758,7 +758,7 @@ void k_pow_normalize(const Inst* __restrict__ insts, State* __restrict__ st, int
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024)
 void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
-              double eps_gap, int screening, int final_pass, long long iters, int kk)
+              double eps_gap, int screening, int final_pass, int K, int kk)
 {
     constexpr int NT = 1024;
     constexpr int E = 4;                       // consecutive preserved positions per thread per chunk
@@ -773,6 +773,10 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
     const int m = I.m, n = I.n;
     const int nA = S.n_active;
     const int passes = S.passes;
+    // every earlier pass ran K primal iterations (all unfinished instances of
+    // a call advance together), this one kk: the arguments stay the same for
+    // every regular pass, so a pass can be replayed from a captured graph
+    const long long iters = (long long)passes * K + kk;
     const double tnorm = S.tnorm;
     const double u1 = kUnit;
     const bool nnls_like = (I.u == nullptr);   // every u_j = +inf
@@ -1205,10 +1209,10 @@ hipError_t launch_pow_normalize(const LaunchCtx& c, int count, int last, double 
 }
 
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening, int final_pass,
-                         long long iters, int kk)
+                         int K, int kk)
 {
     k_screen<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                        final_pass, iters, kk);
+                                                        final_pass, K, kk);
     return hipGetLastError();
 }
 

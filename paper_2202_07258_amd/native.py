@@ -38,7 +38,7 @@ class Opts(C.Structure):
                 ("power_iters", C.c_int), ("t", C.c_void_p), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("history", C.POINTER(PassRecord)), ("history_cap", C.c_long), ("profile", C.c_int),
-                ("iter_precision", C.c_int)]
+                ("iter_precision", C.c_int), ("graph", C.c_int)]
 
 
 class Info(C.Structure):
@@ -160,7 +160,7 @@ def colmajor(A: Any, device="cuda", dtype=None) -> torch.Tensor:
 
 def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, eps_gap=1e-6, step=0.0,
               power_iters=20, t: torch.Tensor | None = None, history=0, stream=None,
-              profile=False, iter_precision="f64") -> tuple[Opts, Any]:
+              profile=False, iter_precision="f64", graph=True) -> tuple[Opts, Any]:
     lib = load()
     o = Opts()
     lib.bxs_default_opts(C.byref(o))
@@ -175,6 +175,7 @@ def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, 
     o.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
     o.profile = 1 if profile else 0
     o.iter_precision = {"f64": 0, "bf16x3": 1}[iter_precision] if isinstance(iter_precision, str) else int(iter_precision)
+    o.graph = 1 if graph else 0
     hist = None
     if history:
         hist = (PassRecord * int(history))()

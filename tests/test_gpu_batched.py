@@ -122,3 +122,31 @@ def test_batched_power_step_and_maxiter():
     for info in infos:
         assert info["status_name"] == "maxiter" and info["iters"] == 30
         assert 0.9 * L <= info["lipschitz"] <= L * (1 + 1e-12)
+
+
+def test_batched_full_c3_size_sampled():
+    """The C3 workload at its full size (A 1024 x 4096 U[0,1] unit columns in
+    FP32, 8192 right-hand sides, the launch configuration the benchmark times:
+    128 x 128 GEMM tiles), for a fixed budget of 40 iterations.  BF16x3 and
+    FP64 engines agree on every column; the FP64 engine follows the oracle's
+    trajectory on sampled columns."""
+    A, Y, _ = W.c3_shared(0, B=8192)
+    m, n = A.shape
+    A64 = A.astype(np.float64)
+    eta = 1.0 / (1.05 * ob.lipschitz_power(A64, 20))
+    kw = dict(screen_every=10, eps_gap=1e-6, max_iter=40, step=eta)
+    X64, S64, inf64 = _run(A, Y, iter_precision="f64", **kw)
+    X3, S3, inf3 = _run(A, Y, iter_precision="bf16x3", **kw)
+    scale = max(1.0, float(np.abs(X64).max()))
+    assert float(np.abs(X3 - X64).max()) <= 1e-6 * scale
+    g64 = np.array([i["gap"] for i in inf64])
+    g3 = np.array([i["gap"] for i in inf3])
+    np.testing.assert_allclose(g3, g64, rtol=1e-5)
+    assert all(i["status_name"] == "maxiter" and i["iters"] == 40 for i in inf64 + inf3)
+    rng = np.random.default_rng(3)
+    for b in rng.choice(8192, size=3, replace=False):
+        P = W.Problem(A, Y[:, b].copy(), np.zeros(n), np.full(n, np.inf))
+        res = ob.solve(A64, P.y, P.l, P.u, K=10, eps_gap=1e-6, max_iter=40, step=eta)
+        assert float(np.abs(X64[:, b] - res.x).max()) <= 1e-9 * max(1.0, float(np.abs(res.x).max()))
+        np.testing.assert_array_equal(S64[:, b], res.sat)
+        assert abs(inf64[b]["gap"] - res.gap) <= 1e-6 * res.gap + 1e-11
