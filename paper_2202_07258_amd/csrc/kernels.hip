@@ -110,6 +110,32 @@ __device__ __forceinline__ void load_pack(const TA* __restrict__ col, int row, i
     }
 }
 
+// Stores through a global address-space pointer: a store through a generic
+// pointer is a flat store, which the compiler's wait-count tracking handles
+// conservatively (it would wait for every outstanding load, including the
+// next round's prefetch).
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) { *(__attribute__((address_space(1))) T*)p = v; }
+
+// Branch-free form for the column sweeps: one vector load through a global
+// address-space pointer, from row `row` if row < m and from row 0 otherwise,
+// so the loads of the next round stay in flight while the current round is
+// reduced (a load under a divergent branch is waited for inside the branch).
+// Elements at rows >= m hold whatever the column's padding holds; the caller
+// masks them before they can reach a stored result.
+template <typename TA, int V>
+__device__ __forceinline__ void load_pack_nb(const TA* __restrict__ col, int row, int m, TA (&o)[V]) {
+    const int rr = (row < m) ? row : 0;
+    if constexpr (V == 1) {
+        o[0] = *(const __attribute__((address_space(1))) TA*)(col + rr);
+    } else {
+        typedef TA VecT __attribute__((ext_vector_type(V)));
+        const VecT v = *(const __attribute__((address_space(1))) VecT*)(col + rr);
+#pragma unroll
+        for (int e = 0; e < V; ++e) o[e] = v[e];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Wave-level reduce-scatter of CBI per-lane partial sums: after log2(CBI)
 // halving exchanges and the remaining butterfly steps, lane L holds the full
@@ -207,6 +233,11 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     const double eta = (MODE == kModePG) ? S.step : 0.0;
     const double tnorm_c = (MODE == kModeCorr) ? S.tnorm : 0.0;
 
+    bool rowok[R];
+#pragma unroll
+    for (int k = 0; k < RO; ++k)
+#pragma unroll
+        for (int e = 0; e < V; ++e) rowok[k * V + e] = (k * TPC + L) * V + e < m;
     double rl[DOT ? R : 1];
     if constexpr (DOT) {
 #pragma unroll
@@ -301,17 +332,14 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
         for (int c = 0; c < CBI; ++c) {
             const int q = rs + c * NG + grp;
             const bool vv = q < pos1;
-            const int jj = vv ? s_j[q - pos0] : 0;
+            // a slot past the item's end reads the item's first column; its
+            // dot product is discarded and its update coefficient is 0
+            const int jj = s_j[vv ? q - pos0 : 0];
             const TA* col = A + (long long)jj * lda;
 #pragma unroll
             for (int k = 0; k < RO; ++k) {
                 TA tmp[V];
-                if (vv) {
-                    load_pack<TA, V>(col, (k * TPC + L) * V, m, tmp);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < V; ++e) tmp[e] = TA(0);
-                }
+                load_pack_nb<TA, V>(col, (k * TPC + L) * V, m, tmp);
 #pragma unroll
                 for (int e = 0; e < V; ++e) a[c][k * V + e] = tmp[e];
             }
@@ -343,7 +371,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
             for (int c = 0; c < CBI; ++c) {
                 double s = 0.0;
 #pragma unroll
-                for (int k = 0; k < R; ++k) s = fma((double)a[c][k], rl[k], s);
+                for (int k = 0; k < R; ++k) s = fma(rowok[k] ? (double)a[c][k] : 0.0, rl[k], s);
                 d[c] = s;
             }
             double tot = wave_reduce_scatter<CBI>(d, lane);
@@ -361,10 +389,10 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
                 if constexpr (MODE == kModePG) {
                     const double xn = fmin(fmax(xo + eta * tot, lo), uo);
                     cown = xn;
-                    if (owner) I.x[s_j[jo]] = xn;
+                    if (owner) gstore(I.x + s_j[jo], xn);
                 } else if constexpr (MODE == kModeCorr) {
                     if (owner) {
-                        I.g[s_j[jo]] = tot;
+                        gstore(I.g + s_j[jo], tot);
                         // screening quantities of this column at eps = 0
                         const int k = jo;
                         const double cnj = s_cn[k], wj = s_w[k], xj = s_x[k], lj = s_l[k], uj = s_u[k];
@@ -415,14 +443,27 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 
     constexpr int STEP = NG * CBI;
     if constexpr (PD == 1) {
-        // prefetch distance one round: two buffers
+        // prefetch distance one round: two buffers.  Every compute that has a
+        // next round is preceded, on every path, by that round's loads, so
+        // the wait before it leaves the prefetch in flight; the last round of
+        // the item leaves the loop through its own exit.
         load_round(pos0, a0, j0, v0, x0, l0, u0, c10, c20);
-        for (int rs = pos0; rs < pos1; rs += 2 * STEP) {
-            if (rs + STEP < pos1) load_round(rs + STEP, a1, j1, v1, x1, l1, u1, c11, c21);
+        int rs = pos0;
+        while (true) {
+            if (rs + STEP >= pos1) {
+                compute_round(a0, j0, v0, x0, l0, u0, c10, c20);
+                break;
+            }
+            load_round(rs + STEP, a1, j1, v1, x1, l1, u1, c11, c21);
             compute_round(a0, j0, v0, x0, l0, u0, c10, c20);
-            if (rs + STEP >= pos1) break;
-            if (rs + 2 * STEP < pos1) load_round(rs + 2 * STEP, a0, j0, v0, x0, l0, u0, c10, c20);
+            rs += STEP;
+            if (rs + STEP >= pos1) {
+                compute_round(a1, j1, v1, x1, l1, u1, c11, c21);
+                break;
+            }
+            load_round(rs + STEP, a0, j0, v0, x0, l0, u0, c10, c20);
             compute_round(a1, j1, v1, x1, l1, u1, c11, c21);
+            rs += STEP;
         }
     } else {
         // prefetch distance two rounds: three buffers in rotation
@@ -518,7 +559,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             const int row = (k * TPC + L) * V + e;
-            if (row < m) out[row] = p[k * V + e];
+            if (row < m) gstore(out + row, p[k * V + e]);
         }
     if constexpr (MODE == kModeFold) {
         double* __restrict__ out2 = I.part2 + (size_t)it.t * m;
@@ -527,7 +568,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int row = (k * TPC + L) * V + e;
-                if (row < m) out2[row] = p2[k * V + e];
+                if (row < m) gstore(out2 + row, p2[k * V + e]);
             }
     }
     if constexpr (MODE == kModePow) {
@@ -1023,33 +1064,45 @@ void k_cd(const Inst* __restrict__ insts, State* __restrict__ st, const int* __r
             const int row = (k * TPC + L) * V + e;
             rl[k * V + e] = (row < m) ? I.r[row] : 0.0;
         }
+    bool rowok[R];
+#pragma unroll
+    for (int k = 0; k < RO; ++k)
+#pragma unroll
+        for (int e = 0; e < V; ++e) rowok[k * V + e] = (k * TPC + L) * V + e < m;
     __shared__ double red[2][NW];
     int buf = 0;
-    auto load_col = [&](int j, TA (&dst)[R]) {
+    // column j and its scalars; rows >= m are masked where the column is used
+    struct Next { int j; double c2, x, l, u; };
+    auto load_col = [&](int j, TA (&dst)[R], Next& nx) {
         const TA* col = A + (long long)j * lda;
 #pragma unroll
         for (int k = 0; k < RO; ++k) {
             TA tmp[V];
-            load_pack<TA, V>(col, (k * TPC + L) * V, m, tmp);
+            load_pack_nb<TA, V>(col, (k * TPC + L) * V, m, tmp);
 #pragma unroll
             for (int e = 0; e < V; ++e) dst[k * V + e] = tmp[e];
         }
+        nx.j = j;
+        nx.c2 = I.cn2[j];
+        nx.x = I.x[j];
+        nx.l = lo_of(I.l, j);
+        nx.u = up_of(I.u, j);
     };
     for (int s = 0; s < sweeps; ++s) {
         if (nA == 0) break;
         TA av[R];
-        int j = I.idx[0];
-        load_col(j, av);
+        Next cur, nxt{};
+        load_col(I.idx[0], av, cur);
+        int jnn = (nA > 1) ? I.idx[1] : 0;     // index of the next column, one step ahead of its load
         for (int p = 0; p < nA; ++p) {
             TA an[R];
-            int jn = 0;
             if (p + 1 < nA) {
-                jn = I.idx[p + 1];
-                load_col(jn, an);
+                load_col(jnn, an, nxt);
+                jnn = (p + 2 < nA) ? I.idx[p + 2] : 0;
             }
             double d = 0.0;
 #pragma unroll
-            for (int k = 0; k < R; ++k) d = fma((double)av[k], rl[k], d);
+            for (int k = 0; k < R; ++k) d = fma(rowok[k] ? (double)av[k] : 0.0, rl[k], d);
             d = wave_sum(d);
             if constexpr (NW > 1) {
                 if ((L & 63) == 0) red[buf][L >> 6] = d;
@@ -1060,24 +1113,23 @@ void k_cd(const Inst* __restrict__ insts, State* __restrict__ st, const int* __r
                 d = t2;
                 buf ^= 1;
             }
-            const double c2 = I.cn2[j];
-            if (c2 > 0.0) {
-                const double xj = I.x[j];
-                const double xn = fmin(fmax(xj + d / c2, lo_of(I.l, j)), up_of(I.u, j));
-                const double delta = xn - xj;
+            if (cur.c2 > 0.0) {
+                const double xn = fmin(fmax(cur.x + d / cur.c2, cur.l), cur.u);
+                const double delta = xn - cur.x;
                 if (delta != 0.0) {
 #pragma unroll
-                    for (int k = 0; k < R; ++k) rl[k] = fma(-delta, (double)av[k], rl[k]);
-                    if constexpr (NW > 1) __syncthreads();  // every lane has read x_j
-                    if (L == 0) I.x[j] = xn;
+                    for (int k = 0; k < R; ++k) rl[k] = fma(-delta, rowok[k] ? (double)av[k] : 0.0, rl[k]);
+                    if (L == 0) gstore(I.x + cur.j, xn);
                 }
             }
             if (p + 1 < nA) {
-                j = jn;
+                cur = nxt;
 #pragma unroll
                 for (int k = 0; k < R; ++k) av[k] = an[k];
             }
         }
+        // the next sweep reads x_j written by lane 0 in this one
+        if constexpr (NW > 1) __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < RO; ++k)
