@@ -144,7 +144,10 @@ def dual_point(A, y, u, x, t):
 # ---------------------------------------------------------------------------
 def safe_radius(gap: float, alpha: float = 1.0) -> float:
     """r = sqrt(2 Gap / alpha) (eq. GAP_Safe_sph); alpha = 1 for LS since f''=1.
-    A gap that rounds below zero is taken as zero."""
+    A gap that rounds below zero is taken as zero.  Plain FP64 without
+    rounding margins: the rule built on it is safe while the gap is well above
+    its rounding floor (about 1e-16 times the primal value), which is where
+    the tests stop."""
     return math.sqrt(2.0 * max(gap, 0.0) / alpha)
 
 

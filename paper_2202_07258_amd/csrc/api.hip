@@ -145,7 +145,7 @@ static int device_cus()
 
 // Sweep-variant preference per row-count class (the smallest default
 // variant whose capacity holds m); set by bxs_set_sweep_variant.
-static int g_variant_pref[kNumDefaultVariants] = {0, 1, 2, 3, 4, 21, 18, 7, 8};
+static int g_variant_pref[kNumDefaultVariants] = {0, 1, 2, 3, 4, 21, 18, 28, 29};
 
 static int choose_variant(long m)
 {
@@ -245,7 +245,7 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap)
         (void)esz;
     }
     long total_ritems = 0;
-    for (auto& s : P.specs) total_ritems += (s.m + 63) / 64;
+    for (auto& s : P.specs) total_ritems += (s.m + kRedRows - 1) / kRedRows;
     P.bytes = common_bytes(count, total_items, total_ritems) + inst_bytes + 256;
     return BXS_OK;
 }
@@ -257,7 +257,7 @@ static void layout(Plan& P, char* base)
     long total_items = 0, total_ritems = 0;
     for (long i = 0; i < count; ++i) {
         total_items += P.sizes[i].items_cap;
-        total_ritems += (P.specs[i].m + 63) / 64;
+        total_ritems += (P.specs[i].m + kRedRows - 1) / kRedRows;
     }
     char* cur = (char*)align_up((uintptr_t)base, 256);
     auto take = [&](size_t bytes) { char* p = cur; cur += align_up(bytes, 256); return p; };
@@ -296,7 +296,7 @@ static void layout(Plan& P, char* base)
         I.item_base = (int)P.items[b].size();
         for (int t = 0; t < z.items_cap; ++t) P.items[b].push_back(Item{(int)i, t});
         P.cd_list[cd_bucket_for_rows(s.m)].push_back((int)i);
-        for (int rb = 0; rb < (int)((s.m + 63) / 64); ++rb) P.ritems.push_back(RItem{(int)i, rb});
+        for (int rb = 0; rb < (int)((s.m + kRedRows - 1) / kRedRows); ++rb) P.ritems.push_back(RItem{(int)i, rb});
         P.insts[i] = I;
     }
 }

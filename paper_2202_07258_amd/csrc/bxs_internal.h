@@ -87,9 +87,11 @@ struct Item {               // one workgroup of a column sweep
     int t;                  // item index within the instance
 };
 
+constexpr int kRedRows = 16;   // rows per workgroup of the partial reduction
+
 struct RItem {              // one workgroup of a partial reduction
     int inst;
-    int rb;                 // block of 64 rows
+    int rb;                 // block of kRedRows rows
 };
 
 enum SweepMode : int {

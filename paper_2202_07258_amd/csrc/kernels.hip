@@ -116,6 +116,8 @@ __device__ __forceinline__ void load_pack(const TA* __restrict__ col, int row, i
 // next round's prefetch).
 template <typename T>
 __device__ __forceinline__ void gstore(T* p, T v) { *(__attribute__((address_space(1))) T*)p = v; }
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) { return *(const __attribute__((address_space(1))) T*)p; }
 
 // Branch-free form for the column sweeps: one vector load through a global
 // address-space pointer, from row `row` if row < m and from row 0 otherwise,
@@ -577,14 +579,16 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 }
 
 // ---------------------------------------------------------------------------
-// Partial reduction: 64 rows x 16 item-groups per workgroup, fixed order.
-// Each thread issues up to 8 independent loads before summing them in order.
+// Partial reduction: kRedRows rows x 64 item-groups per workgroup (many
+// workgroups even for a few thousand rows), fixed summation order.  Each
+// thread issues U independent branch-free global loads (clamped addresses,
+// masked in the sum) before adding them in order.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(1024)
 void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems)
 {
-    constexpr int TG = 16, U = 8;
+    constexpr int TG = 1024 / kRedRows, U = 8;
     const RItem ri = ritems[blockIdx.x];
     const Inst& I = insts[ri.inst];
     const State& S = st[ri.inst];
@@ -592,33 +596,34 @@ void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RIte
     const int nlist = (MODE == kRedFold) ? S.n_fold : S.n_active;
     const int cb = (MODE == kRedFold) ? S.cb_fold : S.cb;
     const int T = (nlist + cb - 1) / cb;
-    const int rowl = threadIdx.x & 63, tg = threadIdx.x >> 6;
-    const int row = ri.rb * 64 + rowl;
+    const int rowl = threadIdx.x % kRedRows, tg = threadIdx.x / kRedRows;
+    const int row = ri.rb * kRedRows + rowl;
     const int m = I.m;
+    const int rowc = (row < m) ? row : m - 1;          // a valid row; its sum is not stored
     double s = 0.0, s2 = 0.0;
-    if (row < m) {
-        for (int t0 = tg; t0 < T; t0 += TG * U) {
-            double v[U], v2[U];
+    for (int t0 = tg; t0 < T; t0 += TG * U) {
+        double v[U], v2[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int t = t0 + u * TG;
-                v[u] = (t < T) ? I.part[(size_t)t * m + row] : 0.0;
-                if (MODE == kRedFold) v2[u] = (t < T) ? I.part2[(size_t)t * m + row] : 0.0;
-            }
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * TG;
+            const size_t off = (size_t)((t < T) ? t : 0) * m + rowc;
+            v[u] = gload(I.part + off);
+            if (MODE == kRedFold) v2[u] = gload(I.part2 + off);
+        }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                s += v[u];
-                if (MODE == kRedFold) s2 += v2[u];
-            }
+        for (int u = 0; u < U; ++u) {
+            const bool ok = t0 + u * TG < T;
+            s += ok ? v[u] : 0.0;
+            if (MODE == kRedFold) s2 += ok ? v2[u] : 0.0;
         }
     }
-    __shared__ double sh[TG][64], sh2[TG][64];
+    __shared__ double sh[TG][kRedRows], sh2[(MODE == kRedFold) ? TG : 1][kRedRows];
     sh[tg][rowl] = s;
     if (MODE == kRedFold) sh2[tg][rowl] = s2;
     __syncthreads();
     if (tg == 0 && row < m) {
         double tot = 0.0, tot2 = 0.0;
-#pragma unroll
+#pragma unroll 16
         for (int g = 0; g < TG; ++g) {
             tot += sh[g][rowl];
             if (MODE == kRedFold) tot2 += sh2[g][rowl];
@@ -693,21 +698,37 @@ void k_colstats(const Inst* __restrict__ insts, State* __restrict__ st, const It
     const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
     const double gm = gamma_k((double)(I.m / 64) + 8.0);   // summation depth of this kernel
     int err = 0;
+    const int m = I.m;
     for (int j = pos0 + wv; j < pos1; j += 4) {
         const TA* col = A + (long long)j * I.lda;
-        double s2 = 0.0, sw = 0.0;
-        for (int i = lane; i < I.m; i += 64) {
-            const double a = (double)col[i];
-            if (!isfinite(a)) err = kErrNonfinite;
-            s2 = fma(a, a, s2);
-            sw = fma(a, t_of(I.t, i), sw);
+        // four independent branch-free loads per lane and step (clamped rows,
+        // masked), four partial sums per lane added in a fixed order: the
+        // summation depth stays below m/64 + 8
+        double s2[4] = {0.0, 0.0, 0.0, 0.0}, sw[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i0 = lane; i0 < m; i0 += 256) {
+            double a[4], tv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 64 * q;
+                const int ic = (i < m) ? i : lane;
+                a[q] = (double)gload(col + ic);
+                tv[q] = I.t ? gload(I.t + ic) : -1.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = i0 + 64 * q < m;
+                const double av = ok ? a[q] : 0.0;
+                if (ok && !isfinite(av)) err = kErrNonfinite;
+                s2[q] = fma(av, av, s2[q]);
+                sw[q] = fma(av, tv[q], sw[q]);
+            }
         }
-        s2 = wave_sum(s2);
-        sw = wave_sum(sw);
+        double s2t = wave_sum((s2[0] + s2[1]) + (s2[2] + s2[3]));
+        double swt = wave_sum((sw[0] + sw[1]) + (sw[2] + sw[3]));
         if (lane == 0) {
-            I.cn2[j] = s2;
-            I.cn[j] = sqrt(s2 * (1.0 + gm)) * (1.0 + 2.0 * kUnit);
-            I.w[j] = sw;
+            I.cn2[j] = s2t;
+            I.cn[j] = sqrt(s2t * (1.0 + gm)) * (1.0 + 2.0 * kUnit);
+            I.w[j] = swt;
         }
     }
     if (err) atomicOr(&S.err, err);

@@ -61,7 +61,8 @@ FAKE = 1 << 20   # never dereferenced: every case below fails validation first
 
 
 @pytest.mark.parametrize("m,n,lda,code", [(0, 5, 1, N.BXS_ERR_SHAPE), (5, 0, 5, N.BXS_ERR_SHAPE),
-                                          (5, 5, 4, N.BXS_ERR_SHAPE), (20000, 5, 20000, N.BXS_ERR_SHAPE)])
+                                          (5, 5, 4, N.BXS_ERR_SHAPE), (20000, 5, 20000, N.BXS_ERR_SHAPE),
+                                          (N.MAX_ROWS + 1, 5, N.MAX_ROWS + 1, N.BXS_ERR_SHAPE)])
 def test_shape_errors(lib, m, n, lda, code):
     o = _opts(lib)
     info = N.Info()
@@ -86,6 +87,14 @@ def test_null_arguments(lib):
     assert lib.solve_nnls(8, 8, 0, FAKE, 8, FAKE, FAKE, FAKE, None, None) == N.BXS_ERR_ARG
     assert lib.solve_nnls(8, 8, 5, FAKE, 8, FAKE, FAKE, FAKE, C.byref(o), None) == N.BXS_ERR_ARG
     assert lib.solve_bvls_varbatch(0, 0, None, C.byref(o), None) == N.BXS_ERR_ARG
+
+
+def test_workspace_query_row_limit(lib):
+    o = N.Opts()
+    lib.bxs_default_opts(C.byref(o))
+    b = C.c_size_t(0)
+    assert lib.bxs_workspace_size(N.MAX_ROWS, 10, C.byref(o), C.byref(b)) == N.BXS_OK and b.value > 0
+    assert lib.bxs_workspace_size(N.MAX_ROWS + 1, 10, C.byref(o), C.byref(b)) == N.BXS_ERR_SHAPE
 
 
 def test_workspace_query_shape_check(lib):

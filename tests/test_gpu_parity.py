@@ -230,3 +230,20 @@ def test_varbatch_parity():
     for P, x, s, info in zip(probs, xs, sats, infos):
         parity_vs_oracle(P, x.cpu().numpy(), s.cpu().numpy(), info, **kw)
     assert status == "ok"
+
+
+@pytest.mark.parametrize("m,n", [(9000, 1200), (16384, 800)])
+def test_large_row_classes(m, n):
+    """The two largest row classes (up to 8192 and 16384 rows, the maximum an
+    instance may have), FP32 storage.  The tolerance stays well above the
+    oracle's rounding floor: its gap has no rounding margins, so once the
+    iteration reaches that floor its sphere becomes smaller than the rounding
+    error of a_j^T theta and its rule is no longer safe (the certified GPU gap
+    carries margins of about 1e-11 at these sizes)."""
+    print(f"\n[large m] m={m} n={n}", flush=True)
+    P = planted(20, m, n, nf_frac=0.02, dtype=np.float32)
+    eta = step_of(P)
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=400, step=eta)
+    xg, sg, info, res = check_parity(P, "bvls", **kw)
+    free = (P.x_true > P.l) & (P.x_true < P.u)
+    assert np.count_nonzero(sg) > 0 and not np.any(sg[free])
