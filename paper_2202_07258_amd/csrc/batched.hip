@@ -88,7 +88,7 @@ __device__ __forceinline__ void split_bf16(float v, short& hi, short& lo) {
 typedef unsigned short u16;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf8v;
 
-constexpr int kG3K = 32, kG3Ld = 40;   // K step; LDS row of 32 bf16 + 16 B pad
+constexpr int kG3K = 32;   // K step (one 16x16x32 MFMA)
 
 struct G3Args {
     const u16* Ahi; const u16* Alo; long long lda;     // Aop, lda = padded K
@@ -102,24 +102,27 @@ struct G3Args {
 
 __device__ __forceinline__ unsigned pack2(u16 a, u16 b) { return (unsigned)a | ((unsigned)b << 16); }
 
-template <int EPI, int TM>
-__global__ __launch_bounds__(256)
+template <int EPI, int TM, int WR, int WC>
+__global__ __launch_bounds__(64 * WR * WC)
 void k_gemm3(G3Args p)
 {
-    constexpr int WT = TM / 2;                 // wave tile (2 x 2 waves)
-    constexpr int NB = WT / 16;                // 16 x 16 blocks per wave and dimension
-    constexpr int NL = TM / 64;                // 16-byte loads per thread and operand part (1 or 2)
-    static_assert(TM == 64 || TM == 128, "tile of 64 or 128");
-    // LDS: the operand tiles of one K step, reused by the epilogue for one
-    // half (WT columns) of the FP32 result tile at a time
-    constexpr int kOpBytes = 4 * TM * kG3Ld * (int)sizeof(u16);
+    constexpr int NT = 64 * WR * WC;           // threads
+    constexpr int WTR = TM / WR, WTC = TM / WC;   // wave tile
+    constexpr int NBR = WTR / 16, NBC = WTC / 16; // 16 x 16 blocks per wave
+    constexpr int NL = 4 * TM / NT;            // 16-byte loads per thread and operand part (1 or 2)
+    static_assert(NL == 1 || NL == 2, "one or two load slots per thread");
+    // LDS: two buffers of the four operand tiles of one K step (rows of 32
+    // bf16 = four 16-byte chunks; chunk c of row r is stored at position
+    // (c + r / 4) mod 4, so 16 lanes reading one chunk of 16 consecutive rows,
+    // and 16 lanes writing four chunks of four rows, hit distinct banks),
+    // reused by the epilogue for CC columns of the FP32 result at a time.
+    constexpr int kTile = TM * kG3K;           // bf16 per operand tile
+    constexpr int kOpBytes = 2 * 4 * kTile * (int)sizeof(u16);
     constexpr int kCLd = TM + 4;
-    constexpr int kCBytes = WT * kCLd * (int)sizeof(float);
-    __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes > kCBytes ? kOpBytes : kCBytes];
-    u16* const sAh = (u16*)smem;
-    u16* const sAl = sAh + TM * kG3Ld;
-    u16* const sBh = sAl + TM * kG3Ld;
-    u16* const sBl = sBh + TM * kG3Ld;
+    constexpr int CC = (kOpBytes / (kCLd * (int)sizeof(float)) >= TM) ? TM : TM / 2;
+    static_assert(CC % WTC == 0 && CC * kCLd * (int)sizeof(float) <= kOpBytes, "epilogue staging fits");
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes];
+    u16* const sbase = (u16*)smem;
     float* const sC = (float*)smem;
     __shared__ int s_act[TM];
     const int tiles = p.tiles_m * p.tiles_n;
@@ -129,14 +132,15 @@ void k_gemm3(G3Args p)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid < TM) s_act[tid] = (col0 + tid < p.nact) ? p.act[col0 + tid] : -1;
     __syncthreads();
+    auto soff = [](int r, int c) { return r * kG3K + 8 * ((c + (r >> 2)) & 3); };
 
     // global -> register slots: NL x 16 B of each of Ahi, Alo, Bhi, Blo per
     // thread.  Columns past the active count read column 0 of Bop: each
     // output column depends on its own Bop column only, and those outputs
     // are never stored.
-    const int kq = 8 * (tid & 3);
-    const int r0 = tid >> 2, r1 = r0 + 64;     // second slot only for TM = 128
-    const int srow0 = r0 * kG3Ld + kq, srow1 = r1 * kG3Ld + kq;
+    const int kc = tid & 3, kq = 8 * kc;
+    const int r0 = tid >> 2, r1 = r0 + NT / 4;   // second slot only when NL = 2
+    const int srow0 = soff(r0, kc), srow1 = soff(r1, kc);
     const u16* const pa0h = p.Ahi + (long long)(row0 + r0) * p.lda + kq;
     const u16* const pa0l = p.Alo + (long long)(row0 + r0) * p.lda + kq;
     const long long bo0 = (long long)max(s_act[r0], 0) * p.ldb + kq;
@@ -153,24 +157,20 @@ void k_gemm3(G3Args p)
         pb1h = p.Bhi + bo1;
         pb1l = p.Blo + bo1;
     }
-    uint4 ga0h = *(const uint4*)pa0h, ga0l = *(const uint4*)pa0l;
-    uint4 gb0h = *(const uint4*)pb0h, gb0l = *(const uint4*)pb0l;
-    uint4 ga1h, ga1l, gb1h, gb1l;
-    if constexpr (NL > 1) {
-        ga1h = *(const uint4*)pa1h; ga1l = *(const uint4*)pa1l;
-        gb1h = *(const uint4*)pb1h; gb1l = *(const uint4*)pb1l;
-    }
-
-    const int wr = wave >> 1, wc = wave & 1;
-    const int lr = lane & 15, lk = 8 * (lane >> 4);
-    f4 acc[NB][NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < p.K; k0 += kG3K) {
-        __syncthreads();                      // every wave is done with the previous K step
+    uint4 ga0h, ga0l, gb0h, gb0l, ga1h, ga1l, gb1h, gb1l;
+    auto gload_step = [&](int k0) {
+        ga0h = *(const uint4*)(pa0h + k0); ga0l = *(const uint4*)(pa0l + k0);
+        gb0h = *(const uint4*)(pb0h + k0); gb0l = *(const uint4*)(pb0l + k0);
+        if constexpr (NL > 1) {
+            ga1h = *(const uint4*)(pa1h + k0); ga1l = *(const uint4*)(pa1l + k0);
+            gb1h = *(const uint4*)(pb1h + k0); gb1l = *(const uint4*)(pb1l + k0);
+        }
+    };
+    auto lds_store = [&](int buf) {
+        u16* const sAh = sbase + (size_t)buf * 4 * kTile;
+        u16* const sAl = sAh + kTile;
+        u16* const sBh = sAl + kTile;
+        u16* const sBl = sBh + kTile;
         *(uint4*)&sAh[srow0] = ga0h;
         *(uint4*)&sAl[srow0] = ga0l;
         *(uint4*)&sBh[srow0] = gb0h;
@@ -181,80 +181,130 @@ void k_gemm3(G3Args p)
             *(uint4*)&sBh[srow1] = gb1h;
             *(uint4*)&sBl[srow1] = gb1l;
         }
-        __syncthreads();
-        const int kn = k0 + kG3K;
-        if (kn < p.K) {                       // next K step in flight during the MFMAs
-            ga0h = *(const uint4*)(pa0h + kn); ga0l = *(const uint4*)(pa0l + kn);
-            gb0h = *(const uint4*)(pb0h + kn); gb0l = *(const uint4*)(pb0l + kn);
-            if constexpr (NL > 1) {
-                ga1h = *(const uint4*)(pa1h + kn); ga1l = *(const uint4*)(pa1l + kn);
-                gb1h = *(const uint4*)(pb1h + kn); gb1l = *(const uint4*)(pb1l + kn);
-            }
-        }
-        bf8v ah[NB], al[NB], bh[NB], bl[NB];
+    };
+
+    const int wr = wave / WC, wc = wave % WC;
+    const int lr = lane & 15, lc = lane >> 4;
+    f4 acc[NBR][NBC];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int ra_ = (wr * WT + q * 16 + lr) * kG3Ld + lk;
-            const int rb_ = (wc * WT + q * 16 + lr) * kG3Ld + lk;
+    for (int a = 0; a < NBR; ++a)
+#pragma unroll
+        for (int b = 0; b < NBC; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    // K steps: step s is multiplied out of buffer s % 2 while step s + 1 is
+    // stored into the other buffer and step s + 2 is loaded into registers;
+    // one barrier per step.
+    gload_step(0);
+    lds_store(0);
+    __syncthreads();
+    if (kG3K < p.K) gload_step(kG3K);
+    for (int k0 = 0, buf = 0; k0 < p.K; k0 += kG3K, buf ^= 1) {
+        const u16* const sAh = sbase + (size_t)buf * 4 * kTile;
+        const u16* const sAl = sAh + kTile;
+        const u16* const sBh = sAl + kTile;
+        const u16* const sBl = sBh + kTile;
+        bf8v ah[NBR], al[NBR], bh[NBC], bl[NBC];
+#pragma unroll
+        for (int q = 0; q < NBR; ++q) {
+            const int ra_ = soff(wr * WTR + q * 16 + lr, lc);
             ah[q] = *(const bf8v*)&sAh[ra_];
             al[q] = *(const bf8v*)&sAl[ra_];
+        }
+#pragma unroll
+        for (int q = 0; q < NBC; ++q) {
+            const int rb_ = soff(wc * WTC + q * 16 + lr, lc);
             bh[q] = *(const bf8v*)&sBh[rb_];
             bl[q] = *(const bf8v*)&sBl[rb_];
         }
+        if (k0 + kG3K < p.K) {
+            lds_store(buf ^ 1);
+            if (k0 + 2 * kG3K < p.K) gload_step(k0 + 2 * kG3K);
+        }
 #pragma unroll
-        for (int a = 0; a < NB; ++a)
+        for (int a = 0; a < NBR; ++a)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
+            for (int b = 0; b < NBC; ++b) {
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
             }
+        __syncthreads();
     }
 
-    // Epilogue, one half of the columns at a time: the waves owning those
-    // columns put their accumulators into LDS (column-major, a lane holds rows
-    // r..r+3 of one column of each 16 x 16 block), then all 256 threads walk
-    // the columns with consecutive lanes on consecutive rows.
+    // Epilogue, CC columns at a time: the waves owning those columns put
+    // their accumulators into LDS (column-major; a lane holds rows r..r+3 of
+    // one column of each 16 x 16 block), then all threads walk the columns
+    // with consecutive lanes on consecutive rows.
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        __syncthreads();                      // LDS free (operand tiles or previous half)
-        if (wc == h) {
+    for (int h = 0; h < TM / CC; ++h) {
+        if (h > 0) __syncthreads();           // previous chunk fully consumed
+        if ((wc * WTC) / CC == h) {
 #pragma unroll
-            for (int cb = 0; cb < NB; ++cb)
+            for (int cb = 0; cb < NBC; ++cb)
 #pragma unroll
-                for (int a = 0; a < NB; ++a)
-                    *(f4*)&sC[(cb * 16 + lr) * kCLd + wr * WT + a * 16 + 4 * (lane >> 4)] = acc[a][cb];
+                for (int a = 0; a < NBR; ++a)
+                    *(f4*)&sC[(wc * WTC - h * CC + cb * 16 + lr) * kCLd + wr * WTR + a * 16 + 4 * lc] = acc[a][cb];
         }
         __syncthreads();
-        for (int idx = tid; idx < WT * TM; idx += 256) {
-            const int cl = idx / TM, rl = idx % TM;
-            const int b = s_act[h * WT + cl];
-            if (b < 0) break;                 // inactive columns are the last ones of the tile
-            const int j = row0 + rl;
-            const float val = sC[cl * kCLd + rl];
-            if (EPI == 0) {
+        if (EPI == 0) {
+            for (int idx = tid; idx < CC * TM; idx += NT) {
+                const int cl = idx / TM, rl = idx % TM;
+                const int b = s_act[h * CC + cl];
+                if (b < 0) break;             // inactive columns are the last ones of the tile
+                const int j = row0 + rl;
                 short hh, ll;
-                split_bf16(val, hh, ll);
+                split_bf16(sC[cl * kCLd + rl], hh, ll);
                 p.Ohi[(long long)b * p.ldo + j] = (u16)hh;
                 p.Olo[(long long)b * p.ldo + j] = (u16)ll;
-            } else if (j < p.n) {
-                const long long e = j + (long long)b * p.n;
-                const float g = p.G[e] - val;
-                p.G[e] = g;
-                const double xo = p.X[e];
-                const double xn = (p.sat[j + (long long)b * p.ldsat] != 0) ? 0.0 : fmax(0.0, xo + p.eta * (double)g);
-                p.X[e] = xn;
-                short hh, ll;
-                split_bf16((float)(xn - xo), hh, ll);
-                p.Ohi[(long long)b * p.ldo + j] = (u16)hh;
-                p.Olo[(long long)b * p.ldo + j] = (u16)ll;
+            }
+        } else {
+            // EU elements per thread at a time: every load of the batch is
+            // issued before the first element is updated
+            constexpr int EU = 4;
+            for (int base = tid; base < CC * TM; base += NT * EU) {
+                long long e[EU];
+                bool ok[EU];
+                float gv[EU];
+                double xv[EU];
+                signed char sv[EU];
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    const int idx = base + NT * u;
+                    const int cl = idx / TM, rl = idx % TM;
+                    const int b = (idx < CC * TM) ? s_act[h * CC + cl] : -1;
+                    const int j = row0 + rl;
+                    ok[u] = b >= 0 && j < p.n;
+                    const long long bb = ok[u] ? b : 0;
+                    const int jj = ok[u] ? j : 0;
+                    e[u] = jj + bb * p.n;
+                    gv[u] = p.G[e[u]];
+                    xv[u] = p.X[e[u]];
+                    sv[u] = p.sat[jj + bb * p.ldsat];
+                }
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    if (!ok[u]) continue;
+                    const int idx = base + NT * u;
+                    const int cl = idx / TM, rl = idx % TM;
+                    const int b = s_act[h * CC + cl];
+                    const int j = row0 + rl;
+                    const float g = gv[u] - sC[cl * kCLd + rl];
+                    p.G[e[u]] = g;
+                    const double xn = (sv[u] != 0) ? 0.0 : fmax(0.0, xv[u] + p.eta * (double)g);
+                    p.X[e[u]] = xn;
+                    short hh, ll;
+                    split_bf16((float)(xn - xv[u]), hh, ll);
+                    p.Ohi[(long long)b * p.ldo + j] = (u16)hh;
+                    p.Olo[(long long)b * p.ldo + j] = (u16)ll;
+                }
             }
         }
     }
 }
 
-// Launch one GEMM of an iteration with 128 x 128 tiles, or 64 x 64 tiles when
-// the larger ones would leave most of the chip idle (fewer tiles than CUs).
+// Launch one GEMM of an iteration: 128 x 128 tiles on 8 waves, or 64 x 64
+// tiles on 4 waves when the larger ones would leave most of the chip idle
+// (fewer tiles than CUs).
 template <int EPI>
 static void launch_gemm3(G3Args g, long Mpad, int nact, int cus, hipStream_t s)
 {
@@ -262,11 +312,11 @@ static void launch_gemm3(G3Args g, long Mpad, int nact, int cus, hipStream_t s)
     if (t128 >= cus) {
         g.tiles_m = (int)(Mpad / 128);
         g.tiles_n = (nact + 127) / 128;
-        k_gemm3<EPI, 128><<<g.tiles_m * g.tiles_n, 256, 0, s>>>(g);
+        k_gemm3<EPI, 128, 2, 4><<<g.tiles_m * g.tiles_n, 512, 0, s>>>(g);
     } else {
         g.tiles_m = (int)(Mpad / 64);
         g.tiles_n = (nact + 63) / 64;
-        k_gemm3<EPI, 64><<<g.tiles_m * g.tiles_n, 256, 0, s>>>(g);
+        k_gemm3<EPI, 64, 2, 2><<<g.tiles_m * g.tiles_n, 256, 0, s>>>(g);
     }
 }
 
