@@ -189,6 +189,15 @@ bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi,
 int        bxs_row_class(long m);            /* -1 if m > BXS_MAX_ROWS */
 int        bxs_sweep_variant_for_rows(long m); /* variant later calls use for m rows, -1 if none */
 bxs_status bxs_set_sweep_variant(int row_class, int v);
+/* Tuning: the work items of an instance (blocks of preserved columns, one
+ * workgroup each, one partial product each) are spread over scale x the
+ * chip's resident workgroups, shared among the instances of a call in
+ * proportion to m*n.  A smaller scale gives fewer, longer items (less
+ * partial-product traffic, less parallelism).  scale in [1/64, 4], default 1;
+ * process-wide per row class; set before the solve that should use it.
+ * Returns BXS_ERR_ARG for a bad class or scale. */
+bxs_status bxs_set_group_scale(int row_class, double scale);
+double bxs_group_scale(int row_class);   /* current scale, 0 for a bad class */
 
 /* Batched non-negative LS with one shared matrix (Alg. 2 for every column
  * y_b of Y):  min 1/2 ||A x_b - y_b||^2  s.t. x_b >= 0,  b = 0..B-1.

@@ -144,8 +144,12 @@ static int device_cus()
 }
 
 // Sweep-variant preference per row-count class (the smallest default
-// variant whose capacity holds m); set by bxs_set_sweep_variant.
-static int g_variant_pref[kNumDefaultVariants] = {0, 1, 2, 3, 4, 21, 18, 28, 29};
+// variant whose capacity holds m); set by bxs_set_sweep_variant.  Defaults:
+// for m up to 512 the narrow shapes that pack several columns per workgroup
+// (best for batches of small instances); above, the autotuner's choices on
+// one MI355X for a single instance with the class's largest row count and
+// four times as many columns (up to 256 MB).
+static int g_variant_pref[kNumDefaultVariants] = {0, 1, 2, 3, 12, 12, 18, 28, 29};
 
 static int choose_variant(long m)
 {
@@ -158,6 +162,13 @@ static int choose_variant(long m)
 // Work-group targets: spread the columns of each instance over a share of
 // the chip's resident workgroups (CUs x kThreadsPerCU / workgroup size)
 // proportional to its size m*n, at least one.
+// Fraction of the chip's resident workgroups an instance's work items are
+// spread over, per row class (fewer, longer items write fewer partial
+// products; set by bxs_set_group_scale).  Defaults from the autotuner on one
+// MI355X, as for the shapes; for 4000 x 16000 the spread 0.5 gives one
+// workgroup of 64 columns per CU (43 us per sweep against 49 us at 1).
+static double g_group_scale[kNumDefaultVariants] = {1, 1, 1, 1, 1, 0.5, 0.5, 1, 1};
+
 static std::vector<int> group_targets(const std::vector<InstSpec>& specs, const std::vector<int>& variant, int cus)
 {
     double total = 0.0;
@@ -166,7 +177,9 @@ static std::vector<int> group_targets(const std::vector<InstSpec>& specs, const 
     for (size_t i = 0; i < specs.size(); ++i) {
         const double share = total > 0 ? (double)specs[i].m * (double)specs[i].n / total : 1.0;
         const int wg = kVariants[variant[i]].tpc * kVariants[variant[i]].ng;
-        const double resident = (double)cus * std::max(1, kThreadsPerCU / wg);
+        const int cls = default_variant_for_rows(specs[i].m);
+        const double scale = (cls >= 0) ? g_group_scale[cls] : 1.0;
+        const double resident = (double)cus * std::max(1, kThreadsPerCU / wg) * scale;
         g[i] = std::max(1, (int)ceil(resident * share));
     }
     return g;
@@ -696,6 +709,19 @@ bxs_status bxs_set_sweep_variant(int row_class, int v)
                     variant_capacity(row_class));
     g_variant_pref[row_class] = v;
     return BXS_OK;
+}
+
+bxs_status bxs_set_group_scale(int row_class, double scale)
+{
+    if (row_class < 0 || row_class >= kNumDefaultVariants) return fail(BXS_ERR_ARG, "row class %d out of range", row_class);
+    if (!(scale >= 1.0 / 64.0 && scale <= 4.0)) return fail(BXS_ERR_ARG, "group scale %g outside [1/64, 4]", scale);
+    g_group_scale[row_class] = scale;
+    return BXS_OK;
+}
+
+double bxs_group_scale(int row_class)
+{
+    return (row_class >= 0 && row_class < kNumDefaultVariants) ? g_group_scale[row_class] : 0.0;
 }
 
 const char* bxs_version(void) { return "boxscreen 0.1.0 (gfx950)"; }

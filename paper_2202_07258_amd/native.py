@@ -59,7 +59,7 @@ class Problem(C.Structure):
 EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls",
             "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
             "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant",
-            "bxs_sweep_variant_for_rows",
+            "bxs_sweep_variant_for_rows", "bxs_set_group_scale", "bxs_group_scale",
             "solve_nnls_batched_shared", "bxs_workspace_size_batched", "nnls_adjoint",
             "bxs_workspace_size_adjoint"]
 
@@ -104,6 +104,10 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     lib.bxs_row_class.restype = C.c_int
     lib.bxs_set_sweep_variant.argtypes = [C.c_int, C.c_int]
     lib.bxs_set_sweep_variant.restype = C.c_int
+    lib.bxs_set_group_scale.argtypes = [C.c_int, C.c_double]
+    lib.bxs_set_group_scale.restype = C.c_int
+    lib.bxs_group_scale.argtypes = [C.c_int]
+    lib.bxs_group_scale.restype = C.c_double
     lib.solve_nnls_batched_shared.argtypes = [C.c_long, C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long,
                                               C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p, C.c_long,
                                               C.POINTER(Opts), C.POINTER(Info)]
@@ -322,6 +326,19 @@ def set_sweep_variant(row_class_: int, variant: int) -> None:
     st = lib.bxs_set_sweep_variant(int(row_class_), int(variant))
     if st != BXS_OK:
         _raise(lib, st)
+
+
+def set_group_scale(row_class_: int, scale: float) -> None:
+    """Spread the work items of instances of this row class over `scale` x the
+    chip's resident workgroups (fewer, longer items for scale < 1)."""
+    lib = load()
+    st = lib.bxs_set_group_scale(int(row_class_), float(scale))
+    if st != BXS_OK:
+        _raise(lib, st)
+
+
+def group_scale(row_class_: int) -> float:
+    return float(load().bxs_group_scale(int(row_class_)))
 
 
 def solve_nnls_batched_shared(A, Y, X0=None, **kw):

@@ -89,6 +89,15 @@ def test_null_arguments(lib):
     assert lib.solve_bvls_varbatch(0, 0, None, C.byref(o), None) == N.BXS_ERR_ARG
 
 
+def test_group_scale_setter(lib):
+    assert lib.bxs_set_group_scale(0, 0.001) == N.BXS_ERR_ARG
+    assert lib.bxs_set_group_scale(0, 5.0) == N.BXS_ERR_ARG
+    assert lib.bxs_set_group_scale(99, 1.0) == N.BXS_ERR_ARG
+    assert lib.bxs_group_scale(99) == 0.0
+    assert lib.bxs_set_group_scale(3, 0.25) == N.BXS_OK and lib.bxs_group_scale(3) == 0.25
+    assert lib.bxs_set_group_scale(3, 1.0) == N.BXS_OK and lib.bxs_group_scale(3) == 1.0
+
+
 def test_workspace_query_row_limit(lib):
     o = N.Opts()
     lib.bxs_default_opts(C.byref(o))

@@ -26,6 +26,7 @@ def test_autotune_installs_valid_shapes_and_keeps_parity():
             assert row["best"] == min(row["us"], key=row["us"].get)
             assert N.variant_for_rows(m) == row["best"]
             assert all(t > 0 for t in row["us"].values())
+            assert row["scale"] in row["scale_us"] and N.group_scale(c) == row["scale"]
         # a solve with the tuned shapes (class 3: 257..512 rows) matches the oracle
         P = planted(77, 400, 900, dtype=np.float32, box=(-1.0, 1.0))
         eta = 1.0 / (1.05 * ob.lipschitz(P.A64()))
@@ -37,3 +38,4 @@ def test_autotune_installs_valid_shapes_and_keeps_parity():
     finally:
         for c, v in before.items():
             N.set_sweep_variant(c, v)
+            N.set_group_scale(c, 1.0)
