@@ -142,6 +142,7 @@ def bench_c3(args, device):
            "note": "PG on this matrix (L ~ 3.1e3, nearly parallel columns) cannot reach gap 1e-6 in any "
                    "practical budget; both engines run the same budget and follow the same trajectory"}
     res = {}
+    keep = {}
     for prec in ["bf16x3", "f64"]:
         kw = dict(iter_precision=prec, screen_every=10, eps_gap=1e-6, max_iter=iters, profile=True)
         bx.solve_nnls_batched_shared(dA, dY, **dict(kw, max_iter=10))
@@ -171,9 +172,12 @@ def bench_c3(args, device):
                              "unit": "TFLOP/s", "frac": round(r["useful_tflops"] / FP64_PEAK_TFLOPS, 4),
                              "traffic": None, "kernel": "rocBLAS DGEMM pair"}
         res[prec] = r
-        del X, S
+        keep[prec] = X
+        keep[prec + "_gaps"] = gaps
+        del S
         torch.cuda.empty_cache()
     res["bf16x3_speedup_vs_f64"] = round(res["f64"]["seconds"] / res["bf16x3"]["seconds"], 3)
+    res["bf16x3_max_abs_diff_vs_f64_engine"] = float((keep["bf16x3"] - keep["f64"]).abs().max())
     out.update(res)
     if not args.no_cpu_baseline:
         from oracle import boxls as ob
@@ -186,6 +190,17 @@ def bench_c3(args, device):
         dtc = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(nb * iters / dtc, 1), "unit": "rhs_iters/s", "cores": _cores(),
                                "kind": "oracle", "sample": f"{nb} right-hand sides x {iters} iterations"}
+        # the oracle's own FP64 gap (eq. Dual_Gap, t = -1) at sampled BF16x3 solutions
+        Xb = keep["bf16x3"].cpu().numpy()
+        sample = np.random.default_rng(5).choice(B, size=4, replace=False)
+        gaps = []
+        for b in sample:
+            x = Xb[:, b]
+            theta, _, _ = ob.dual_point(A64, Y[:, b], np.full(4096, np.inf), x, -np.ones(1024))
+            gaps.append(ob.duality_gap(A64, Y[:, b], np.zeros(4096), np.full(4096, np.inf), x, theta))
+        # the GPU's certified gap is an upper bound on the exact one at its own x
+        out["bf16x3_gap_check_sampled"] = {"rhs": [int(b) for b in sample], "oracle_fp64_gap": gaps,
+                                           "gpu_certified_gap": [float(keep["bf16x3_gaps"][b]) for b in sample]}
     return out
 
 

@@ -247,3 +247,20 @@ def test_large_row_classes(m, n):
     xg, sg, info, res = check_parity(P, "bvls", **kw)
     free = (P.x_true > P.l) & (P.x_true < P.u)
     assert np.count_nonzero(sg) > 0 and not np.any(sg[free])
+
+
+@pytest.mark.parametrize("scale", [0.015625, 4.0])
+def test_work_item_spread_extremes(scale):
+    """The tuning knob that sets how many work items (and partial products) an
+    instance is split into does not change the result: parity at the
+    smallest and largest spread (one long item, and the 4-column minimum)."""
+    from paper_2202_07258_amd import native as N
+    P = planted(21, 700, 2600, dtype=np.float32)
+    cls = N.row_class(P.m)
+    before = N.group_scale(cls)
+    try:
+        N.set_group_scale(cls, scale)
+        eta = step_of(P)
+        check_parity(P, "bvls", screen_every=10, eps_gap=1e-8, max_iter=3000, step=eta)
+    finally:
+        N.set_group_scale(cls, before)
