@@ -68,15 +68,17 @@ def time_solves(dev_inputs, steps, warmup, **kw):
 def sweep_roofline(infos, m, elem_bytes):
     """Algorithmic bytes of one fused PG sweep launch: every preserved column
     once (m * elem_bytes), its x read and write, l, u and index (36 B), plus
-    the residual m-vector (8 m).  Duration: HIP events recorded on the solve's
-    stream around each launch (dispatch included)."""
+    the residual m-vector (8 m), with the preserved-set size averaged over
+    the solve's iterations (the timed launches are all but the first of each
+    screening pass).  Duration: HIP events recorded on the solve's stream
+    around each launch (dispatch included)."""
     col_iters = sum(i["col_iters"] for i in infos)
+    iters = sum(i["iters"] for i in infos)
     launches = sum(i["sweep_launches"] for i in infos)
     ms = sum(i["sweep_ms"] for i in infos)
-    if launches == 0 or ms <= 0:
+    if launches == 0 or ms <= 0 or iters == 0:
         return None
-    bytes_total = col_iters * (m * elem_bytes + 36) + launches * 8 * m
-    per_launch = bytes_total / launches
+    per_launch = col_iters / iters * (m * elem_bytes + 36) + 8 * m
     avg_s = ms * 1e-3 / launches
     # the event pair around a launch also spans its dispatch, so this duration
     # is an upper bound of the kernel's own (reported: the same pair's elapsed

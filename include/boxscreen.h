@@ -86,8 +86,12 @@ typedef struct {
     int     screen_every;    /* K >= 1: PG steps or CD sweeps between two screening passes     */
     long    max_iter;        /* >= 1: iteration budget (PG steps or CD sweeps)                  */
     double  eps_gap;         /* >= 0: absolute gap tolerance (stop when gap < eps_gap)          */
-    double  step;            /* PG step; <= 0 selects 1/(1.05 L), L from power iteration        */
-    int     power_iters;     /* power-iteration count for L (<= 0: 20)                          */
+    double  step;            /* PG step; <= 0 selects 1/(1.05 L_est), see power_iters          */
+    int     power_iters;     /* steps of the estimate of L = ||A||_2^2 when step <= 0, at most 64.
+                                solve_bvls / solve_nnls / solve_bvls_varbatch: Lanczos steps on
+                                A A^T, each one pass over A (<= 0: 8); the step is
+                                1 / (1.05 L_est) with L_est the largest Ritz value (<= L).
+                                Batched shared-matrix solver: power iterations (<= 0: 20).    */
     const double* t;         /* device m-vector translation direction for the u_j = +inf
                                 columns (Sec. 4.2); NULL means t = -1 (Sec. 5).  If some
                                 preserved column has a_j^T t >= 0 the library falls back to
@@ -120,12 +124,14 @@ typedef struct {
     double radius;      /* last safe radius                                             */
     double eps;         /* last translation coefficient                                 */
     double step;        /* PG step used                                                 */
-    double lipschitz;   /* power-iteration estimate of ||A||_2^2 (0 if step was given)  */
+    double lipschitz;   /* estimate of ||A||_2^2, a lower bound (0 if step was given)   */
     double ms_setup;    /* device time of the setup phase (column norms, A^T t, L)      */
     double ms_solve;    /* device time of the iterations and screening passes           */
     long   col_iters;   /* sum over primal iterations of the preserved-set size         */
     double sweep_ms;    /* opts->profile: summed duration of the primal-iteration sweep
-                           launches (PG: fused A^T r / update / A x; CD: the sweep;
+                           launches (PG: fused A^T r / update / A x, all but the first
+                           of each screening pass, which returns at once when the
+                           previous pass already took that step; CD: the sweep;
                            batched solver: the pair of iteration GEMMs)               */
     long   sweep_launches; /* opts->profile: number of timed sweep launches             */
     double event_overhead_ms; /* opts->profile: average HIP-event elapsed time around an

@@ -111,7 +111,7 @@ struct PlanSizes {
 };
 
 // Per-instance device bytes.
-static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap)
+static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap, int lz_steps)
 {
     PlanSizes p;
     p.g_target = g_target;
@@ -119,12 +119,13 @@ static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap)
     cap = std::min<long>(cap, (n + kCbMin - 1) / kCbMin);
     p.items_cap = (int)std::max<long>(cap, 1);
     size_t b = 0;
-    b += align_up(sizeof(double) * 2 * m, 256);                   // yp, r
-    b += align_up(sizeof(double) * 6 * n, 256);                   // g, w, cn, cn2, fval, fdx
+    b += align_up(sizeof(double) * 3 * m, 256);                   // yp, r, r2
+    b += align_up(sizeof(double) * 7 * n, 256);                   // g, w, cn, cn2, fval, fdx, xs
     b += align_up(sizeof(int) * 2 * n, 256);                      // idx, fidx
     b += align_up(sizeof(double) * 2 * (size_t)p.items_cap * m, 256);  // part, part2
     b += align_up(sizeof(double) * kItemScalars * p.items_cap, 256);  // iscal
     b += align_up(sizeof(bxs_pass_record) * std::max<long>(rec_cap, 0), 256);
+    if (lz_steps > 0) b += align_up(sizeof(double) * (2 * (size_t)lz_steps + 2 * m), 256);  // Lanczos
     p.bytes = b;
     return p;
 }
@@ -209,7 +210,16 @@ static bxs_status check_opts(const bxs_opts* o)
     if (o->history && o->history_cap < 0) return fail(BXS_ERR_ARG, "history_cap < 0");
     if (o->iter_precision != BXS_ITER_F64 && o->iter_precision != BXS_ITER_BF16X3)
         return fail(BXS_ERR_ARG, "unknown iter_precision %d", o->iter_precision);
+    if (o->power_iters > kLanczosMax) return fail(BXS_ERR_ARG, "power_iters must be <= %d", kLanczosMax);
     return BXS_OK;
+}
+
+// Lanczos steps of the ||A||_2^2 estimate of the sweep solvers (0 when the
+// caller gives the step).
+static int lanczos_steps(const bxs_opts* o)
+{
+    if (o->step > 0.0) return 0;
+    return o->power_iters > 0 ? o->power_iters : kLanczosDefault;
 }
 
 static bxs_status check_spec(const InstSpec& s, long i)
@@ -231,11 +241,12 @@ struct Plan {
     std::vector<int> cd_list[kNumCdBuckets];
     std::vector<int> variant;                // sweep variant per instance
     long rec_cap = 0;
+    int lz_steps = 0;
     int vec = 1;
     size_t bytes = 0;
 };
 
-static bxs_status build_plan(Plan& P, int dtype, long rec_cap)
+static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps)
 {
     const long count = (long)P.specs.size();
     const int cus = device_cus();
@@ -243,6 +254,7 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap)
     for (long i = 0; i < count; ++i) P.variant[i] = choose_variant(P.specs[i].m);
     std::vector<int> g = group_targets(P.specs, P.variant, cus);
     P.rec_cap = rec_cap;
+    P.lz_steps = lz_steps;
     P.sizes.resize(count);
     long total_items = 0;
     size_t inst_bytes = 0;
@@ -251,7 +263,7 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap)
     P.vec = 1;
     for (long i = 0; i < count; ++i) {
         const InstSpec& s = P.specs[i];
-        P.sizes[i] = instance_sizes(s.m, s.n, g[i], (i == 0 && count == 1) ? rec_cap : 0);
+        P.sizes[i] = instance_sizes(s.m, s.n, g[i], (i == 0 && count == 1) ? rec_cap : 0, lz_steps);
         total_items += P.sizes[i].items_cap;
         inst_bytes += P.sizes[i].bytes;
         if ((s.lda % vecw) != 0 || ((uintptr_t)s.A % 16) != 0) P.vec = 0;
@@ -290,11 +302,12 @@ static void layout(Plan& P, char* base)
         memset(&I, 0, sizeof(I));
         I.A = s.A; I.lda = s.lda; I.m = (int)s.m; I.n = (int)s.n;
         I.y = s.y; I.l = s.l; I.u = s.u; I.t = nullptr; I.x = s.x; I.sat = s.sat;
-        I.yp = (double*)take(sizeof(double) * 2 * s.m);
+        I.yp = (double*)take(sizeof(double) * 3 * s.m);
         I.r = I.yp + s.m;
-        double* nv = (double*)take(sizeof(double) * 6 * s.n);
+        I.r2 = I.yp + 2 * s.m;
+        double* nv = (double*)take(sizeof(double) * 7 * s.n);
         I.g = nv; I.w = nv + s.n; I.cn = nv + 2 * s.n; I.cn2 = nv + 3 * s.n;
-        I.fval = nv + 4 * s.n; I.fdx = nv + 5 * s.n;
+        I.fval = nv + 4 * s.n; I.fdx = nv + 5 * s.n; I.xs = nv + 6 * s.n;
         int* iv = (int*)take(sizeof(int) * 2 * s.n);
         I.idx = iv; I.fidx = iv + s.n;
         I.part = (double*)take(sizeof(double) * 2 * (size_t)z.items_cap * s.m);
@@ -305,6 +318,8 @@ static void layout(Plan& P, char* base)
         I.rec_cap = (int)rc;
         I.items_cap = z.items_cap;
         I.g_target = z.g_target;
+        I.lz_steps = P.lz_steps;
+        I.lz = P.lz_steps > 0 ? (double*)take(sizeof(double) * (2 * (size_t)P.lz_steps + 2 * s.m)) : nullptr;
         const int b = P.variant[i];
         I.item_base = (int)P.items[b].size();
         for (int t = 0; t < z.items_cap; ++t) P.items[b].push_back(Item{(int)i, t});
@@ -461,12 +476,13 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_colstats(c, b, D.items[b], D.n_items[b]));
     const bool do_pow = !(o->step > 0.0);
     if (do_pow) {
+        // Lanczos on A A^T from a fixed unit vector: one sweep per step
         BXS_HIP(launch_pow_init(c, (int)count));
-        const int np = o->power_iters > 0 ? o->power_iters : 20;
+        const int np = P.lz_steps;
         for (int k = 0; k < np; ++k) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModePow, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedPow, D.ritems, D.n_ritems));
-            BXS_HIP(launch_pow_normalize(c, (int)count, k == np - 1, 0.0));
+            BXS_HIP(launch_lanczos(c, (int)count, k, k == np - 1));
         }
     } else {
         BXS_HIP(launch_set_step(c, (int)count, o->step));
@@ -519,25 +535,38 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
 
     // The kernels of one pass: kk primal iterations, the correlation sweep,
     // the screening kernel and the fold.  `slot` selects the profile events.
+    // PG: the correlation sweep also takes the next step from the screening
+    // point (kModePGS); when the screening kernel keeps that step, the first
+    // iteration of the next pass returns at once, so a pass reads A kk times
+    // instead of kk + 1.  Every iterate is the one of the plain order (test,
+    // fold, step): the step is only kept when the test fixed nothing.
+    const bool pg = o->solver == BXS_PG;
     auto enqueue_kernels = [&](int slot, long long kk, int final_pass) -> bxs_status {
         for (long long k = 0; k < kk; ++k) {
+            const int first = (k == 0) ? 1 : 0;
             if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k], stream));
-            if (o->solver == BXS_PG) {
-                for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModePG, D.items[b], D.n_items[b]));
+            if (pg) {
+                for (int b = 0; b < kNumVariants; ++b)
+                    BXS_HIP(launch_sweep(c, b, kModePG, D.items[b], D.n_items[b], first));
             } else {
                 for (int b = 0; b < kNumCdBuckets; ++b) BXS_HIP(launch_cd(c, b, D.lists[b], D.n_list[b], 1));
             }
             if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k + 1], stream));
-            if (o->solver == BXS_PG) {
-                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+            if (pg) {
+                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, first));
             } else {
                 // fresh residual from the updated iterate
                 for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
                 BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
             }
         }
-        for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
-        BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk));
+        if (pg) {
+            for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModePGS, D.items[b], D.n_items[b]));
+            BXS_HIP(launch_reduce(c, kRedAhead, D.ritems, D.n_ritems));
+        } else {
+            for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
+        }
+        BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk, pg ? 1 : 0));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));
@@ -599,6 +628,9 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         BXS_HIP(hipEventSynchronize(dev_done[slot]));
         if (o->profile) {
             for (long long k = 0; k < slot_kk[slot]; ++k) {
+                // PG: the first sweep of a pass returns at once when the step
+                // was taken ahead, so it is left out of the timing
+                if (pg && k == 0 && K > 1) continue;
                 float ms = 0.f;
                 BXS_HIP(hipEventElapsedTime(&ms, pev[(size_t)slot * 2 * K + 2 * k], pev[(size_t)slot * 2 * K + 2 * k + 1]));
                 sweep_ms += ms;
@@ -675,7 +707,7 @@ void bxs_default_opts(bxs_opts* o)
     o->max_iter = 100000;
     o->eps_gap = 1e-6;
     o->step = 0.0;
-    o->power_iters = 20;
+    o->power_iters = 0;
     o->graph = 1;
 }
 
@@ -739,7 +771,7 @@ bxs_status bxs_workspace_size_batch(long count, const long* m, const long* n, co
         sp.m = m[i]; sp.n = n[i]; sp.lda = m[i];
         if (sp.m < 1 || sp.n < 1 || sp.m > BXS_MAX_ROWS) return fail(BXS_ERR_SHAPE, "problem %ld: bad shape", i);
     }
-    build_plan(P, BXS_F64, (count == 1 && opts->history) ? opts->history_cap : 0);
+    build_plan(P, BXS_F64, (count == 1 && opts->history) ? opts->history_cap : 0, lanczos_steps(opts));
     *bytes = P.bytes;
     return BXS_OK;
 }
@@ -762,7 +794,7 @@ static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const 
     Plan P;
     P.specs = specs;
     const long rc = (specs.size() == 1 && opts->history) ? opts->history_cap : 0;
-    s = build_plan(P, a_dtype, rc);
+    s = build_plan(P, a_dtype, rc, lanczos_steps(opts));
     if (s != BXS_OK) return s;
     return run(P, a_dtype, opts, opts->t, infos, opts->history, opts->history_cap);
 }

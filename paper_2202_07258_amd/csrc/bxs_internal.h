@@ -20,6 +20,10 @@ namespace bxs {
 constexpr int kCbMin = 4;
 constexpr int kCbMax = 256;
 
+// Lanczos steps of the ||A||_2^2 estimate when the caller gives no step.
+constexpr int kLanczosDefault = 8;
+constexpr int kLanczosMax = 64;
+
 struct Inst {
     const void* A;          // column-major, element type given by the launch
     long long lda;
@@ -31,7 +35,9 @@ struct Inst {
     double* x;              // [n] caller iterate (original index space)
     signed char* sat;       // [n]
     double* yp;             // [m] data with the screened part folded in (Remark 3)
-    double* r;              // [m] residual yp - A_P x_P (or power-iteration vector)
+    double* r;              // [m] residual yp - A_P x_P (or the Lanczos vector)
+    double* r2;             // [m] residual after the step taken ahead of a screening test
+    double* xs;             // [n] iterate at the screening point (before that step)
     double* g;              // [n] correlations a_j^T r
     double* w;              // [n] a_j^T t
     double* cn;             // [n] rigorous upper bound of ||a_j||_2
@@ -42,12 +48,14 @@ struct Inst {
     double* fdx;            // [n] bound value minus the iterate before fixing
     double* part;           // [items_cap * m] partial A-products per work item
     double* part2;          // [items_cap * m] second partial (fold pass only)
-    double* iscal;          // [items_cap * kItemScalars] per-item scalars (power iteration, screening)
+    double* iscal;          // [items_cap * kItemScalars] per-item scalars of the screening pass
     bxs_pass_record* rec;   // [rec_cap] per-pass records
     int rec_cap;
     int items_cap;          // ceil(n / kCbMin): grid extent reserved for this instance
     int g_target;           // workgroups the instance should spread over
     int item_base;          // first work item of this instance in its bucket list
+    int lz_steps;           // Lanczos steps of the ||A||_2^2 estimate (0: step given)
+    double* lz;             // [2 lz_steps + 2 m] alpha, beta, q_k, q_{k-1}
 };
 
 struct State {
@@ -61,11 +69,11 @@ struct State {
     int err;                // input-validation flags (kErr*)
     int passes;
     int n_lower, n_upper;
-    int pad_;
+    int ahead;              // 1: the step after the last screening pass is already taken
     long long iters;        // iterations done when the instance stopped
     long long col_iters;    // sum over primal iterations of n_active
     double step;            // PG step
-    double lipschitz;       // power-iteration estimate of ||A||_2^2
+    double lipschitz;       // Lanczos estimate of ||A||_2^2
     double gap, radius, eps, primal;
     double tnorm;           // upper bound of ||t||_2
     double ynorm;           // upper bound of ||y||_2
@@ -75,7 +83,7 @@ struct State {
 // Per-item scalars written by the correlation sweep for the screening pass:
 // sum |x_j| ||a_j||, interior flag of t, largest translation ratio, presence
 // of u_j = +inf columns, gap terms at eps = 0, largest screening score at
-// eps = 0.  The power iteration uses slot 0.
+// eps = 0.
 constexpr int kItemScalars = 8;
 enum ItemScalar : int { kIsMass = 0, kIsTv = 1, kIsEmax = 2, kIsHasInf = 3, kIsGap0 = 4, kIsZmax0 = 5 };
 
@@ -99,13 +107,16 @@ enum SweepMode : int {
     kModeCorr = 1,          // g = A^T r stored
     kModeAx = 2,            // partial += A x
     kModeFold = 3,          // partial += A_S b_S, partial2 += A_S (b_S - x_S)
-    kModePow = 4            // g = A^T r, partial += A g, iscal += ||g||^2
+    kModePow = 4,           // g = A^T r, partial += A g (one product with A A^T)
+    kModePGS = 5            // kModeCorr at x and the kModePG step from x in one pass;
+                            // x is kept in xs, g stored
 };
 
 enum ReduceMode : int {
     kRedResidual = 0,       // r = yp - sum
     kRedFold = 1,           // yp -= sum, r -= sum2
-    kRedPow = 2             // r = sum
+    kRedPow = 2,            // r = sum (= A A^T r)
+    kRedAhead = 3           // r2 = yp - sum
 };
 
 // gamma_k = k u / (1 - k u), u = 2^-53: the standard bound on the relative
@@ -205,13 +216,17 @@ struct LaunchCtx {
 
 hipError_t launch_init(const LaunchCtx& c, int count, const double* x0_is_given);
 hipError_t launch_colstats(const LaunchCtx& c, int variant, const Item* items, int n_items);
-hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items);
-hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems);
+// first = 1 marks the first primal iteration of a pass: its sweep and
+// reduction return at once for instances whose step was already taken by
+// the kModePGS sweep of the previous pass.
+hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items,
+                        int first = 0);
+hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems, int first = 0);
 hipError_t launch_pow_init(const LaunchCtx& c, int count);
 hipError_t launch_set_step(const LaunchCtx& c, int count, double step);
-hipError_t launch_pow_normalize(const LaunchCtx& c, int count, int last, double user_step);
+hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last);
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening,
-                         int final_pass, int K, int kk);
+                         int final_pass, int K, int kk, int ahead);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
 
 }  // namespace bxs

@@ -1,6 +1,6 @@
 // gfx950 kernels of the boxscreen library: column sweeps (the matrix-vector
 // products of the projected-gradient step, the correlations A^T r, the fold of
-// screened columns, power iteration), their deterministic partial reductions,
+// screened columns, products with A A^T), their deterministic partial reductions,
 // per-column statistics, the screening pass (dual point, gap, safe rule,
 // stream compaction) and the coordinate-descent sweep.
 //
@@ -199,13 +199,22 @@ __device__ __forceinline__ int lane_of_col(int c) { return c << (6 - Log2C<CBI>:
 // product in registers.  Columns of the next round are loaded before the
 // current round's dot products are reduced (software pipeline), so a barrier
 // never drains the memory queue.
+//
+// kModePGS reads every column once for both the screening test at the
+// current iterate x (correlations g = A^T r and the per-column gap terms)
+// and the next projected-gradient step from x, which needs the same g: the
+// step is taken ahead of the test.  x is kept in xs and the new residual goes
+// to r2, so the screening pass can either keep the step (nothing screened,
+// no stop) or return to x.
 // ---------------------------------------------------------------------------
 template <typename TA, int TPC, int NG, int R, int V, int CBI, int PD, int MODE>
 __global__ __launch_bounds__(TPC * NG)
-void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item* __restrict__ items)
+void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item* __restrict__ items, int first)
 {
     constexpr int RO = R / V;
-    constexpr bool DOT = (MODE == kModePG || MODE == kModeCorr || MODE == kModePow);
+    constexpr bool SCR = (MODE == kModeCorr || MODE == kModePGS);   // screening quantities at x
+    constexpr bool STP = (MODE == kModePG || MODE == kModePGS);     // projected step
+    constexpr bool DOT = (STP || SCR || MODE == kModePow);
     constexpr bool ACC = (MODE != kModeCorr);
     constexpr int NW = TPC / 64;
     static_assert(R % V == 0, "rows per thread must be a multiple of the vector width");
@@ -215,6 +224,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     const Inst& I = insts[it.inst];
     State& S = st[it.inst];
     if (S.done) return;
+    if (MODE == kModePG && first && S.ahead) return;
     const int nlist = (MODE == kModeFold) ? S.n_fold : S.n_active;
     const int cb = (MODE == kModeFold) ? S.cb_fold : S.cb;
     const int pos0 = it.t * cb;
@@ -232,8 +242,8 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     const long long lda = I.lda;
     const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
     const int* __restrict__ list = (MODE == kModeFold) ? I.fidx : I.idx;
-    const double eta = (MODE == kModePG) ? S.step : 0.0;
-    const double tnorm_c = (MODE == kModeCorr) ? S.tnorm : 0.0;
+    const double eta = STP ? S.step : 0.0;
+    const double tnorm_c = SCR ? S.tnorm : 0.0;
 
     bool rowok[R];
 #pragma unroll
@@ -255,7 +265,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     // per-column screening quantities accumulated by the owner lanes.
     double rnorm_c = 0.0;
     double a_mass = 0.0, a_tv = 1.0, a_emax = 0.0, a_inf = 0.0, a_gap = 0.0, a_z = -__builtin_inf();
-    if constexpr (MODE == kModeCorr) {
+    if constexpr (SCR) {
         double sq = 0.0;
 #pragma unroll
         for (int k = 0; k < R; ++k) sq = fma(rl[k], rl[k], sq);
@@ -279,7 +289,6 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     for (int k = 0; k < (ACC ? R : 1); ++k) p[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < ((MODE == kModeFold) ? R : 1); ++k) p2[k] = 0.0;
-    double gsq = 0.0;
 
     __shared__ double red[2][NG][(NW > 1) ? NW : 1][CBI];
     int buf = 0;
@@ -298,18 +307,17 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 
     // Stage the item's column indices and per-column scalars in LDS once, so
     // that a round's column loads never wait on a dependent index load.
-    constexpr bool CORR = (MODE == kModeCorr);
     __shared__ int s_j[kCbMax];
-    __shared__ double s_x[(MODE == kModePG || MODE == kModeAx || MODE == kModeFold || CORR) ? kCbMax : 1];
-    __shared__ double s_l[(MODE == kModePG || MODE == kModeFold || CORR) ? kCbMax : 1];
-    __shared__ double s_u[(MODE == kModePG || CORR) ? kCbMax : 1];
-    __shared__ double s_cn[CORR ? kCbMax : 1];
-    __shared__ double s_w[CORR ? kCbMax : 1];
+    __shared__ double s_x[(STP || SCR || MODE == kModeAx || MODE == kModeFold) ? kCbMax : 1];
+    __shared__ double s_l[(STP || SCR || MODE == kModeFold) ? kCbMax : 1];
+    __shared__ double s_u[(STP || SCR) ? kCbMax : 1];
+    __shared__ double s_cn[SCR ? kCbMax : 1];
+    __shared__ double s_w[SCR ? kCbMax : 1];
     for (int k = tid; k < pos1 - pos0; k += TPC * NG) {
         const int q = pos0 + k;
         const int j = list[q];
         s_j[k] = j;
-        if constexpr (CORR) {
+        if constexpr (SCR) {
             s_x[k] = I.x[j];
             s_l[k] = lo_of(I.l, j);
             s_u[k] = up_of(I.u, j);
@@ -357,7 +365,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
             const int q = rs + myc * NG + grp;
             vo = q < pos1;
             jo = vo ? q - pos0 : 0;
-            if constexpr (MODE == kModePG) {
+            if constexpr (STP) {
                 xo = vo ? s_x[jo] : 0.0;
                 lo = vo ? s_l[jo] : 0.0;
                 uo = vo ? s_u[jo] : 0.0;
@@ -388,11 +396,13 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
             }
             double cown = 0.0;
             if (vo) {
-                if constexpr (MODE == kModePG) {
+                if constexpr (STP) {
                     const double xn = fmin(fmax(xo + eta * tot, lo), uo);
                     cown = xn;
                     if (owner) gstore(I.x + s_j[jo], xn);
-                } else if constexpr (MODE == kModeCorr) {
+                    if (MODE == kModePGS && owner) gstore(I.xs + s_j[jo], xo);
+                }
+                if constexpr (SCR) {
                     if (owner) {
                         gstore(I.g + s_j[jo], tot);
                         // screening quantities of this column at eps = 0
@@ -416,10 +426,8 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
                         a_gap += term;
                         if (cnj > 0.0) a_z = fmax(a_z, zs / cnj);
                     }
-                } else {  // power iteration
-                    cown = tot;
-                    if (owner) gsq += tot * tot;
                 }
+                if constexpr (MODE == kModePow) cown = tot;
             }
             if constexpr (ACC) {
 #pragma unroll
@@ -488,7 +496,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
         }
     }
 
-    if constexpr (MODE == kModeCorr) {
+    if constexpr (SCR) {
         // combine the owner lanes' screening quantities over the workgroup
         constexpr int NWB = (TPC * NG) / 64;
         __shared__ double s_red[6][NWB];
@@ -516,28 +524,19 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     }
     if constexpr (!ACC) return;
 
-    if constexpr (MODE == kModePow) gsq = wave_sum(gsq);   // owners live in wave 0 of each group
-
     // combine the NG groups' partial products (fixed order) and store
     if constexpr (NG > 1) {
         __shared__ double comb[(NG > 1) ? (NG - 1) * TPC * R : 1];
-        __shared__ double gs[NG];
         if (grp > 0) {
 #pragma unroll
             for (int k = 0; k < R; ++k) comb[((grp - 1) * R + k) * TPC + L] = p[k];
         }
-        if (MODE == kModePow && L == 0) gs[grp] = gsq;
         __syncthreads();
         if (grp == 0) {
 #pragma unroll
             for (int g2 = 1; g2 < NG; ++g2)
 #pragma unroll
                 for (int k = 0; k < R; ++k) p[k] += comb[((g2 - 1) * R + k) * TPC + L];
-            if (MODE == kModePow && L == 0) {
-                double s2 = 0.0;
-                for (int g2 = 0; g2 < NG; ++g2) s2 += gs[g2];
-                gsq = s2;
-            }
         }
         if constexpr (MODE == kModeFold) {
             __syncthreads();
@@ -573,9 +572,6 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
                 if (row < m) gstore(out2 + row, p2[k * V + e]);
             }
     }
-    if constexpr (MODE == kModePow) {
-        if (L == 0) I.iscal[(size_t)it.t * kItemScalars] = gsq;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -586,13 +582,14 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(1024)
-void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems)
+void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems, int first)
 {
     constexpr int TG = 1024 / kRedRows, U = 8;
     const RItem ri = ritems[blockIdx.x];
     const Inst& I = insts[ri.inst];
     const State& S = st[ri.inst];
     if (S.done) return;
+    if (MODE == kRedResidual && first && S.ahead) return;
     const int nlist = (MODE == kRedFold) ? S.n_fold : S.n_active;
     const int cb = (MODE == kRedFold) ? S.cb_fold : S.cb;
     const int T = (nlist + cb - 1) / cb;
@@ -630,6 +627,8 @@ void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RIte
         }
         if constexpr (MODE == kRedResidual) {
             I.r[row] = I.yp[row] - tot;
+        } else if constexpr (MODE == kRedAhead) {
+            I.r2[row] = I.yp[row] - tot;
         } else if constexpr (MODE == kRedFold) {
             I.yp[row] -= tot;
             I.r[row] -= tot2;
@@ -677,6 +676,7 @@ void k_init(const Inst* __restrict__ insts, State* __restrict__ st)
         S.status = BXS_OK;
         S.t_valid = 1;
         S.passes = 0;
+        S.ahead = 0;
     }
 }
 
@@ -736,7 +736,7 @@ void k_colstats(const Inst* __restrict__ insts, State* __restrict__ st, const It
 
 // ---------------------------------------------------------------------------
 // Per-instance scalars: bounds on ||y|| and ||t||, step from the caller, and
-// the starting vector of the power iteration (when do_pow).
+// the unit starting vector q_0 of the Lanczos estimate of ||A||_2^2 (when do_pow).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256)
 void k_inst_scalars(const Inst* __restrict__ insts, State* __restrict__ st, int do_pow, double user_step)
@@ -763,7 +763,12 @@ void k_inst_scalars(const Inst* __restrict__ insts, State* __restrict__ st, int 
     su = block_sum<256>(su, sh);
     if (do_pow) {
         const double inv = 1.0 / sqrt(su);
-        for (int i = threadIdx.x; i < m; i += 256) I.r[i] *= inv;
+        double* q0 = I.lz + 2 * I.lz_steps;
+        for (int i = threadIdx.x; i < m; i += 256) {
+            const double q = I.r[i] * inv;
+            I.r[i] = q;
+            q0[i] = q;
+        }
     }
     if (threadIdx.x == 0) {
         const double gm = gamma_k((double)m + 32.0);
@@ -776,28 +781,98 @@ void k_inst_scalars(const Inst* __restrict__ insts, State* __restrict__ st, int 
     }
 }
 
-// Power iteration on A A^T: after the sweep and reduction r = A A^T u, with
-// iscal holding the pieces of ||A^T u||^2 (the Rayleigh quotient of A A^T at
-// the unit vector u).  Normalise r; on the last round set the step.
-__global__ __launch_bounds__(256)
-void k_pow_normalize(const Inst* __restrict__ insts, State* __restrict__ st, int last, double user_step)
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal a[0..s)
+// and off-diagonal b[0..s-1), by multisection on Sturm counts: each of the
+// wave's 64 lanes counts the eigenvalues below its own point of the current
+// bracket (signs of the LDL^T pivots), and the bracket shrinks 65-fold per
+// round.  Called by one whole wave; every lane returns the same value, the
+// upper end of the final bracket.
+__device__ double tridiag_max_eig(const double* a, const double* b, int s)
 {
-    __shared__ double sh[4];
+    const int lane = threadIdx.x & 63;
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < s; ++i) {
+        const double rad = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < s ? fabs(b[i]) : 0.0);
+        hi = fmax(hi, a[i] + rad);
+        lo = fmin(lo, a[i] - rad);
+    }
+    hi *= 1.0 + 4.0 * kUnit;
+    for (int round = 0; round < 16 && hi - lo > 8.0 * kUnit * fabs(hi); ++round) {
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        int below = 0;
+        double d = 1.0;
+        for (int i = 0; i < s; ++i) {
+            d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            below += d < 0.0;
+        }
+        // lanes whose point lies above every eigenvalue
+        const unsigned long long above = __ballot(below == s);
+        const int f = above ? __ffsll((long long)above) - 1 : 64;
+        const double xf = (f < 64) ? __shfl(x, f, 64) : hi;
+        const double xl = (f > 0) ? __shfl(x, f - 1, 64) : lo;
+        hi = xf;
+        lo = xl;
+    }
+    return hi;
+}
+
+// One Lanczos step on M = A A^T (three-term recurrence, Golub & Van Loan,
+// Matrix Computations, Sec. 10.1).  On entry r = M q_k (column sweep and
+// partial reduction of the previous launches), q_k and q_{k-1} in lz:
+//   alpha_k = q_k^T r,  w = r - alpha_k q_k - beta_{k-1} q_{k-1},
+//   beta_k = ||w||,  q_{k+1} = w / beta_k  (0 if beta_k = 0: the Krylov space
+//   is invariant and the remaining steps add zero rows to T).
+// After the last step the largest eigenvalue of the tridiagonal T (a
+// Rayleigh-Ritz value of M: at most ||A||_2^2 up to rounding, and far closer
+// to it than the power iteration with as many products) gives the PG step
+// 1 / (1.05 L).  One workgroup per instance.
+__global__ __launch_bounds__(1024)
+void k_lanczos(const Inst* __restrict__ insts, State* __restrict__ st, int k, int last)
+{
+    constexpr int NT = 1024;
+    __shared__ double sh[NT / 64];
     const Inst& I = insts[blockIdx.x];
     State& S = st[blockIdx.x];
-    const int m = I.m;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < m; i += 256) s = fma(I.r[i], I.r[i], s);
-    s = block_sum<256>(s, sh);
-    const int T = (S.n_active + S.cb - 1) / S.cb;
-    double lam = 0.0;
-    for (int t = threadIdx.x; t < T; t += 256) lam += I.iscal[(size_t)t * kItemScalars];
-    lam = block_sum<256>(lam, sh);
-    const double inv = (s > 0.0) ? 1.0 / sqrt(s) : 0.0;
-    for (int i = threadIdx.x; i < m; i += 256) I.r[i] *= inv;
-    if (threadIdx.x == 0) {
-        S.lipschitz = lam;
-        if (last) S.step = (user_step > 0.0) ? user_step : ((lam > 0.0) ? 1.0 / (1.05 * lam) : 1.0);
+    const int m = I.m, steps = I.lz_steps;
+    double* al = I.lz;
+    double* be = I.lz + steps;
+    double* qc = I.lz + 2 * steps;
+    double* qp = qc + m;
+    const int tid = threadIdx.x;
+    double a = 0.0;
+    for (int i = tid; i < m; i += NT) a = fma(qc[i], I.r[i], a);
+    a = block_sum<NT>(a, sh);
+    const double bp = (k > 0) ? be[k - 1] : 0.0;
+    double ss = 0.0;
+    for (int i = tid; i < m; i += NT) {
+        double w = fma(-a, qc[i], I.r[i]);
+        if (k > 0) w = fma(-bp, qp[i], w);
+        I.r[i] = w;
+        ss = fma(w, w, ss);
+    }
+    ss = block_sum<NT>(ss, sh);
+    const double b = sqrt(ss);
+    const double inv = (b > 0.0) ? 1.0 / b : 0.0;
+    for (int i = tid; i < m; i += NT) {
+        const double q = I.r[i] * inv;
+        qp[i] = qc[i];
+        qc[i] = q;
+        I.r[i] = q;
+    }
+    if (tid == 0) {
+        al[k] = a;
+        be[k] = b;
+    }
+    if (last) {
+        __syncthreads();
+        if (tid < 64) {
+            const double lam = tridiag_max_eig(al, be, k + 1);
+            if (tid == 0) {
+                S.lipschitz = lam;
+                S.step = (lam > 0.0) ? 1.0 / (1.05 * lam) : 1.0;
+            }
+        }
     }
 }
 
@@ -820,7 +895,7 @@ void k_pow_normalize(const Inst* __restrict__ insts, State* __restrict__ st, int
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024)
 void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
-              double eps_gap, int screening, int final_pass, int K, int kk)
+              double eps_gap, int screening, int final_pass, int K, int kk, int ahead)
 {
     constexpr int NT = 1024;
     constexpr int E = 4;                       // consecutive preserved positions per thread per chunk
@@ -870,7 +945,7 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
             c[e].g = valid[e] ? I.g[j] : 0.0;
             c[e].w = valid[e] ? I.w[j] : 0.0;
             c[e].cn = valid[e] ? I.cn[j] : 0.0;
-            c[e].x = valid[e] ? I.x[j] : 0.0;
+            c[e].x = valid[e] ? (ahead ? I.xs[j] : I.x[j]) : 0.0;
             c[e].l = valid[e] ? lo_of(I.l, j) : 0.0;
             c[e].u = valid[e] ? up_of(I.u, j) : 0.0;
         }
@@ -968,6 +1043,19 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
                 S.iters = iters;
                 atomicAdd(done_counter, 1);
             }
+            S.ahead = (ahead && !(stop || final_pass)) ? 1 : 0;
+        }
+        if (ahead) {
+            if (stop || final_pass) {
+                // the result is the iterate the gap was computed at
+                for (int p = tid; p < nA; p += NT) {
+                    const int j = I.idx[p];
+                    I.x[j] = I.xs[j];
+                }
+            } else {
+                // keep the step taken ahead: its residual becomes r
+                for (int i = tid; i < m; i += NT) I.r[i] = I.r2[i];
+            }
         }
         return;
     }
@@ -1053,6 +1141,19 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
         S.n_lower += (int)nlo;
         S.n_upper += (int)nhi;
         S.mass_screened += smass;
+        S.ahead = (ahead && fout == 0) ? 1 : 0;
+    }
+    if (ahead) {
+        if (fout > 0) {
+            // the step taken ahead used columns now fixed: return the kept
+            // coordinates to the screening point (r still holds its residual)
+            for (int p = tid; p < out; p += NT) {
+                const int j = I.idx[p];
+                I.x[j] = I.xs[j];
+            }
+        } else {
+            for (int i = tid; i < m; i += NT) I.r[i] = I.r2[i];
+        }
     }
 }
 
@@ -1165,39 +1266,44 @@ void k_cd(const Inst* __restrict__ insts, State* __restrict__ st, const int* __r
 // host-side launchers
 // ---------------------------------------------------------------------------
 template <typename TA, int V, int TPC, int NG, int R, int CBI, int PD>
-static hipError_t sweep_launch_t(const LaunchCtx& c, int mode, const Item* items, int n_items)
+static hipError_t sweep_launch_t(const LaunchCtx& c, int mode, const Item* items, int n_items, int first)
 {
     constexpr int VV = (V < R) ? V : R;
     dim3 grid(n_items), block(TPC * NG);
+#define BXS_SW(MD) k_sweep<TA, TPC, NG, R, VV, CBI, PD, MD><<<grid, block, 0, c.stream>>>(c.insts, c.st, items, first)
     switch (mode) {
-    case kModePG: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModePG><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
-    case kModeCorr: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModeCorr><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
-    case kModeAx: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModeAx><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
-    case kModeFold: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModeFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
-    default: k_sweep<TA, TPC, NG, R, VV, CBI, PD, kModePow><<<grid, block, 0, c.stream>>>(c.insts, c.st, items); break;
+    case kModePG: BXS_SW(kModePG); break;
+    case kModeCorr: BXS_SW(kModeCorr); break;
+    case kModeAx: BXS_SW(kModeAx); break;
+    case kModeFold: BXS_SW(kModeFold); break;
+    case kModePow: BXS_SW(kModePow); break;
+    case kModePGS: BXS_SW(kModePGS); break;
+    default: return hipErrorInvalidValue;
     }
+#undef BXS_SW
     return hipGetLastError();
 }
 
 template <typename TA, int V>
-static hipError_t sweep_dispatch_v(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items)
+static hipError_t sweep_dispatch_v(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items,
+                                   int first)
 {
     switch (variant) {
-#define BXS_V(ID, TPC, NG, R, CBI, PD) case ID: return sweep_launch_t<TA, V, TPC, NG, R, CBI, PD>(c, mode, items, n_items);
+#define BXS_V(ID, TPC, NG, R, CBI, PD) case ID: return sweep_launch_t<TA, V, TPC, NG, R, CBI, PD>(c, mode, items, n_items, first);
     BXS_SWEEP_VARIANTS(BXS_V)
 #undef BXS_V
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items)
+hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items, int first)
 {
     if (n_items <= 0) return hipSuccess;
     if (c.dtype == BXS_F32)
-        return c.vec ? sweep_dispatch_v<float, 4>(c, variant, mode, items, n_items)
-                     : sweep_dispatch_v<float, 1>(c, variant, mode, items, n_items);
-    return c.vec ? sweep_dispatch_v<double, 2>(c, variant, mode, items, n_items)
-                 : sweep_dispatch_v<double, 1>(c, variant, mode, items, n_items);
+        return c.vec ? sweep_dispatch_v<float, 4>(c, variant, mode, items, n_items, first)
+                     : sweep_dispatch_v<float, 1>(c, variant, mode, items, n_items, first);
+    return c.vec ? sweep_dispatch_v<double, 2>(c, variant, mode, items, n_items, first)
+                 : sweep_dispatch_v<double, 1>(c, variant, mode, items, n_items, first);
 }
 
 template <typename TA, int V>
@@ -1234,14 +1340,16 @@ hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n
                  : cd_dispatch_v<double, 1>(c, bucket, inst_list, n_list, sweeps);
 }
 
-hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems)
+hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems, int first)
 {
     if (n_ritems <= 0) return hipSuccess;
     dim3 grid(n_ritems), block(1024);
     switch (mode) {
-    case kRedResidual: k_reduce<kRedResidual><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems); break;
-    case kRedFold: k_reduce<kRedFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems); break;
-    default: k_reduce<kRedPow><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems); break;
+    case kRedResidual: k_reduce<kRedResidual><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first); break;
+    case kRedFold: k_reduce<kRedFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first); break;
+    case kRedPow: k_reduce<kRedPow><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first); break;
+    case kRedAhead: k_reduce<kRedAhead><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -1275,17 +1383,17 @@ hipError_t launch_set_step(const LaunchCtx& c, int count, double step)
     return hipGetLastError();
 }
 
-hipError_t launch_pow_normalize(const LaunchCtx& c, int count, int last, double user_step)
+hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last)
 {
-    k_pow_normalize<<<dim3(count), dim3(256), 0, c.stream>>>(c.insts, c.st, last, user_step);
+    k_lanczos<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, k, last);
     return hipGetLastError();
 }
 
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening, int final_pass,
-                         int K, int kk)
+                         int K, int kk, int ahead)
 {
     k_screen<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                        final_pass, K, kk);
+                                                        final_pass, K, kk, ahead);
     return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ def test_default_opts(lib):
     o = N.Opts()
     lib.bxs_default_opts(C.byref(o))
     assert (o.solver, o.screening, o.screen_every, o.max_iter, o.eps_gap, o.step, o.power_iters) == \
-        (0, 1, 10, 100000, 1e-6, 0.0, 20)
+        (0, 1, 10, 100000, 1e-6, 0.0, 0)
     assert not o.t and not o.workspace and not o.stream
 
 
