@@ -223,8 +223,8 @@ def main():
     m, n = P.m, P.n
 
     log("[bench] screened solves")
-    # `value`: the solves as a user runs them (each regular screening pass
-    # replayed from a graph, no timing events).  The roofline: the same solves
+    # `value`: the solves as a user runs them (default options: direct
+    # launches, no timing events).  The roofline: the same solves
     # again with HIP events around every PG sweep launch (profile mode), which
     # adds a few microseconds between kernels but not to the kernels.
     dt, _, (x, sat, info) = time_solves(dev, args.steps, args.warmup, screening=True, eps_gap=1e-6,

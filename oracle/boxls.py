@@ -221,6 +221,36 @@ def lipschitz_power(A, iters: int = 100, seed: int = 0) -> float:
     return lam
 
 
+def lipschitz_lanczos(A, steps: int, u0) -> float:
+    """Lanczos estimate of ||A||_2^2 from the unit vector u0 / ||u0|| in R^m:
+    the largest eigenvalue of the steps x steps tridiagonal matrix T that the
+    three-term Lanczos recurrence builds for M = A A^T (Golub & Van Loan,
+    Matrix Computations, Sec. 10.1):
+        w = M q_k,  alpha_k = q_k^T w,  w -= alpha_k q_k + beta_{k-1} q_{k-1},
+        beta_k = ||w||,  q_{k+1} = w / beta_k  (0 once beta_k = 0).
+    It is a Rayleigh-Ritz value of M, hence at most ||A||_2^2, and it is exact
+    once the Krylov space is invariant.  (The step rule eta = 1 / L of the PG
+    solver needs only an estimate of L; this is the estimate the GPU library
+    makes, written plainly.)"""
+    A = np.asarray(A, dtype=np.float64)
+    q = np.asarray(u0, dtype=np.float64)
+    q = q / np.linalg.norm(q)
+    q_prev = np.zeros_like(q)
+    b_prev = 0.0
+    alpha, beta = [], []
+    for _ in range(steps):
+        w = A @ (A.T @ q)
+        a = float(q @ w)
+        w = w - a * q - b_prev * q_prev
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        beta.append(b)
+        q_prev, q = q, (w / b if b > 0.0 else np.zeros_like(w))
+        b_prev = b
+    T = np.diag(alpha) + np.diag(beta[:-1], 1) + np.diag(beta[:-1], -1)
+    return float(np.linalg.eigvalsh(T)[-1])
+
+
 # ---------------------------------------------------------------------------
 # The screening loop (Alg. 1; Alg. 2 is its l = 0, u = +inf case)
 # ---------------------------------------------------------------------------

@@ -167,8 +167,9 @@ static int choose_variant(long m)
 // spread over, per row class (fewer, longer items write fewer partial
 // products; set by bxs_set_group_scale).  Defaults from the autotuner on one
 // MI355X, as for the shapes; for 4000 x 16000 the spread 0.5 gives one
-// workgroup of 64 columns per CU (43 us per sweep against 49 us at 1).
-static double g_group_scale[kNumDefaultVariants] = {1, 1, 1, 1, 1, 0.5, 0.5, 1, 1};
+// workgroup of 64 columns per CU (43 us per sweep against 49 us at 1), and
+// for 1000 x 3000 (FP64) 13.0 us per iteration against 14.3 us at 1.
+static double g_group_scale[kNumDefaultVariants] = {1, 1, 1, 1, 0.5, 0.5, 0.5, 1, 1};
 
 static std::vector<int> group_targets(const std::vector<InstSpec>& specs, const std::vector<int>& variant, int cus)
 {
@@ -347,6 +348,24 @@ struct PinnedBuf {
     ~PinnedBuf() { if (p) (void)hipHostFree(p); }
 };
 
+// Pinned host staging area for the device tables of a solve (one copy
+// uploads them all) and for the State download at its end.  A solve
+// synchronises its stream before it returns, so the next call of the same
+// thread finds the area free.
+static bxs_status staging(size_t bytes, void** out)
+{
+    static thread_local PinnedBuf buf;
+    if (buf.bytes < bytes) {
+        if (buf.p) (void)hipHostFree(buf.p);
+        buf.p = nullptr;
+        buf.bytes = 0;
+        BXS_HIP(hipHostMalloc(&buf.p, bytes, hipHostMallocDefault));
+        buf.bytes = bytes;
+    }
+    *out = buf.p;
+    return BXS_OK;
+}
+
 static bxs_status pinned(size_t bytes, void** out)
 {
     static thread_local PinnedBuf buf;
@@ -430,27 +449,40 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     int* ints = (int*)cur;
     D.done_counter = ints + count;
     D.n_ritems = (int)P.ritems.size();
-    std::vector<Item> all_items;
-    std::vector<int> all_lists;
+    // Host image of the tables (descriptors, zeroed states, work items,
+    // reduction items, CD lists, zeroed stop counter and ticket), uploaded
+    // with one copy from pinned memory.
+    const size_t tbytes = (size_t)((char*)(D.done_counter + 2) - (char*)D.insts);
+    const size_t sbytes = sizeof(State) * count;
+    void* stage_p = nullptr;
+    {
+        bxs_status ss = staging(std::max(tbytes, sbytes), &stage_p);
+        if (ss != BXS_OK) return ss;
+    }
+    char* img = (char*)stage_p;
+    memset(img, 0, tbytes);
+    auto at = [&](const void* dev) { return img + ((const char*)dev - (const char*)D.insts); };
+    memcpy(at(D.insts), P.insts.data(), sizeof(Inst) * count);
     long off = 0, loff = 0;
     for (int b = 0; b < kNumVariants; ++b) {
         D.items[b] = items_base + off;
         D.n_items[b] = (int)P.items[b].size();
-        all_items.insert(all_items.end(), P.items[b].begin(), P.items[b].end());
+        if (D.n_items[b] > 0) memcpy(at(D.items[b]), P.items[b].data(), sizeof(Item) * P.items[b].size());
         off += D.n_items[b];
     }
+    if (!P.ritems.empty()) memcpy(at(D.ritems), P.ritems.data(), sizeof(RItem) * P.ritems.size());
     for (int b = 0; b < kNumCdBuckets; ++b) {
         D.lists[b] = ints + loff;
         D.n_list[b] = (int)P.cd_list[b].size();
-        all_lists.insert(all_lists.end(), P.cd_list[b].begin(), P.cd_list[b].end());
+        if (D.n_list[b] > 0) memcpy(at(D.lists[b]), P.cd_list[b].data(), sizeof(int) * P.cd_list[b].size());
         loff += D.n_list[b];
     }
-    BXS_HIP(hipMemcpyAsync(D.insts, P.insts.data(), sizeof(Inst) * count, hipMemcpyHostToDevice, stream));
-    BXS_HIP(hipMemsetAsync(D.st, 0, sizeof(State) * count, stream));
-    BXS_HIP(hipMemcpyAsync(items_base, all_items.data(), sizeof(Item) * all_items.size(), hipMemcpyHostToDevice, stream));
-    BXS_HIP(hipMemcpyAsync(D.ritems, P.ritems.data(), sizeof(RItem) * P.ritems.size(), hipMemcpyHostToDevice, stream));
-    BXS_HIP(hipMemcpyAsync(ints, all_lists.data(), sizeof(int) * all_lists.size(), hipMemcpyHostToDevice, stream));
-    BXS_HIP(hipMemsetAsync(D.done_counter, 0, sizeof(int), stream));
+    BXS_HIP(hipMemcpyAsync(D.insts, img, tbytes, hipMemcpyHostToDevice, stream));
+    struct StageGuard {
+        hipStream_t s;
+        bool done = false;
+        ~StageGuard() { if (!done) (void)hipStreamSynchronize(s); }   // the area is reused by the next call
+    } stage_guard{stream};
 
     LaunchCtx c;
     c.stream = stream; c.dtype = dtype; c.vec = P.vec;
@@ -474,6 +506,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     // ---- setup ----
     BXS_HIP(launch_init(c, (int)count, nullptr));
     for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_colstats(c, b, D.items[b], D.n_items[b]));
+    BXS_HIP(launch_validate(c, (int)count));
     const bool do_pow = !(o->step > 0.0);
     if (do_pow) {
         // Lanczos on A A^T from a fixed unit vector: one sweep per step
@@ -491,14 +524,9 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
     BXS_HIP(hipEventRecord(ev1, stream));
 
-    // validation flags
+    // instances that failed validation are stopped on the device (k_validate)
+    // and reported after the loop
     std::vector<State> hst(count);
-    BXS_HIP(hipMemcpyAsync(hst.data(), D.st, sizeof(State) * count, hipMemcpyDeviceToHost, stream));
-    BXS_HIP(hipStreamSynchronize(stream));
-    for (long i = 0; i < count; ++i) {
-        if (hst[i].err & kErrNonfinite) return fail(BXS_ERR_NONFINITE, "problem %ld: non-finite value in A, y, x0, t or bounds", i);
-        if (hst[i].err & kErrBounds) return fail(BXS_ERR_BOUNDS, "problem %ld: l_j = -inf, u_j = -inf or l_j > u_j", i);
-    }
 
     // ---- screening loop ----
     int* hdone = nullptr;
@@ -541,7 +569,9 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     // instead of kk + 1.  Every iterate is the one of the plain order (test,
     // fold, step): the step is only kept when the test fixed nothing.
     const bool pg = o->solver == BXS_PG;
-    auto enqueue_kernels = [&](int slot, long long kk, int final_pass) -> bxs_status {
+    // host_done: where the screening kernel publishes the stop counter
+    // (nullptr inside a captured graph: a copy kernel follows the replay).
+    auto enqueue_kernels = [&](int slot, long long kk, int final_pass, int* host_done) -> bxs_status {
         for (long long k = 0; k < kk; ++k) {
             const int first = (k == 0) ? 1 : 0;
             if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k], stream));
@@ -566,7 +596,8 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         } else {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
         }
-        BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk, pg ? 1 : 0));
+        BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk, pg ? 1 : 0,
+                              host_done));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));
@@ -588,7 +619,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     } gguard{&graph, &gexec};
     if (want_graph) {
         BXS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        const bxs_status cs = enqueue_kernels(0, K, 0);
+        const bxs_status cs = enqueue_kernels(0, K, 0, nullptr);
         const hipError_t ce = hipStreamEndCapture(stream, &graph);
         if (cs != BXS_OK) return cs;
         BXS_HIP(ce);
@@ -601,11 +632,11 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         const int final_pass = iters >= o->max_iter;
         if (gexec && kk == K && !final_pass) {
             BXS_HIP(hipGraphLaunch(gexec, stream));
+            BXS_HIP(launch_publish(c, hdone + slot));
         } else {
-            const bxs_status es = enqueue_kernels(slot, kk, final_pass);
+            const bxs_status es = enqueue_kernels(slot, kk, final_pass, hdone + slot);
             if (es != BXS_OK) return es;
         }
-        BXS_HIP(hipMemcpyAsync(hdone + slot, D.done_counter, sizeof(int), hipMemcpyDeviceToHost, stream));
         BXS_HIP(hipEventRecord(dev_done[slot], stream));
         slot_kk[slot] = kk;
         slot_final[slot] = final_pass;
@@ -642,7 +673,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         slot = nxt;
     }
     BXS_HIP(hipEventRecord(ev2, stream));
-    BXS_HIP(hipMemcpyAsync(hst.data(), D.st, sizeof(State) * count, hipMemcpyDeviceToHost, stream));
+    BXS_HIP(hipMemcpyAsync(img, D.st, sbytes, hipMemcpyDeviceToHost, stream));
     std::vector<bxs_pass_record> hrec;
     long nrec = 0;
     if (history && count == 1 && P.rec_cap > 0) {
@@ -651,6 +682,12 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
                                hipMemcpyDeviceToHost, stream));
     }
     BXS_HIP(hipStreamSynchronize(stream));
+    stage_guard.done = true;
+    memcpy(hst.data(), img, sbytes);
+    for (long i = 0; i < count; ++i) {
+        if (hst[i].err & kErrNonfinite) return fail(BXS_ERR_NONFINITE, "problem %ld: non-finite value in A, y, x0, t or bounds", i);
+        if (hst[i].err & kErrBounds) return fail(BXS_ERR_BOUNDS, "problem %ld: l_j = -inf, u_j = -inf or l_j > u_j", i);
+    }
     float ms_setup = 0.f, ms_solve = 0.f;
     BXS_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
     BXS_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
@@ -708,7 +745,7 @@ void bxs_default_opts(bxs_opts* o)
     o->eps_gap = 1e-6;
     o->step = 0.0;
     o->power_iters = 0;
-    o->graph = 1;
+    o->graph = 0;
 }
 
 const char* bxs_last_error(void) { return g_last_error.c_str(); }

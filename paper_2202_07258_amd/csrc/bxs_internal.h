@@ -222,11 +222,15 @@ hipError_t launch_colstats(const LaunchCtx& c, int variant, const Item* items, i
 hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items,
                         int first = 0);
 hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems, int first = 0);
+hipError_t launch_validate(const LaunchCtx& c, int count);
+hipError_t launch_publish(const LaunchCtx& c, int* host_dst);
 hipError_t launch_pow_init(const LaunchCtx& c, int count);
 hipError_t launch_set_step(const LaunchCtx& c, int count, double step);
 hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last);
+// host_done: pinned host word that receives the stop counter at the end of
+// the pass (nullptr: the caller copies it itself).
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening,
-                         int final_pass, int K, int kk, int ahead);
+                         int final_pass, int K, int kk, int ahead, int* host_done);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
 
 }  // namespace bxs

@@ -680,6 +680,29 @@ void k_init(const Inst* __restrict__ insts, State* __restrict__ st)
     }
 }
 
+// Input validation on the device: an instance whose data failed the checks of
+// k_init or k_colstats stops here with the error as its status, so the solve
+// needs no host round trip before its first iteration.
+__global__ __launch_bounds__(256)
+void k_validate(State* __restrict__ st, int* __restrict__ done_counter, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    State& S = st[i];
+    if (S.err == 0 || S.done) return;
+    S.done = 1;
+    S.status = (S.err & kErrNonfinite) ? BXS_ERR_NONFINITE : BXS_ERR_BOUNDS;
+    atomicAdd(done_counter, 1);
+}
+
+// Copy of the stop counter into host memory (pinned, mapped): the host reads
+// it once the pass's completion event has fired.
+__global__ __launch_bounds__(64)
+void k_publish(const int* __restrict__ src, int* __restrict__ dst)
+{
+    if (threadIdx.x == 0) dst[0] = src[0];
+}
+
 // ---------------------------------------------------------------------------
 // Column statistics: rigorous norm bound, sum of squares, w = A^T t, and a
 // finiteness check of A.  One wave per column.
@@ -893,9 +916,9 @@ void k_lanczos(const Inst* __restrict__ insts, State* __restrict__ st, int k, in
 // e_j bounds |computed - exact| of a_j^T theta, delta_r bounds the residual
 // error, and each rounded sum, product and square root is pushed outward.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024)
-void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
-              double eps_gap, int screening, int final_pass, int K, int kk, int ahead)
+__device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, State* __restrict__ st,
+                                            int* __restrict__ done_counter, double eps_gap, int screening,
+                                            int final_pass, int K, int kk, int ahead)
 {
     constexpr int NT = 1024;
     constexpr int E = 4;                       // consecutive preserved positions per thread per chunk
@@ -1157,6 +1180,28 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
     }
 }
 
+// One workgroup per instance.  With host_done set, the last workgroup to
+// finish (ticket counter next to the stop counter) also copies the stop
+// counter into host memory, so no separate copy follows the pass.
+__global__ __launch_bounds__(1024)
+void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
+              double eps_gap, int screening, int final_pass, int K, int kk, int ahead, int* host_done)
+{
+    screen_pass(insts, st, done_counter, eps_gap, screening, final_pass, K, kk, ahead);
+    if (host_done == nullptr) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int* ticket = done_counter + 1;
+        __threadfence();
+        const int t = atomicAdd(ticket, 1);
+        if (t == (int)gridDim.x - 1) {
+            __threadfence();
+            host_done[0] = atomicAdd(done_counter, 0);
+            atomicExch(ticket, 0);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Cyclic coordinate descent, one workgroup per instance: for j in P in
 // ascending order, x_j <- Pi(x_j + a_j^T r / ||a_j||^2), r -= delta a_j.
@@ -1371,6 +1416,18 @@ hipError_t launch_colstats(const LaunchCtx& c, int bucket, const Item* items, in
     return hipGetLastError();
 }
 
+hipError_t launch_validate(const LaunchCtx& c, int count)
+{
+    k_validate<<<dim3((count + 255) / 256), dim3(256), 0, c.stream>>>(c.st, c.done_counter, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish(const LaunchCtx& c, int* host_dst)
+{
+    k_publish<<<dim3(1), dim3(64), 0, c.stream>>>(c.done_counter, host_dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_pow_init(const LaunchCtx& c, int count)
 {
     k_inst_scalars<<<dim3(count), dim3(256), 0, c.stream>>>(c.insts, c.st, 1, 0.0);
@@ -1390,10 +1447,10 @@ hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last)
 }
 
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening, int final_pass,
-                         int K, int kk, int ahead)
+                         int K, int kk, int ahead, int* host_done)
 {
     k_screen<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                        final_pass, K, kk, ahead);
+                                                        final_pass, K, kk, ahead, host_done);
     return hipGetLastError();
 }
 

@@ -164,7 +164,7 @@ def colmajor(A: Any, device="cuda", dtype=None) -> torch.Tensor:
 
 def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, eps_gap=1e-6, step=0.0,
               power_iters=0, t: torch.Tensor | None = None, history=0, stream=None,
-              profile=False, iter_precision="f64", graph=True) -> tuple[Opts, Any]:
+              profile=False, iter_precision="f64", graph=False) -> tuple[Opts, Any]:
     lib = load()
     o = Opts()
     lib.bxs_default_opts(C.byref(o))

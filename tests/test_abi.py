@@ -106,6 +106,24 @@ def test_workspace_query_row_limit(lib):
     assert lib.bxs_workspace_size(N.MAX_ROWS + 1, 10, C.byref(o), C.byref(b)) == N.BXS_ERR_SHAPE
 
 
+def test_step_estimate_option(lib):
+    """power_iters: at most 64 Lanczos steps; their workspace (two m-vectors and
+    the tridiagonal coefficients) is only reserved when the step is computed."""
+    o = N.Opts()
+    lib.bxs_default_opts(C.byref(o))
+    b8, b64, bstep = C.c_size_t(0), C.c_size_t(0), C.c_size_t(0)
+    assert lib.bxs_workspace_size(1000, 50, C.byref(o), C.byref(b8)) == N.BXS_OK
+    o.power_iters = 64
+    assert lib.bxs_workspace_size(1000, 50, C.byref(o), C.byref(b64)) == N.BXS_OK
+    assert b64.value >= b8.value
+    o.power_iters = 65
+    assert lib.bxs_workspace_size(1000, 50, C.byref(o), C.byref(b64)) == N.BXS_ERR_ARG
+    o.power_iters = 0
+    o.step = 0.1
+    assert lib.bxs_workspace_size(1000, 50, C.byref(o), C.byref(bstep)) == N.BXS_OK
+    assert bstep.value < b8.value
+
+
 def test_workspace_query_shape_check(lib):
     o = _opts(lib)
     b = C.c_size_t(0)

@@ -17,6 +17,7 @@ def test_autotune_installs_valid_shapes_and_keeps_parity():
     from paper_2202_07258_amd import native as N
     variants = N.sweep_variants()
     before = {c: N.variant_for_rows(variants[c]["capacity"]) for c in (1, 3)}
+    scale_before = {c: N.group_scale(c) for c in (1, 3)}
     table = bx.autotune.tune(classes=[1, 3], iters=20, reps=1)
     try:
         for c in (1, 3):
@@ -38,4 +39,4 @@ def test_autotune_installs_valid_shapes_and_keeps_parity():
     finally:
         for c, v in before.items():
             N.set_sweep_variant(c, v)
-            N.set_group_scale(c, 1.0)
+            N.set_group_scale(c, scale_before[c])

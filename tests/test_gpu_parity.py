@@ -118,11 +118,29 @@ def test_cd_nnls_parity():
     xg, sg, info, res = check_parity(P, "nnls", xtol=1e-8, **kw)
 
 
-def test_power_iteration_step():
-    P = planted(4, 500, 1500, dtype=np.float32)
-    xg, sg, info = run_gpu(P, "bvls", eps_gap=1e-6, max_iter=50)
+def _hash_start(m):
+    """Start vector of the library's Lanczos estimate: 1 +- 1/4 by the top bit
+    of Knuth's multiplicative hash i * 2654435761 mod 2^32 of the row index."""
+    h = (np.arange(m, dtype=np.uint64) * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)
+    return np.where((h >> np.uint64(31)) != 0, 1.25, 0.75)
+
+
+@pytest.mark.parametrize("m,n,dtype,steps", [(500, 1500, np.float32, 0), (500, 1500, np.float64, 3),
+                                             (777, 300, np.float32, 20), (6, 40, np.float64, 8)])
+def test_step_estimate(m, n, dtype, steps):
+    """The default step 1 / (1.05 L_est): L_est is the oracle's Lanczos
+    estimate from the same start vector (8 steps by default), a lower bound of
+    ||A||_2^2, within 10% of it from 8 steps on (exact when m <= steps)."""
+    P = planted(4, m, n, dtype=dtype)
+    xg, sg, info = run_gpu(P, "bvls", eps_gap=1e-6, max_iter=50, power_iters=steps)
     L = ob.lipschitz(P.A64())
-    assert 0.9 * L <= info["lipschitz"] <= L * (1 + 1e-12)
+    est = ob.lipschitz_lanczos(P.A64(), steps if steps > 0 else 8, _hash_start(m))
+    assert info["lipschitz"] == pytest.approx(est, rel=1e-9)
+    assert info["lipschitz"] <= L * (1 + 1e-12)
+    if steps == 0 or steps >= 8:
+        assert info["lipschitz"] >= 0.9 * L
+    if m <= max(steps, 8):
+        assert info["lipschitz"] == pytest.approx(L, rel=1e-9)
     assert info["step"] == pytest.approx(1.0 / (1.05 * info["lipschitz"]), rel=1e-15)
 
 
@@ -212,6 +230,18 @@ def test_device_side_validation():
     lbad = l.clone(); lbad[5] = -float("inf")
     with pytest.raises(bx.BoxscreenError, match="err_bounds"):
         bx.solve_bvls(A, y, lbad, u)
+    Abad = P.A.copy(); Abad[7, 11] = np.inf
+    with pytest.raises(bx.BoxscreenError, match="err_nonfinite"):
+        bx.solve_bvls(bx.colmajor(Abad), y, l, u)
+    # one failing instance of a batch fails the call; the others still run and
+    # the next call is unaffected
+    good = {"A": A, "y": y, "l": l, "u": u}
+    with pytest.raises(bx.BoxscreenError, match="err_nonfinite"):
+        bx.solve_bvls_varbatch([good, {"A": A, "y": ybad, "l": l, "u": u}, good], eps_gap=1e-9)
+    x, _, info = bx.solve_bvls(A, y, l, u, eps_gap=1e-9, step=step_of(P))
+    assert info["status_name"] == "ok"
+    res = ob.solve(P.A64(), P.y, P.l, P.u, K=10, eps_gap=1e-9, step=step_of(P))
+    assert np.max(np.abs(x.cpu().numpy() - res.x)) <= 1e-9 * max(1.0, float(np.max(np.abs(res.x))))
 
 
 def test_varbatch_parity():

@@ -107,3 +107,46 @@ def test_maxiter_status():
     P = W.tiny_bvls(2, 10, 20)
     res = ob.solve(P.A, P.y, P.l, P.u, eps_gap=0.0, max_iter=23, K=10)
     assert res.status == "maxiter" and res.iters == 23 and res.passes == 3
+
+
+def _hash_start(m):
+    """The start vector of the library's Lanczos estimate: 1 +- 1/4 by the top
+    bit of Knuth's multiplicative hash of the row index, i * 2654435761 mod
+    2^32 (TAOCP Vol. 3, Sec. 6.4)."""
+    h = (np.arange(m, dtype=np.uint64) * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)
+    return np.where((h >> np.uint64(31)) != 0, 1.25, 0.75)
+
+
+def test_lanczos_estimate_pins():
+    rng = np.random.default_rng(7)
+    # one step is the Rayleigh quotient u^T A A^T u of the unit start vector
+    A = rng.standard_normal((9, 14))
+    u = _hash_start(9)
+    uu = u / np.linalg.norm(u)
+    assert ob.lipschitz_lanczos(A, 1, u) == pytest.approx(float(np.sum((A.T @ uu) ** 2)), rel=1e-13)
+    # a Krylov space that is invariant after two steps: exact largest eigenvalue
+    # of the two coordinates the start vector touches
+    s = np.array([3.0, 0.5, 7.0, 1.0])
+    D = np.diag(s)
+    assert ob.lipschitz_lanczos(D, 2, np.array([1.0, 1.0, 0.0, 0.0])) == pytest.approx(9.0, rel=1e-13)
+    assert ob.lipschitz_lanczos(D, 3, np.array([1.0, 1.0, 1.0, 0.0])) == pytest.approx(49.0, rel=1e-13)
+    # m steps span R^m: the exact ||A||_2^2
+    L = ob.lipschitz(A)
+    assert ob.lipschitz_lanczos(A, 9, u) == pytest.approx(L, rel=1e-10)
+    # a Rayleigh-Ritz value: below L, nondecreasing in the number of steps,
+    # and at least the Rayleigh quotient of the power iterate M^(k-1) u
+    B = rng.standard_normal((60, 200))
+    LB = ob.lipschitz(B)
+    u = _hash_start(60)
+    prev = 0.0
+    v = u / np.linalg.norm(u)
+    for k in range(1, 13):
+        est = ob.lipschitz_lanczos(B, k, u)
+        rq = float(np.sum((B.T @ v) ** 2))
+        assert est <= LB * (1 + 1e-12)
+        assert est >= prev * (1 - 1e-12)
+        assert est >= rq * (1 - 1e-12)
+        prev = est
+        w = B @ (B.T @ v)
+        v = w / np.linalg.norm(w)
+    assert prev > 0.9 * LB
