@@ -488,6 +488,25 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     c.stream = stream; c.dtype = dtype; c.vec = P.vec;
     c.insts = D.insts; c.st = D.st; c.done_counter = D.done_counter;
 
+    // Sweeps that read A and also accumulate a product with A: one fused pass,
+    // or a dot pass and a product pass for the shapes too large for the fused
+    // kernel's registers.
+    auto sweep_pg = [&](int b, int first) -> hipError_t {
+        if (!variant_two_pass(b)) return launch_sweep(c, b, kModePG, D.items[b], D.n_items[b], first);
+        const hipError_t e = launch_sweep(c, b, kModeStep, D.items[b], D.n_items[b], first);
+        return e != hipSuccess ? e : launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b], first);
+    };
+    auto sweep_pgs = [&](int b) -> hipError_t {
+        if (!variant_two_pass(b)) return launch_sweep(c, b, kModePGS, D.items[b], D.n_items[b]);
+        const hipError_t e = launch_sweep(c, b, kModeStepS, D.items[b], D.n_items[b]);
+        return e != hipSuccess ? e : launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]);
+    };
+    auto sweep_pow = [&](int b) -> hipError_t {
+        if (!variant_two_pass(b)) return launch_sweep(c, b, kModePow, D.items[b], D.n_items[b]);
+        const hipError_t e = launch_sweep(c, b, kModePowG, D.items[b], D.n_items[b]);
+        return e != hipSuccess ? e : launch_sweep(c, b, kModeAg, D.items[b], D.n_items[b]);
+    };
+
     hipEvent_t ev0, ev1, ev2;
     BXS_HIP(hipEventCreate(&ev0));
     BXS_HIP(hipEventCreate(&ev1));
@@ -513,7 +532,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         BXS_HIP(launch_pow_init(c, (int)count));
         const int np = P.lz_steps;
         for (int k = 0; k < np; ++k) {
-            for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModePow, D.items[b], D.n_items[b]));
+            for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pow(b));
             BXS_HIP(launch_reduce(c, kRedPow, D.ritems, D.n_ritems));
             BXS_HIP(launch_lanczos(c, (int)count, k, k == np - 1));
         }
@@ -576,8 +595,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             const int first = (k == 0) ? 1 : 0;
             if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k], stream));
             if (pg) {
-                for (int b = 0; b < kNumVariants; ++b)
-                    BXS_HIP(launch_sweep(c, b, kModePG, D.items[b], D.n_items[b], first));
+                for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pg(b, first));
             } else {
                 for (int b = 0; b < kNumCdBuckets; ++b) BXS_HIP(launch_cd(c, b, D.lists[b], D.n_list[b], 1));
             }
@@ -591,7 +609,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             }
         }
         if (pg) {
-            for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModePGS, D.items[b], D.n_items[b]));
+            for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pgs(b));
             BXS_HIP(launch_reduce(c, kRedAhead, D.ritems, D.n_ritems));
         } else {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));

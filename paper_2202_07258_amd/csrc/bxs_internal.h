@@ -108,9 +108,20 @@ enum SweepMode : int {
     kModeAx = 2,            // partial += A x
     kModeFold = 3,          // partial += A_S b_S, partial2 += A_S (b_S - x_S)
     kModePow = 4,           // g = A^T r, partial += A g (one product with A A^T)
-    kModePGS = 5            // kModeCorr at x and the kModePG step from x in one pass;
+    kModePGS = 5,           // kModeCorr at x and the kModePG step from x in one pass;
                             // x is kept in xs, g stored
+    // Two-pass forms for the shapes whose fused form does not fit the register
+    // file (TPC * rows >= 16384: the residual is staged in LDS instead): a dot
+    // pass, then a product pass over the same columns.
+    kModeStep = 6,          // kModePG without the product: x <- Pi(x + eta g)
+    kModeStepS = 7,         // kModePGS without the product
+    kModePowG = 8,          // g = A^T r stored
+    kModeAg = 9             // partial += A g
 };
+
+// Shapes that run the PG step, the screening sweep and the products with
+// A A^T as two passes (dot pass + product pass).
+constexpr bool two_pass_shape(int tpc, int rows) { return tpc * rows >= 16384; }
 
 enum ReduceMode : int {
     kRedResidual = 0,       // r = yp - sum
@@ -181,6 +192,7 @@ constexpr VariantSpec kVariants[kNumVariants] = {
 };
 
 inline long variant_capacity(int v) { return (long)kVariants[v].tpc * kVariants[v].rows; }
+inline bool variant_two_pass(int v) { return two_pass_shape(kVariants[v].tpc, kVariants[v].rows); }
 
 inline int default_variant_for_rows(long m) {
     for (int b = 0; b < kNumDefaultVariants; ++b)

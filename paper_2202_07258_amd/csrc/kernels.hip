@@ -212,10 +212,14 @@ __global__ __launch_bounds__(TPC * NG)
 void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item* __restrict__ items, int first)
 {
     constexpr int RO = R / V;
-    constexpr bool SCR = (MODE == kModeCorr || MODE == kModePGS);   // screening quantities at x
-    constexpr bool STP = (MODE == kModePG || MODE == kModePGS);     // projected step
-    constexpr bool DOT = (STP || SCR || MODE == kModePow);
-    constexpr bool ACC = (MODE != kModeCorr);
+    constexpr bool SCR = (MODE == kModeCorr || MODE == kModePGS || MODE == kModeStepS);  // screening at x
+    constexpr bool STP = (MODE == kModePG || MODE == kModePGS || MODE == kModeStep || MODE == kModeStepS);
+    constexpr bool KEEPX = (MODE == kModePGS || MODE == kModeStepS);  // x kept in xs
+    constexpr bool DOT = (STP || SCR || MODE == kModePow || MODE == kModePowG);
+    constexpr bool ACC = !(MODE == kModeCorr || MODE == kModeStep || MODE == kModeStepS || MODE == kModePowG);
+    constexpr bool COEF = (MODE == kModeAx || MODE == kModeAg);      // partial += A c, c staged per column
+    // residual rows staged in LDS (shapes too large for it to stay in registers)
+    constexpr bool RLDS = DOT && two_pass_shape(TPC, R);
     constexpr int NW = TPC / 64;
     static_assert(R % V == 0, "rows per thread must be a multiple of the vector width");
     static_assert(TPC % 64 == 0, "a column group is whole waves");
@@ -224,7 +228,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     const Inst& I = insts[it.inst];
     State& S = st[it.inst];
     if (S.done) return;
-    if (MODE == kModePG && first && S.ahead) return;
+    if ((MODE == kModePG || MODE == kModeStep || MODE == kModeAx) && first && S.ahead) return;
     const int nlist = (MODE == kModeFold) ? S.n_fold : S.n_active;
     const int cb = (MODE == kModeFold) ? S.cb_fold : S.cb;
     const int pos0 = it.t * cb;
@@ -250,14 +254,19 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     for (int k = 0; k < RO; ++k)
 #pragma unroll
         for (int e = 0; e < V; ++e) rowok[k * V + e] = (k * TPC + L) * V + e < m;
-    double rl[DOT ? R : 1];
+    double rl[(DOT && !RLDS) ? R : 1];
+    __shared__ double s_r[RLDS ? TPC * R : 1];
+    auto rv = [&](int k) -> double {
+        if constexpr (RLDS) return s_r[k * TPC + L]; else return rl[k];
+    };
     if constexpr (DOT) {
 #pragma unroll
         for (int k = 0; k < RO; ++k)
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int row = (k * TPC + L) * V + e;
-                rl[k * V + e] = (row < m) ? I.r[row] : 0.0;
+                const double v = (row < m) ? I.r[row] : 0.0;
+                if constexpr (RLDS) s_r[(k * V + e) * TPC + L] = v; else rl[k * V + e] = v;
             }
     }
     // CORR: bound on ||r|| (every workgroup sums the same registers in the
@@ -268,7 +277,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     if constexpr (SCR) {
         double sq = 0.0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) sq = fma(rl[k], rl[k], sq);
+        for (int k = 0; k < R; ++k) sq = fma(rv(k), rv(k), sq);
         sq = wave_sum(sq);
         __shared__ double s_sq[(TPC * NG) / 64];
         if (lane == 0) s_sq[tid >> 6] = sq;
@@ -308,7 +317,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     // Stage the item's column indices and per-column scalars in LDS once, so
     // that a round's column loads never wait on a dependent index load.
     __shared__ int s_j[kCbMax];
-    __shared__ double s_x[(STP || SCR || MODE == kModeAx || MODE == kModeFold) ? kCbMax : 1];
+    __shared__ double s_x[(STP || SCR || COEF || MODE == kModeFold) ? kCbMax : 1];
     __shared__ double s_l[(STP || SCR || MODE == kModeFold) ? kCbMax : 1];
     __shared__ double s_u[(STP || SCR) ? kCbMax : 1];
     __shared__ double s_cn[SCR ? kCbMax : 1];
@@ -323,12 +332,14 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
             s_u[k] = up_of(I.u, j);
             s_cn[k] = I.cn[j];
             s_w[k] = I.w[j];
-        } else if constexpr (MODE == kModePG) {
+        } else if constexpr (STP) {
             s_x[k] = I.x[j];
             s_l[k] = lo_of(I.l, j);
             s_u[k] = up_of(I.u, j);
         } else if constexpr (MODE == kModeAx) {
             s_x[k] = I.x[j];
+        } else if constexpr (MODE == kModeAg) {
+            s_x[k] = I.g[j];
         } else if constexpr (MODE == kModeFold) {
             s_x[k] = I.fval[q];
             s_l[k] = I.fdx[q];
@@ -353,7 +364,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 #pragma unroll
                 for (int e = 0; e < V; ++e) a[c][k * V + e] = tmp[e];
             }
-            if constexpr (MODE == kModeAx) {
+            if constexpr (COEF) {
                 c1[c] = vv ? s_x[q - pos0] : 0.0;
             } else if constexpr (MODE == kModeFold) {
                 c1[c] = vv ? s_x[q - pos0] : 0.0;
@@ -381,7 +392,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
             for (int c = 0; c < CBI; ++c) {
                 double s = 0.0;
 #pragma unroll
-                for (int k = 0; k < R; ++k) s = fma(rowok[k] ? (double)a[c][k] : 0.0, rl[k], s);
+                for (int k = 0; k < R; ++k) s = fma(rowok[k] ? (double)a[c][k] : 0.0, rv(k), s);
                 d[c] = s;
             }
             double tot = wave_reduce_scatter<CBI>(d, lane);
@@ -400,7 +411,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
                     const double xn = fmin(fmax(xo + eta * tot, lo), uo);
                     cown = xn;
                     if (owner) gstore(I.x + s_j[jo], xn);
-                    if (MODE == kModePGS && owner) gstore(I.xs + s_j[jo], xo);
+                    if (KEEPX && owner) gstore(I.xs + s_j[jo], xo);
                 }
                 if constexpr (SCR) {
                     if (owner) {
@@ -428,6 +439,9 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
                     }
                 }
                 if constexpr (MODE == kModePow) cown = tot;
+                if constexpr (MODE == kModePowG) {
+                    if (owner) gstore(I.g + s_j[jo], tot);
+                }
             }
             if constexpr (ACC) {
 #pragma unroll
@@ -578,13 +592,15 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 // Partial reduction: kRedRows rows x 64 item-groups per workgroup (many
 // workgroups even for a few thousand rows), fixed summation order.  Each
 // thread issues U independent branch-free global loads (clamped addresses,
-// masked in the sum) before adding them in order.
+// masked in the sum) before adding them in order; the 64 group sums of a row
+// are then added by wave shuffles (4 groups per wave) and 16 per-wave sums.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(1024)
 void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems, int first)
 {
-    constexpr int TG = 1024 / kRedRows, U = 8;
+    constexpr int TG = 1024 / kRedRows, U = 4, NWV = 1024 / 64;
+    static_assert(kRedRows == 16, "four item-groups per wave");
     const RItem ri = ritems[blockIdx.x];
     const Inst& I = insts[ri.inst];
     const State& S = st[ri.inst];
@@ -597,6 +613,7 @@ void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RIte
     const int row = ri.rb * kRedRows + rowl;
     const int m = I.m;
     const int rowc = (row < m) ? row : m - 1;          // a valid row; its sum is not stored
+    const double ypv = (MODE == kRedPow) ? 0.0 : gload(I.yp + rowc);
     double s = 0.0, s2 = 0.0;
     for (int t0 = tg; t0 < T; t0 += TG * U) {
         double v[U], v2[U];
@@ -614,23 +631,33 @@ void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RIte
             if (MODE == kRedFold) s2 += ok ? v2[u] : 0.0;
         }
     }
-    __shared__ double sh[TG][kRedRows], sh2[(MODE == kRedFold) ? TG : 1][kRedRows];
-    sh[tg][rowl] = s;
-    if (MODE == kRedFold) sh2[tg][rowl] = s2;
+    // the wave's four groups of the same row: lanes l, l^16, l^32, l^48
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (MODE == kRedFold) {
+        s2 += __shfl_xor(s2, 16, 64);
+        s2 += __shfl_xor(s2, 32, 64);
+    }
+    __shared__ double sh[NWV][kRedRows], sh2[(MODE == kRedFold) ? NWV : 1][kRedRows];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < kRedRows) {
+        sh[wave][rowl] = s;
+        if (MODE == kRedFold) sh2[wave][rowl] = s2;
+    }
     __syncthreads();
     if (tg == 0 && row < m) {
         double tot = 0.0, tot2 = 0.0;
-#pragma unroll 16
-        for (int g = 0; g < TG; ++g) {
-            tot += sh[g][rowl];
-            if (MODE == kRedFold) tot2 += sh2[g][rowl];
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) {
+            tot += sh[w][rowl];
+            if (MODE == kRedFold) tot2 += sh2[w][rowl];
         }
         if constexpr (MODE == kRedResidual) {
-            I.r[row] = I.yp[row] - tot;
+            I.r[row] = ypv - tot;
         } else if constexpr (MODE == kRedAhead) {
-            I.r2[row] = I.yp[row] - tot;
+            I.r2[row] = ypv - tot;
         } else if constexpr (MODE == kRedFold) {
-            I.yp[row] -= tot;
+            I.yp[row] = ypv - tot;
             I.r[row] -= tot2;
         } else {
             I.r[row] = tot;
@@ -1316,13 +1343,20 @@ static hipError_t sweep_launch_t(const LaunchCtx& c, int mode, const Item* items
     constexpr int VV = (V < R) ? V : R;
     dim3 grid(n_items), block(TPC * NG);
 #define BXS_SW(MD) k_sweep<TA, TPC, NG, R, VV, CBI, PD, MD><<<grid, block, 0, c.stream>>>(c.insts, c.st, items, first)
+    // the fused forms are built only for shapes that hold them in registers,
+    // the two-pass forms only for the others
+    constexpr bool TWO = two_pass_shape(TPC, R);
     switch (mode) {
-    case kModePG: BXS_SW(kModePG); break;
     case kModeCorr: BXS_SW(kModeCorr); break;
     case kModeAx: BXS_SW(kModeAx); break;
     case kModeFold: BXS_SW(kModeFold); break;
-    case kModePow: BXS_SW(kModePow); break;
-    case kModePGS: BXS_SW(kModePGS); break;
+    case kModePG: if constexpr (!TWO) { BXS_SW(kModePG); break; } else { return hipErrorInvalidValue; }
+    case kModePow: if constexpr (!TWO) { BXS_SW(kModePow); break; } else { return hipErrorInvalidValue; }
+    case kModePGS: if constexpr (!TWO) { BXS_SW(kModePGS); break; } else { return hipErrorInvalidValue; }
+    case kModeStep: if constexpr (TWO) { BXS_SW(kModeStep); break; } else { return hipErrorInvalidValue; }
+    case kModeStepS: if constexpr (TWO) { BXS_SW(kModeStepS); break; } else { return hipErrorInvalidValue; }
+    case kModePowG: if constexpr (TWO) { BXS_SW(kModePowG); break; } else { return hipErrorInvalidValue; }
+    case kModeAg: if constexpr (TWO) { BXS_SW(kModeAg); break; } else { return hipErrorInvalidValue; }
     default: return hipErrorInvalidValue;
     }
 #undef BXS_SW

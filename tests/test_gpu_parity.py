@@ -126,7 +126,8 @@ def _hash_start(m):
 
 
 @pytest.mark.parametrize("m,n,dtype,steps", [(500, 1500, np.float32, 0), (500, 1500, np.float64, 3),
-                                             (777, 300, np.float32, 20), (6, 40, np.float64, 8)])
+                                             (777, 300, np.float32, 20), (6, 40, np.float64, 8),
+                                             (9000, 300, np.float32, 0), (16384, 100, np.float64, 12)])
 def test_step_estimate(m, n, dtype, steps):
     """The default step 1 / (1.05 L_est): L_est is the oracle's Lanczos
     estimate from the same start vector (8 steps by default), a lower bound of
@@ -277,6 +278,22 @@ def test_large_row_classes(m, n):
     xg, sg, info, res = check_parity(P, "bvls", **kw)
     free = (P.x_true > P.l) & (P.x_true < P.u)
     assert np.count_nonzero(sg) > 0 and not np.any(sg[free])
+
+
+def test_largest_class_nnls_two_pass():
+    """NNLS with the dual translation on the largest row class, whose sweeps
+    run as a dot pass and a product pass (step, screening sweep with the step
+    taken ahead, fold): screening fires and the trajectory matches the oracle."""
+    rng = W.rng_for(94, 0)
+    m, n = 9000, 600
+    # non-negative entries (t = -1 is interior), a strong diagonal block
+    A = 0.002 * rng.random((m, n))
+    A[:n, :] += np.diag(0.5 + rng.random(n))
+    P = W.Problem(np.asfortranarray(A.astype(np.float32)), rng.standard_normal(m), np.zeros(n), np.full(n, np.inf))
+    print(f"\n[two-pass nnls] m={m} n={n}", flush=True)
+    kw = dict(screen_every=10, eps_gap=1e-8, max_iter=5000, step=step_of(P))
+    xg, sg, info, res = check_parity(P, "nnls", **kw)
+    assert res.status == "ok" and info["n_lower"] > n // 2
 
 
 @pytest.mark.parametrize("scale", [0.015625, 4.0])
