@@ -150,7 +150,7 @@ static int device_cus()
 // (best for batches of small instances); above, the autotuner's choices on
 // one MI355X for a single instance with the class's largest row count and
 // four times as many columns (up to 256 MB).
-static int g_variant_pref[kNumDefaultVariants] = {0, 1, 2, 3, 12, 12, 18, 28, 29};
+static int g_variant_pref[kNumDefaultVariants] = {0, 1, 2, 3, 12, 12, 18, 31, 29};
 
 static int choose_variant(long m)
 {
@@ -168,8 +168,9 @@ static int choose_variant(long m)
 // products; set by bxs_set_group_scale).  Defaults from the autotuner on one
 // MI355X, as for the shapes; for 4000 x 16000 the spread 0.5 gives one
 // workgroup of 64 columns per CU (43 us per sweep against 49 us at 1), and
-// for 1000 x 3000 (FP64) 13.0 us per iteration against 14.3 us at 1.
-static double g_group_scale[kNumDefaultVariants] = {1, 1, 1, 1, 0.5, 0.5, 0.5, 1, 1};
+// for 1000 x 3000 (FP64) 13.0 us per iteration against 14.3 us at 1; for
+// 8000 x 8000 with the 512 x 16 shape 54 us against 62 us for 1024 x 8 at 1.
+static double g_group_scale[kNumDefaultVariants] = {1, 1, 1, 1, 0.5, 0.5, 0.5, 0.5, 1};
 
 static std::vector<int> group_targets(const std::vector<InstSpec>& specs, const std::vector<int>& variant, int cus)
 {
@@ -553,8 +554,10 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         void* pp = nullptr;
         bxs_status s = pinned(64, &pp);
         if (s != BXS_OK) return s;
-        hdone = (int*)pp;
+        hdone = (int*)pp;                                   // stop counter per slot: bytes 0..7
     }
+    double* hgap = (double*)((char*)hdone + 16);            // gap per slot: bytes 16..31
+    hgap[0] = hgap[1] = -1.0;
     const int K = o->screen_every;
     long long iters = 0;
     // Passes are enqueued one ahead of the stop check: while the host waits
@@ -579,6 +582,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     long sweep_launches = 0;
     long long slot_kk[2] = {0, 0};
     int slot_final[2] = {0, 0};
+    int slot_gap[2] = {0, 0};
 
     // The kernels of one pass: kk primal iterations, the correlation sweep,
     // the screening kernel and the fold.  `slot` selects the profile events.
@@ -615,7 +619,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
         }
         BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk, pg ? 1 : 0,
-                              host_done));
+                              host_done, (host_done && count == 1) ? hgap + slot : nullptr));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));
@@ -658,7 +662,18 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         BXS_HIP(hipEventRecord(dev_done[slot], stream));
         slot_kk[slot] = kk;
         slot_final[slot] = final_pass;
+        slot_gap[slot] = (count == 1 && !(gexec && kk == K && !final_pass)) ? 1 : 0;
         return BXS_OK;
+    };
+
+    // Single instance: the gaps of the last two passes predict the next one
+    // (linear convergence); when it is predicted below eps_gap, the pass after
+    // it is not enqueued ahead (it would only return at once), at the cost of
+    // one host reaction when the prediction fails.
+    double g_old = -1.0, g_new = -1.0;
+    auto predict_stop = [&]() -> bool {
+        if (!(g_old > 0.0) || !(g_new >= 0.0) || !(g_new < g_old)) return false;
+        return g_new * (g_new / g_old) < o->eps_gap;
     };
 
     int slot = 0;
@@ -669,12 +684,16 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     while (true) {
         const int nxt = slot ^ 1;
         bool queued_next = false;
-        if (!slot_final[slot]) {
+        if (!slot_final[slot] && !predict_stop()) {
             bxs_status s = enqueue_pass(nxt);
             if (s != BXS_OK) return s;
             queued_next = true;
         }
         BXS_HIP(hipEventSynchronize(dev_done[slot]));
+        if (slot_gap[slot]) {
+            g_old = g_new;
+            g_new = hgap[slot];
+        }
         if (o->profile) {
             for (long long k = 0; k < slot_kk[slot]; ++k) {
                 // PG: the first sweep of a pass returns at once when the step
@@ -687,7 +706,10 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             }
         }
         if (hdone[slot] >= count || slot_final[slot]) break;
-        if (!queued_next) break;
+        if (!queued_next) {
+            bxs_status s = enqueue_pass(nxt);
+            if (s != BXS_OK) return s;
+        }
         slot = nxt;
     }
     BXS_HIP(hipEventRecord(ev2, stream));

@@ -180,10 +180,13 @@ constexpr double kDotDepth = 64.0;
     X(26, 256, 1, 8, 2, 2)      \
     X(27, 512, 1, 4, 2, 2)      \
     X(28, 1024, 1, 8, 1, 2)     \
-    X(29, 1024, 1, 16, 1, 2)
+    X(29, 1024, 1, 16, 1, 2)     \
+    X(30, 512, 1, 16, 1, 1)      \
+    X(31, 512, 1, 16, 2, 1)      \
+    X(32, 512, 1, 16, 1, 2)
 
 struct VariantSpec { int tpc, ng, rows, cbi, pd; };
-constexpr int kNumVariants = 30;
+constexpr int kNumVariants = 33;
 constexpr int kNumDefaultVariants = 9;
 constexpr VariantSpec kVariants[kNumVariants] = {
 #define BXS_VS(ID, TPC, NG, R, CBI, PD) {TPC, NG, R, CBI, PD},
@@ -240,9 +243,11 @@ hipError_t launch_pow_init(const LaunchCtx& c, int count);
 hipError_t launch_set_step(const LaunchCtx& c, int count, double step);
 hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last);
 // host_done: pinned host word that receives the stop counter at the end of
-// the pass (nullptr: the caller copies it itself).
+// the pass (nullptr: the caller copies it itself); host_gap: pinned host
+// double that receives the gap of instance 0 (single-instance calls), or
+// nullptr.
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening,
-                         int final_pass, int K, int kk, int ahead, int* host_done);
+                         int final_pass, int K, int kk, int ahead, int* host_done, double* host_gap);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
 
 }  // namespace bxs

@@ -1209,10 +1209,13 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
 
 // One workgroup per instance.  With host_done set, the last workgroup to
 // finish (ticket counter next to the stop counter) also copies the stop
-// counter into host memory, so no separate copy follows the pass.
+// counter into host memory, so no separate copy follows the pass; with
+// host_gap set (single instance), it also copies the instance's gap, from
+// which the host predicts whether the next pass will stop.
 __global__ __launch_bounds__(1024)
 void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
-              double eps_gap, int screening, int final_pass, int K, int kk, int ahead, int* host_done)
+              double eps_gap, int screening, int final_pass, int K, int kk, int ahead, int* host_done,
+              double* host_gap)
 {
     screen_pass(insts, st, done_counter, eps_gap, screening, final_pass, K, kk, ahead);
     if (host_done == nullptr) return;
@@ -1224,6 +1227,7 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
         if (t == (int)gridDim.x - 1) {
             __threadfence();
             host_done[0] = atomicAdd(done_counter, 0);
+            if (host_gap) host_gap[0] = st[0].gap;
             atomicExch(ticket, 0);
         }
     }
@@ -1481,10 +1485,10 @@ hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last)
 }
 
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening, int final_pass,
-                         int K, int kk, int ahead, int* host_done)
+                         int K, int kk, int ahead, int* host_done, double* host_gap)
 {
     k_screen<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                        final_pass, K, kk, ahead, host_done);
+                                                        final_pass, K, kk, ahead, host_done, host_gap);
     return hipGetLastError();
 }
 
