@@ -732,12 +732,15 @@ void k_publish(const int* __restrict__ src, int* __restrict__ dst)
 
 // ---------------------------------------------------------------------------
 // Column statistics: rigorous norm bound, sum of squares, w = A^T t, and a
-// finiteness check of A.  One wave per column.
+// finiteness check of A.  One wave per column; each lane reads V consecutive
+// rows per 16-byte load (V = 1 when the columns are not 16-byte aligned) and
+// keeps U loads in flight before using them.
 // ---------------------------------------------------------------------------
-template <typename TA>
+template <typename TA, int V>
 __global__ __launch_bounds__(256)
 void k_colstats(const Inst* __restrict__ insts, State* __restrict__ st, const Item* __restrict__ items)
 {
+    constexpr int U = 8;
     const Item it = items[blockIdx.x];
     const Inst& I = insts[it.inst];
     State& S = st[it.inst];
@@ -746,35 +749,46 @@ void k_colstats(const Inst* __restrict__ insts, State* __restrict__ st, const It
     const int pos1 = min(pos0 + cb, I.n);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
-    const double gm = gamma_k((double)(I.m / 64) + 8.0);   // summation depth of this kernel
+    const double* __restrict__ t = I.t;
+    // each of the V chains of a lane adds at most m / (64 V) + 1 terms, then
+    // V chains and the 6-level wave butterfly: depth below m / 64 + 8
+    const double gm = gamma_k((double)(I.m / 64) + 8.0);
     int err = 0;
     const int m = I.m;
     for (int j = pos0 + wv; j < pos1; j += 4) {
         const TA* col = A + (long long)j * I.lda;
-        // four independent branch-free loads per lane and step (clamped rows,
-        // masked), four partial sums per lane added in a fixed order: the
-        // summation depth stays below m/64 + 8
-        double s2[4] = {0.0, 0.0, 0.0, 0.0}, sw[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int i0 = lane; i0 < m; i0 += 256) {
-            double a[4], tv[4];
+        double s2[V], sw[V];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + 64 * q;
-                const int ic = (i < m) ? i : lane;
-                a[q] = (double)gload(col + ic);
-                tv[q] = I.t ? gload(I.t + ic) : -1.0;
+        for (int e = 0; e < V; ++e) { s2[e] = 0.0; sw[e] = 0.0; }
+        for (int k0 = 0; k0 * 64 * V < m; k0 += U) {
+            TA a[U][V];
+            double tv[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int row = ((k0 + u) * 64 + lane) * V;
+                load_pack_nb<TA, V>(col, row, m, a[u]);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int rc = (row + e < m) ? row + e : 0;
+                    tv[u][e] = t ? gload(t + rc) : -1.0;
+                }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const bool ok = i0 + 64 * q < m;
-                const double av = ok ? a[q] : 0.0;
-                if (ok && !isfinite(av)) err = kErrNonfinite;
-                s2[q] = fma(av, av, s2[q]);
-                sw[q] = fma(av, tv[q], sw[q]);
-            }
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const bool ok = ((k0 + u) * 64 + lane) * V + e < m;
+                    const double av = ok ? (double)a[u][e] : 0.0;
+                    if (ok && !isfinite(av)) err = kErrNonfinite;
+                    s2[e] = fma(av, av, s2[e]);
+                    sw[e] = fma(av, tv[u][e], sw[e]);
+                }
         }
-        double s2t = wave_sum((s2[0] + s2[1]) + (s2[2] + s2[3]));
-        double swt = wave_sum((sw[0] + sw[1]) + (sw[2] + sw[3]));
+        double s2l = 0.0, swl = 0.0;
+#pragma unroll
+        for (int e = 0; e < V; ++e) { s2l += s2[e]; swl += sw[e]; }
+        const double s2t = wave_sum(s2l);
+        const double swt = wave_sum(swl);
         if (lane == 0) {
             I.cn2[j] = s2t;
             I.cn[j] = sqrt(s2t * (1.0 + gm)) * (1.0 + 2.0 * kUnit);
@@ -1447,10 +1461,14 @@ hipError_t launch_colstats(const LaunchCtx& c, int bucket, const Item* items, in
 {
     (void)bucket;
     if (n_items <= 0) return hipSuccess;
-    if (c.dtype == BXS_F32)
-        k_colstats<float><<<dim3(n_items), dim3(256), 0, c.stream>>>(c.insts, c.st, items);
-    else
-        k_colstats<double><<<dim3(n_items), dim3(256), 0, c.stream>>>(c.insts, c.st, items);
+    const dim3 g(n_items), b(256);
+    if (c.dtype == BXS_F32) {
+        if (c.vec) k_colstats<float, 4><<<g, b, 0, c.stream>>>(c.insts, c.st, items);
+        else k_colstats<float, 1><<<g, b, 0, c.stream>>>(c.insts, c.st, items);
+    } else {
+        if (c.vec) k_colstats<double, 2><<<g, b, 0, c.stream>>>(c.insts, c.st, items);
+        else k_colstats<double, 1><<<g, b, 0, c.stream>>>(c.insts, c.st, items);
+    }
     return hipGetLastError();
 }
 
