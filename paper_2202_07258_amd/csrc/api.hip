@@ -493,7 +493,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     // or a dot pass and a product pass for the shapes too large for the fused
     // kernel's registers.
     auto sweep_pg = [&](int b, int first) -> hipError_t {
-        if (!variant_two_pass(b)) return launch_sweep(c, b, kModePG, D.items[b], D.n_items[b], first);
+        if (!variant_two_pass(b)) return launch_sweep(c, b, first ? kModePG1 : kModePG, D.items[b], D.n_items[b]);
         const hipError_t e = launch_sweep(c, b, kModeStep, D.items[b], D.n_items[b], first);
         return e != hipSuccess ? e : launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b], first);
     };

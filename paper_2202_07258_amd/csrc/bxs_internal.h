@@ -116,7 +116,10 @@ enum SweepMode : int {
     kModeStep = 6,          // kModePG without the product: x <- Pi(x + eta g)
     kModeStepS = 7,         // kModePGS without the product
     kModePowG = 8,          // g = A^T r stored
-    kModeAg = 9             // partial += A g
+    kModeAg = 9,            // partial += A g
+    kModePG1 = 10           // kModePG for the first iteration of a pass: returns at once
+                            // when the previous screening pass took this step (a kernel
+                            // of its own, so profiles separate it from the full sweeps)
 };
 
 // Shapes that run the PG step, the screening sweep and the products with

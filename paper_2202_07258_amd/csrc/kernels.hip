@@ -213,7 +213,8 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 {
     constexpr int RO = R / V;
     constexpr bool SCR = (MODE == kModeCorr || MODE == kModePGS || MODE == kModeStepS);  // screening at x
-    constexpr bool STP = (MODE == kModePG || MODE == kModePGS || MODE == kModeStep || MODE == kModeStepS);
+    constexpr bool STP = (MODE == kModePG || MODE == kModePG1 || MODE == kModePGS || MODE == kModeStep ||
+                          MODE == kModeStepS);
     constexpr bool KEEPX = (MODE == kModePGS || MODE == kModeStepS);  // x kept in xs
     constexpr bool DOT = (STP || SCR || MODE == kModePow || MODE == kModePowG);
     constexpr bool ACC = !(MODE == kModeCorr || MODE == kModeStep || MODE == kModeStepS || MODE == kModePowG);
@@ -228,7 +229,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     const Inst& I = insts[it.inst];
     State& S = st[it.inst];
     if (S.done) return;
-    if ((MODE == kModePG || MODE == kModeStep || MODE == kModeAx) && first && S.ahead) return;
+    if ((MODE == kModePG1 || ((MODE == kModeStep || MODE == kModeAx) && first)) && S.ahead) return;
     const int nlist = (MODE == kModeFold) ? S.n_fold : S.n_active;
     const int cb = (MODE == kModeFold) ? S.cb_fold : S.cb;
     const int pos0 = it.t * cb;
@@ -1369,6 +1370,7 @@ static hipError_t sweep_launch_t(const LaunchCtx& c, int mode, const Item* items
     case kModeAx: BXS_SW(kModeAx); break;
     case kModeFold: BXS_SW(kModeFold); break;
     case kModePG: if constexpr (!TWO) { BXS_SW(kModePG); break; } else { return hipErrorInvalidValue; }
+    case kModePG1: if constexpr (!TWO) { BXS_SW(kModePG1); break; } else { return hipErrorInvalidValue; }
     case kModePow: if constexpr (!TWO) { BXS_SW(kModePow); break; } else { return hipErrorInvalidValue; }
     case kModePGS: if constexpr (!TWO) { BXS_SW(kModePGS); break; } else { return hipErrorInvalidValue; }
     case kModeStep: if constexpr (TWO) { BXS_SW(kModeStep); break; } else { return hipErrorInvalidValue; }
