@@ -1,0 +1,80 @@
+"""The headline workload at its full size (BVLS 4000 x 16000, FP32 storage) in
+the launch configuration the benchmark times (default sweep shape, work-item
+spread and options): trajectory parity with the oracle on the instance as
+specified, and, on the planted companion of the same shape where screening
+fires, the safety of every screened coordinate against the planted optimum."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import boxls as ob
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _hash_start(m):
+    """Start vector of the library's Lanczos estimate: 1 +- 1/4 by the top bit
+    of Knuth's multiplicative hash i * 2654435761 mod 2^32 of the row index."""
+    h = (np.arange(m, dtype=np.uint64) * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)
+    return np.where((h >> np.uint64(31)) != 0, 1.25, 0.75)
+
+
+def _dev(P):
+    import paper_2202_07258_amd as bx
+    A = bx.colmajor(P.A, device="cuda")
+    y, l, u = (torch.tensor(v, dtype=torch.float64, device="cuda") for v in (P.y, P.l, P.u))
+    return A, y, l, u
+
+
+def _oracle_gap(A64, P, x):
+    """The oracle's gap at theta = y - Ax (every u_j finite), per-coordinate
+    form.  It and the certified gap (taken at the library's own rounded
+    residual, with margins) are two upper bounds of P(x) - P*, at two dual
+    points a rounding apart: they agree closely but are not ordered."""
+    assert np.all(np.isfinite(P.u))
+    return ob.gap_closed_form(A64, P.y, P.l, P.u, x, 0.0, None)
+
+
+def test_c2_full_size_trajectory():
+    import paper_2202_07258_amd as bx
+    P = W.c2_bvls(0)
+    print(f"\n[c2 full size] m={P.m} n={P.n}", flush=True)
+    A64 = P.A64()
+    L = ob.lipschitz_lanczos(A64, 8, _hash_start(P.m))
+    eta = 1.0 / (1.05 * L)
+    A, y, l, u = _dev(P)
+    # the default step is the oracle's Lanczos estimate from the same start
+    _, _, info0 = bx.solve_bvls(A, y, l, u, eps_gap=1e-6, screen_every=10, max_iter=10)
+    assert info0["lipschitz"] == pytest.approx(L, rel=1e-9)
+    x, sat, info = bx.solve_bvls(A, y, l, u, eps_gap=1e-6, screen_every=10, step=eta)
+    res = ob.solve(A64, P.y, P.l, P.u, K=10, eps_gap=1e-6, step=eta)
+    xg, sg = x.cpu().numpy(), sat.cpu().numpy()
+    assert info["status_name"] == "ok" and res.status == "ok"
+    assert info["iters"] == res.iters and info["passes"] == res.passes
+    assert np.max(np.abs(xg - res.x)) <= 1e-8 * max(1.0, float(np.max(np.abs(res.x))))
+    assert np.array_equal(sg, res.sat) and np.count_nonzero(sg) == 0   # zero-residual optimum
+    # the optimum has zero residual (P* = 0), so P(x) itself must lie below the
+    # certified gap; the oracle's gap at x agrees with it
+    assert info["gap"] < 1e-6 and ob.primal(A64, P.y, xg) <= info["gap"] * (1 + 1e-6)
+    assert _oracle_gap(A64, P, xg) == pytest.approx(info["gap"], rel=1e-5)
+
+
+def test_c2_planted_full_size_safety():
+    import paper_2202_07258_amd as bx
+    P = W.c2_planted(0)
+    print(f"\n[c2-pl full size] m={P.m} n={P.n}", flush=True)
+    A64 = P.A64()
+    A, y, l, u = _dev(P)
+    x, sat, info = bx.solve_bvls(A, y, l, u, eps_gap=1e-6, screen_every=10)
+    xg, sg = x.cpu().numpy(), sat.cpu().numpy()
+    assert info["status_name"] == "ok" and np.count_nonzero(sg) > P.n // 2
+    # every screened coordinate is saturated at the planted optimum, on its side
+    lo, hi = sg == -1, sg == 1
+    assert np.all(P.x_true[lo] == P.l[lo]) and np.all(P.x_true[hi] == P.u[hi])
+    assert np.all(xg[lo] == P.l[lo]) and np.all(xg[hi] == P.u[hi])
+    # the certified gap bounds the suboptimality against the planted optimum
+    sub = ob.primal(A64, P.y, xg) - ob.primal(A64, P.y, P.x_true)
+    assert info["gap"] < 1e-6 and sub <= info["gap"] + 1e-10
+    assert _oracle_gap(A64, P, xg) == pytest.approx(info["gap"], rel=1e-5)
+    assert np.max(np.abs(xg - P.x_true)) < 1e-5

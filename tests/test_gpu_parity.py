@@ -186,12 +186,13 @@ def test_determinism():
     assert np.array_equal(x1, x2) and np.array_equal(s1, s2) and i1["iters"] == i2["iters"]
 
 
-@pytest.mark.parametrize("solver", ["pg", "cd"])
-def test_graph_replay_matches_direct_launches(solver):
+@pytest.mark.parametrize("solver,m,n", [("pg", 300, 900), ("cd", 300, 900), ("pg", 9000, 400)])
+def test_graph_replay_matches_direct_launches(solver, m, n):
     """Regular passes replayed from one captured HIP graph give bit-identical
     results to direct launches, with the program's own eager work (other
-    solves, host synchronisation) between calls; pass records agree too."""
-    P = planted(16, 300, 900, dtype=np.float32)
+    solves, host synchronisation) between calls; pass records agree too.
+    The 9000-row case replays the two-pass sweeps of the largest row class."""
+    P = planted(16, m, n, dtype=np.float32)
     eta = step_of(P)
     kw = dict(solver=solver, eps_gap=1e-9, max_iter=4000, step=eta, screen_every=5, history=1000)
     xd, sd, idd = run_gpu(P, "bvls", graph=False, **kw)
