@@ -983,9 +983,55 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
     const double u1 = kUnit;
     const bool nnls_like = (I.u == nullptr);   // every u_j = +inf
 
+    // ||r||^2 and the per-item quantities written by the correlation sweep
+    // (mass, interior flag of t, largest translation ratio, presence of
+    // u = +inf columns, gap terms and largest screening score at eps = 0),
+    // combined over the workgroup in one reduction
     double a = 0.0;
     for (int i = tid; i < m; i += NT) a = fma(I.r[i], I.r[i], a);
-    const double rsq = block_sum<NT>(a, sh);
+    const int T = (nA + S.cb - 1) / S.cb;
+    double red7[7] = {a, 0.0, 0.0, 1.0, 0.0, 0.0, -__builtin_inf()};   // rsq mass gap0 | tv | emax hasinf z0
+    for (int t = tid; t < T; t += NT) {
+        const double* o = I.iscal + (size_t)t * kItemScalars;
+        red7[1] += o[kIsMass];
+        red7[2] += o[kIsGap0];
+        red7[3] = fmin(red7[3], o[kIsTv]);
+        red7[4] = fmax(red7[4], o[kIsEmax]);
+        red7[5] = fmax(red7[5], o[kIsHasInf]);
+        red7[6] = fmax(red7[6], o[kIsZmax0]);
+    }
+    {
+        __shared__ double sh7[7][NT / 64];
+        red7[0] = wave_sum(red7[0]);
+        red7[1] = wave_sum(red7[1]);
+        red7[2] = wave_sum(red7[2]);
+        red7[3] = wave_min(red7[3]);
+        red7[4] = wave_max(red7[4]);
+        red7[5] = wave_max(red7[5]);
+        red7[6] = wave_max(red7[6]);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) sh7[k][wave] = red7[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) tot += sh7[k][w];
+            red7[k] = tot;
+        }
+        double mn = sh7[3][0], m4 = sh7[4][0], m5 = sh7[5][0], m6 = sh7[6][0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) {
+            mn = fmin(mn, sh7[3][w]);
+            m4 = fmax(m4, sh7[4][w]);
+            m5 = fmax(m5, sh7[5][w]);
+            m6 = fmax(m6, sh7[6][w]);
+        }
+        red7[3] = mn; red7[4] = m4; red7[5] = m5; red7[6] = m6;
+    }
+    const double rsq = red7[0];
     const double rnorm = sqrt(rsq * (1.0 + gamma_k((double)(m / NT) + 24.0))) * (1.0 + 2.0 * u1);
     // error bounds of the correlations g_j (sweep kernels) and of w_j = a_j^T t
     // (column statistics), by Cauchy-Schwarz: sum_i |a_ij v_i| <= ||a_j|| ||v||
@@ -1016,26 +1062,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
         }
     };
 
-    // Combine the per-item quantities written by the correlation sweep: mass,
-    // interior flag of t, largest translation ratio, presence of u = +inf
-    // columns, gap terms and largest screening score at eps = 0.
-    const int T = (nA + S.cb - 1) / S.cb;
-    double tv = 1.0, emax = 0.0, mass = 0.0, hasinf = 0.0, gap0 = 0.0, z0 = -__builtin_inf();
-    for (int t = tid; t < T; t += NT) {
-        const double* o = I.iscal + (size_t)t * kItemScalars;
-        mass += o[kIsMass];
-        tv = fmin(tv, o[kIsTv]);
-        emax = fmax(emax, o[kIsEmax]);
-        hasinf = fmax(hasinf, o[kIsHasInf]);
-        gap0 += o[kIsGap0];
-        z0 = fmax(z0, o[kIsZmax0]);
-    }
-    tv = block_min<NT>(tv, sh);
-    emax = block_max<NT>(emax, sh);
-    mass = block_sum<NT>(mass, sh);
-    hasinf = block_max<NT>(hasinf, sh);
-    gap0 = block_sum<NT>(gap0, sh);
-    z0 = block_max<NT>(z0, sh);
+    const double tv = red7[3], emax = red7[4], mass = red7[1], hasinf = red7[5], gap0 = red7[2], z0 = red7[6];
     const bool has_inf = hasinf > 0.5;
     const bool fallback = has_inf && !(tv > 0.5);
     const double eps = (has_inf && !fallback) ? emax * (1.0 + 4.0 * u1) : 0.0;
