@@ -486,7 +486,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     } stage_guard{stream};
 
     LaunchCtx c;
-    c.stream = stream; c.dtype = dtype; c.vec = P.vec;
+    c.stream = stream; c.dtype = dtype; c.vec = P.vec; c.single = (count == 1) ? 1 : 0;
     c.insts = D.insts; c.st = D.st; c.done_counter = D.done_counter;
 
     // Sweeps that read A and also accumulate a product with A: one fused pass,

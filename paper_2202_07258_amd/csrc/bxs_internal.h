@@ -227,6 +227,7 @@ struct LaunchCtx {
     hipStream_t stream;
     int dtype;              // bxs_dtype
     int vec;                // 1: 16-byte loads of A are valid for every instance
+    int single;             // 1: one instance (work item k is {0, k}, row block k is {0, k})
     const Inst* insts;
     State* st;
     int* done_counter;

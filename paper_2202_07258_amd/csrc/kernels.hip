@@ -209,7 +209,8 @@ __device__ __forceinline__ int lane_of_col(int c) { return c << (6 - Log2C<CBI>:
 // ---------------------------------------------------------------------------
 template <typename TA, int TPC, int NG, int R, int V, int CBI, int PD, int MODE>
 __global__ __launch_bounds__(TPC * NG)
-void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item* __restrict__ items, int first)
+void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item* __restrict__ items, int first,
+             int single)
 {
     constexpr int RO = R / V;
     constexpr bool SCR = (MODE == kModeCorr || MODE == kModePGS || MODE == kModeStepS);  // screening at x
@@ -225,7 +226,9 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     static_assert(R % V == 0, "rows per thread must be a multiple of the vector width");
     static_assert(TPC % 64 == 0, "a column group is whole waves");
 
-    const Item it = items[blockIdx.x];
+    // a single instance's items are {0, blockIdx.x}: no table load on the
+    // critical path of the launch
+    const Item it = single ? Item{0, (int)blockIdx.x} : items[blockIdx.x];
     const Inst& I = insts[it.inst];
     State& S = st[it.inst];
     if (S.done) return;
@@ -598,11 +601,12 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(1024)
-void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems, int first)
+void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems, int first,
+              int single)
 {
     constexpr int TG = 1024 / kRedRows, U = 4, NWV = 1024 / 64;
     static_assert(kRedRows == 16, "four item-groups per wave");
-    const RItem ri = ritems[blockIdx.x];
+    const RItem ri = single ? RItem{0, (int)blockIdx.x} : ritems[blockIdx.x];
     const Inst& I = insts[ri.inst];
     const State& S = st[ri.inst];
     if (S.done) return;
@@ -1388,7 +1392,7 @@ static hipError_t sweep_launch_t(const LaunchCtx& c, int mode, const Item* items
 {
     constexpr int VV = (V < R) ? V : R;
     dim3 grid(n_items), block(TPC * NG);
-#define BXS_SW(MD) k_sweep<TA, TPC, NG, R, VV, CBI, PD, MD><<<grid, block, 0, c.stream>>>(c.insts, c.st, items, first)
+#define BXS_SW(MD) k_sweep<TA, TPC, NG, R, VV, CBI, PD, MD><<<grid, block, 0, c.stream>>>(c.insts, c.st, items, first, c.single)
     // the fused forms are built only for shapes that hold them in registers,
     // the two-pass forms only for the others
     constexpr bool TWO = two_pass_shape(TPC, R);
@@ -1471,10 +1475,10 @@ hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int 
     if (n_ritems <= 0) return hipSuccess;
     dim3 grid(n_ritems), block(1024);
     switch (mode) {
-    case kRedResidual: k_reduce<kRedResidual><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first); break;
-    case kRedFold: k_reduce<kRedFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first); break;
-    case kRedPow: k_reduce<kRedPow><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first); break;
-    case kRedAhead: k_reduce<kRedAhead><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first); break;
+    case kRedResidual: k_reduce<kRedResidual><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first, c.single); break;
+    case kRedFold: k_reduce<kRedFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first, c.single); break;
+    case kRedPow: k_reduce<kRedPow><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first, c.single); break;
+    case kRedAhead: k_reduce<kRedAhead><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first, c.single); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
