@@ -205,7 +205,11 @@ __device__ __forceinline__ int lane_of_col(int c) { return c << (6 - Log2C<CBI>:
 // and the next projected-gradient step from x, which needs the same g: the
 // step is taken ahead of the test.  x is kept in xs and the new residual goes
 // to r2, so the screening pass can either keep the step (nothing screened,
-// no stop) or return to x.
+// no stop) or return to x.  kModePG1 (the first iteration of the next pass)
+// then returns at once; so do the two-pass forms' kernels launched with
+// first = 1.  For the shapes too large to keep the residual and the partial
+// product in registers the residual is staged in LDS and the products run as
+// a dot pass and a product pass (two_pass_shape).
 // ---------------------------------------------------------------------------
 template <typename TA, int TPC, int NG, int R, int V, int CBI, int PD, int MODE>
 __global__ __launch_bounds__(TPC * NG)
