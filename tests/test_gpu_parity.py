@@ -93,6 +93,30 @@ def test_pg_nnls_user_direction():
     xg, sg, info, res = check_parity(P, "nnls", **kw)
 
 
+def test_pg_nnls_tall_full_rank_direction():
+    """Prop. 2, first case: a tall full-rank A (n <= m), signed entries, and t
+    solving A^T t = -1 is interior; the translated dual point then screens."""
+    rng = W.rng_for(95, 0)
+    m, n = 120, 80
+    A = np.asfortranarray(W.unit_columns(rng.standard_normal((m, n))))
+    t, *_ = np.linalg.lstsq(A.T, -np.ones(n), rcond=None)      # least-norm solution, A^T t = -1
+    assert np.allclose(A.T @ t, -1.0) and ob.interior_direction_ok(A, np.full(n, np.inf), t)
+    y = A @ np.maximum(rng.standard_normal(n), 0.0) - 0.5 * rng.random(m)
+    P = W.Problem(A, y, np.zeros(n), np.full(n, np.inf))
+    kw = dict(screen_every=5, eps_gap=1e-10, max_iter=20000, step=step_of(P), t=t)
+    xg, sg, info, res = check_parity(P, "nnls", **kw)
+    assert res.status == "ok" and info["t_valid"] == 1
+
+
+def test_pg_linf_box_special_case():
+    """App. A: the l-infinity-constrained problem (u = -l = c 1) is a BVLS
+    instance; parity with the oracle, and coordinates screened at both ends."""
+    P = planted(23, 300, 900, box=(-0.3, 0.3))
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=4000, step=step_of(P))
+    xg, sg, info, res = check_parity(P, "bvls", **kw)
+    assert np.count_nonzero(sg == -1) > 0 and np.count_nonzero(sg == 1) > 0
+
+
 def test_pg_mixed_bounds():
     rng = W.rng_for(92, 0)
     P = W.c1_companion(1, 100, 260)
