@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <string>
+#include <chrono>
 #include <vector>
 
 #include "bxs_internal.h"
@@ -367,6 +368,8 @@ static bxs_status staging(size_t bytes, void** out)
     return BXS_OK;
 }
 
+// Coherent (fine-grained) pinned words the screening kernel writes for the
+// host: the stop counter, the gap and the pass sequence number.
 static bxs_status pinned(size_t bytes, void** out)
 {
     static thread_local PinnedBuf buf;
@@ -374,7 +377,7 @@ static bxs_status pinned(size_t bytes, void** out)
         if (buf.p) (void)hipHostFree(buf.p);
         buf.p = nullptr;
         buf.bytes = 0;
-        BXS_HIP(hipHostMalloc(&buf.p, bytes, hipHostMallocDefault));
+        BXS_HIP(hipHostMalloc(&buf.p, bytes, hipHostMallocCoherent));
         buf.bytes = bytes;
     }
     *out = buf.p;
@@ -453,7 +456,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     // Host image of the tables (descriptors, zeroed states, work items,
     // reduction items, CD lists, zeroed stop counter and ticket), uploaded
     // with one copy from pinned memory.
-    const size_t tbytes = (size_t)((char*)(D.done_counter + 2) - (char*)D.insts);
+    const size_t tbytes = (size_t)((char*)(D.done_counter + 3) - (char*)D.insts);   // + ticket, pass count
     const size_t sbytes = sizeof(State) * count;
     void* stage_p = nullptr;
     {
@@ -558,6 +561,8 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     }
     double* hgap = (double*)((char*)hdone + 16);            // gap per slot: bytes 16..31
     hgap[0] = hgap[1] = -1.0;
+    int* hseq = (int*)((char*)hdone + 32);                  // passes published: bytes 32..35
+    __atomic_store_n(hseq, 0, __ATOMIC_RELEASE);
     const int K = o->screen_every;
     long long iters = 0;
     // Passes are enqueued one ahead of the stop check: while the host waits
@@ -592,6 +597,12 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     // instead of kk + 1.  Every iterate is the one of the plain order (test,
     // fold, step): the step is only kept when the test fixed nothing.
     const bool pg = o->solver == BXS_PG;
+    // Direct launches without profiling: the host waits for a pass by reading
+    // the pass count the screening kernel publishes (no completion event
+    // between passes on the stream); graph replay and profiling use events.
+    const bool poll = !o->profile && !want_graph;
+    int enq_passes = 0;
+    int slot_seq[2] = {0, 0};
     // host_done: where the screening kernel publishes the stop counter
     // (nullptr inside a captured graph: a copy kernel follows the replay).
     auto enqueue_kernels = [&](int slot, long long kk, int final_pass, int* host_done) -> bxs_status {
@@ -619,7 +630,8 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
         }
         BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk, pg ? 1 : 0,
-                              host_done, (host_done && count == 1) ? hgap + slot : nullptr));
+                              host_done, (host_done && count == 1) ? hgap + slot : nullptr,
+                              (host_done && poll) ? hseq : nullptr));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));
@@ -659,7 +671,8 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             const bxs_status es = enqueue_kernels(slot, kk, final_pass, hdone + slot);
             if (es != BXS_OK) return es;
         }
-        BXS_HIP(hipEventRecord(dev_done[slot], stream));
+        if (poll) slot_seq[slot] = ++enq_passes;
+        else BXS_HIP(hipEventRecord(dev_done[slot], stream));
         slot_kk[slot] = kk;
         slot_final[slot] = final_pass;
         slot_gap[slot] = (count == 1 && !(gexec && kk == K && !final_pass)) ? 1 : 0;
@@ -689,7 +702,21 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             if (s != BXS_OK) return s;
             queued_next = true;
         }
-        BXS_HIP(hipEventSynchronize(dev_done[slot]));
+        if (poll) {
+            // spin on the coherent word; should it not advance (it always
+            // does), the stream's completion makes every published value final
+            const auto t0 = std::chrono::steady_clock::now();
+            long spins = 0;
+            while (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) < slot_seq[slot]) {
+                __builtin_ia32_pause();
+                if ((++spins & 4095) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+                    BXS_HIP(hipStreamSynchronize(stream));
+                    break;
+                }
+            }
+        } else {
+            BXS_HIP(hipEventSynchronize(dev_done[slot]));
+        }
         if (slot_gap[slot]) {
             g_old = g_new;
             g_new = hgap[slot];

@@ -249,9 +249,11 @@ hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last);
 // host_done: pinned host word that receives the stop counter at the end of
 // the pass (nullptr: the caller copies it itself); host_gap: pinned host
 // double that receives the gap of instance 0 (single-instance calls), or
-// nullptr.
+// nullptr; host_seq: pinned (coherent) host word that receives the number of
+// screening passes run, written last with a system-scope release, or nullptr.
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening,
-                         int final_pass, int K, int kk, int ahead, int* host_done, double* host_gap);
+                         int final_pass, int K, int kk, int ahead, int* host_done, double* host_gap,
+                         int* host_seq);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
 
 }  // namespace bxs

@@ -1261,11 +1261,14 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
 // finish (ticket counter next to the stop counter) also copies the stop
 // counter into host memory, so no separate copy follows the pass; with
 // host_gap set (single instance), it also copies the instance's gap, from
-// which the host predicts whether the next pass will stop.
+// which the host predicts whether the next pass will stop; with host_seq set
+// it then stores the number of screening passes run so far (a counter after
+// the ticket) with a system-scope release, so the host can wait for the pass
+// by reading that word instead of a completion event.
 __global__ __launch_bounds__(1024)
 void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
               double eps_gap, int screening, int final_pass, int K, int kk, int ahead, int* host_done,
-              double* host_gap)
+              double* host_gap, int* host_seq)
 {
     screen_pass(insts, st, done_counter, eps_gap, screening, final_pass, K, kk, ahead);
     if (host_done == nullptr) return;
@@ -1279,6 +1282,11 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
             host_done[0] = atomicAdd(done_counter, 0);
             if (host_gap) host_gap[0] = st[0].gap;
             atomicExch(ticket, 0);
+            if (host_seq) {
+                const int seq = atomicAdd(done_counter + 2, 1) + 1;
+                __threadfence_system();
+                __hip_atomic_store(host_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
     }
 }
@@ -1540,10 +1548,10 @@ hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last)
 }
 
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening, int final_pass,
-                         int K, int kk, int ahead, int* host_done, double* host_gap)
+                         int K, int kk, int ahead, int* host_done, double* host_gap, int* host_seq)
 {
     k_screen<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                        final_pass, K, kk, ahead, host_done, host_gap);
+                                                        final_pass, K, kk, ahead, host_done, host_gap, host_seq);
     return hipGetLastError();
 }
 
