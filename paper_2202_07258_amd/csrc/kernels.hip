@@ -613,18 +613,36 @@ void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RIte
     const RItem ri = single ? RItem{0, (int)blockIdx.x} : ritems[blockIdx.x];
     const Inst& I = insts[ri.inst];
     const State& S = st[ri.inst];
+    const int rowl = threadIdx.x % kRedRows, tg = threadIdx.x / kRedRows;
+    const int row = ri.rb * kRedRows + rowl;
+    const int m = I.m;
+    const int rowc = (row < m) ? row : m - 1;          // a valid row; its sum is not stored
+    // The first round of loads goes out before the instance's state is read:
+    // every slot below items_cap is a valid partial (the number in use, T,
+    // is never larger; the others are masked below).
+    const int Tcap = I.items_cap;
+    double v0[U], w0[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int t = tg + u * TG;
+        const size_t off = (size_t)((t < Tcap) ? t : 0) * m + rowc;
+        v0[u] = gload(I.part + off);
+        if (MODE == kRedFold) w0[u] = gload(I.part2 + off);
+    }
+    const double ypv = (MODE == kRedPow) ? 0.0 : gload(I.yp + rowc);
     if (S.done) return;
     if (MODE == kRedResidual && first && S.ahead) return;
     const int nlist = (MODE == kRedFold) ? S.n_fold : S.n_active;
     const int cb = (MODE == kRedFold) ? S.cb_fold : S.cb;
     const int T = (nlist + cb - 1) / cb;
-    const int rowl = threadIdx.x % kRedRows, tg = threadIdx.x / kRedRows;
-    const int row = ri.rb * kRedRows + rowl;
-    const int m = I.m;
-    const int rowc = (row < m) ? row : m - 1;          // a valid row; its sum is not stored
-    const double ypv = (MODE == kRedPow) ? 0.0 : gload(I.yp + rowc);
     double s = 0.0, s2 = 0.0;
-    for (int t0 = tg; t0 < T; t0 += TG * U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool ok = tg + u * TG < T;
+        s += ok ? v0[u] : 0.0;
+        if (MODE == kRedFold) s2 += ok ? w0[u] : 0.0;
+    }
+    for (int t0 = tg + TG * U; t0 < T; t0 += TG * U) {
         double v[U], v2[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
