@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 METRIC = "solves/sec to gap 1e-6 (screened vs unscreened), HBM GB/s % of peak"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pg_sweep_c2_traffic.md")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_2202_07258_amd", "csrc", "kernels.hip")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2202_07258_amd", "csrc", "sweep.h")
 
 
 def log(*a):
@@ -95,15 +95,14 @@ def sweep_roofline(infos, m, elem_bytes):
 
 
 def _source_digest(path):
-    """Digest of the column-sweep kernel's source text (from its header
-    comment to the partial-reduction kernel that follows it)."""
+    """Digest of the column-sweep kernel's source text (the whole of sweep.h:
+    the kernel template and its launchers)."""
     import hashlib
-    with open(path, encoding="utf-8") as f:
-        text = f.read()
-    i, j = text.find("// Column sweep."), text.find("// Partial reduction")
-    if i < 0 or j < i:
+    try:
+        with open(path, "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
         return None
-    return hashlib.sha256(text[i:j].encode()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, m):

@@ -197,6 +197,9 @@ constexpr VariantSpec kVariants[kNumVariants] = {
 #undef BXS_VS
 };
 
+// Translation units the 16-byte-load sweep variants are split over.
+constexpr int kSweepParts = 3;
+
 inline long variant_capacity(int v) { return (long)kVariants[v].tpc * kVariants[v].rows; }
 inline bool variant_two_pass(int v) { return two_pass_shape(kVariants[v].tpc, kVariants[v].rows); }
 

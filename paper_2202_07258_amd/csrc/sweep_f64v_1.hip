@@ -1,0 +1,9 @@
+// Instantiation unit of the column sweep: double storage, 16-byte loads, variants with id % kSweepParts == 1.
+#include "sweep.h"
+
+namespace bxs {
+hipError_t sweep_f64v_1(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items, int first)
+{
+    return sweep_dispatch_part<double, 2, kSweepParts, 1>(c, variant, mode, items, n_items, first);
+}
+}  // namespace bxs
