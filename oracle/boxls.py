@@ -65,26 +65,32 @@ def duality_gap(A, y, l, u, x, theta) -> float:
     return primal(A, y, x) - dual(A, y, l, u, theta)
 
 
-def gap_closed_form(A, y, l, u, x, eps, t) -> float:
-    """Per-coordinate form of the gap at theta = (y - Ax) + eps t.
+def gap_per_coordinate(A, y, l, u, x, theta) -> float:
+    """Gap(x, theta) = P(x) - D(theta) (eq. Dual_Gap) rewritten as a sum of
+    per-coordinate terms, the form the screening loop evaluates.
 
-    Substituting theta into eq. Dual_obj with f* from Sec. 5:
-    1/2||y||^2 - 1/2||y - theta||^2 = 1/2||y||^2 - 1/2||Ax - eps t||^2, so
-    P - D = -<theta, Ax> + 1/2 eps^2 ||t||^2 + sum_j (l_j [g_j]^- + u_j [g_j]^+)
-    with g = A^T theta, and -x_j g_j + l_j[g_j]^- + u_j[g_j]^+ regroups into
-        sum_j (u_j - x_j)[g_j]^+ + (x_j - l_j)[-g_j]^+ + 1/2 eps^2 ||t||^2;
-    a term with u_j = +inf and g_j <= 0 contributes 0.
-    Used only as a cross-check of ``duality_gap``."""
+    From eq. Dual_obj with f* of Sec. 5,
+        -sum_i f*(-theta_i; y_i) = 1/2 ||y||^2 - 1/2 ||y - theta||^2,
+    and with rho = y - Ax, y - theta = Ax + (rho - theta), so that
+        P(x) - D(theta) = sum_j (-x_j c_j + l_j [c_j]^- + u_j [c_j]^+) + 1/2 ||rho - theta||^2,
+    c = A^T theta, the u_j term only for finite u_j (eq. Dual_obj).  Per
+    coordinate, for l_j <= x_j <= u_j:
+        finite u_j:  (u_j - x_j) [c_j]^+ + (x_j - l_j) [-c_j]^+        (>= 0)
+        u_j = +inf:  (x_j - l_j) [-c_j]^+ - x_j [c_j]^+                 (>= 0 on F_D)
+    No two large numbers are subtracted, so rounding cannot drive the value
+    toward zero while a coordinate inside the box still has a correlation of
+    its own (its term keeps the radius sqrt(2 Gap) above that correlation),
+    unlike P - D, whose two sides are each of the size of 1/2 ||y||^2."""
     A = np.asarray(A, dtype=np.float64)
-    theta = (y - A @ x) + (eps * t if eps else 0.0)
-    g = A.T @ theta
-    pos = np.maximum(g, 0.0)
-    up = np.zeros_like(pos)
-    k = pos > 0                                         # 0 * inf := 0
-    up[k] = (u[k] - x[k]) * pos[k]
-    lo = (x - l) * np.maximum(-g, 0.0)
-    tt = 0.0 if not eps else 0.5 * eps * eps * float(t @ t)
-    return float(np.sum(up) + np.sum(lo)) + tt
+    rho = y - A @ x
+    c = A.T @ theta
+    pos, neg = np.maximum(c, 0.0), np.maximum(-c, 0.0)
+    fin = np.isfinite(u)
+    terms = (x - l) * neg
+    terms[fin] += (u[fin] - x[fin]) * pos[fin]
+    terms[~fin] -= x[~fin] * pos[~fin]
+    d = rho - theta
+    return float(np.sum(terms)) + 0.5 * float(d @ d)
 
 
 # ---------------------------------------------------------------------------
@@ -145,9 +151,7 @@ def dual_point(A, y, u, x, t):
 def safe_radius(gap: float, alpha: float = 1.0) -> float:
     """r = sqrt(2 Gap / alpha) (eq. GAP_Safe_sph); alpha = 1 for LS since f''=1.
     A gap that rounds below zero is taken as zero.  Plain FP64 without
-    rounding margins: the rule built on it is safe while the gap is well above
-    its rounding floor (about 1e-16 times the primal value), which is where
-    the tests stop."""
+    rounding margins."""
     return math.sqrt(2.0 * max(gap, 0.0) / alpha)
 
 
@@ -281,7 +285,12 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
          coordinates into the data (Remark 3);
       2. dual update theta = Theta(x) on the reduced problem (Sec. 4);
       3. gap of the reduced problem and safe radius (eqs. Dual_Gap,
-         GAP_Safe_sph);
+         GAP_Safe_sph); the gap is evaluated in its per-coordinate form
+         (``gap_per_coordinate``), which equals P - D but has no cancellation,
+         so the rule stays meaningful down to FP64's rounding floor (with
+         P - D, rounding noise of the size u * 1/2||y||^2 can replace the gap
+         once the true gap is that small, and a radius built on noise screens
+         free coordinates);
       4. stop if the gap is below eps_gap (the returned x is the one whose gap
          was just measured);
       5. otherwise (screening on) apply the safe rule on P, fix the screened
@@ -321,10 +330,10 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
         theta, eps, t_valid = dual_point(AP, yp, uP, xP, t)
         prim = primal(AP, yp, xP)
         dl = dual(AP, yp, lP, uP, theta)
-        gap = prim - dl
+        gap = gap_per_coordinate(AP, yp, lP, uP, xP, theta)
         rad = safe_radius(gap)
         passes += 1
-        hist.append({"iters": iters, "gap": gap, "radius": rad, "n_active": int(P.size),
+        hist.append({"iters": iters, "gap": gap, "gap_pd": prim - dl, "radius": rad, "n_active": int(P.size),
                      "eps": eps, "primal": prim, "t_valid": t_valid})
         if keep_theta:
             hist[-1]["theta"] = theta.copy()

@@ -33,7 +33,7 @@ def _oracle_gap(A64, P, x):
     residual, with margins) are two upper bounds of P(x) - P*, at two dual
     points a rounding apart: they agree closely but are not ordered."""
     assert np.all(np.isfinite(P.u))
-    return ob.gap_closed_form(A64, P.y, P.l, P.u, x, 0.0, None)
+    return ob.gap_per_coordinate(A64, P.y, P.l, P.u, x, P.y - A64 @ x)
 
 
 def test_c2_full_size_trajectory():

@@ -79,7 +79,7 @@ def test_remark1_linf_box_gives_l1_penalty():
 
 
 @pytest.mark.parametrize("kind", ["bvls", "nnls", "mixed"])
-def test_gap_closed_form_matches_definition(kind):
+def test_gap_per_coordinate_matches_definition(kind):
     rng = np.random.default_rng(3)
     for s in range(20):
         if kind == "bvls":
@@ -95,14 +95,39 @@ def test_gap_closed_form_matches_definition(kind):
         theta, eps, ok = ob.dual_point(A, y, u, x, t)
         assert ok
         g_def = ob.duality_gap(A, y, l, u, x, theta)
-        g_cf = ob.gap_closed_form(A, y, l, u, x, eps, t)
+        g_cf = ob.gap_per_coordinate(A, y, l, u, x, theta)
         assert g_cf >= 0.0
         assert abs(g_def - g_cf) <= 1e-11 * (1 + 0.5 * float(y @ y))
 
 
-def test_gap_closed_form_each_term_nonnegative_and_zero_at_optimum():
+def test_gap_per_coordinate_zero_at_optimum():
     rng = W.rng_for(98, 0)
     A = W.unit_columns(rng.standard_normal((40, 80)))
     l, u = -rng.random(80), rng.random(80)
     y, x, th, F = W.planted_bvls(A, l, u, 15, 0.05, rng)
-    assert ob.gap_closed_form(A, y, l, u, x, 0.0, np.zeros(40)) < 1e-13
+    assert ob.gap_per_coordinate(A, y, l, u, x, y - A @ x) < 1e-13
+
+
+def test_gap_per_coordinate_any_feasible_theta():
+    """The identity holds at any dual-feasible point, not only at the
+    residual-based ones: random theta (BVLS, F_D = R^m) and random translated
+    points (NNLS), compared with P - D in exact rational arithmetic."""
+    from fractions import Fraction as Fr
+    rng = np.random.default_rng(5)
+    for s in range(6):
+        P = W.tiny_bvls(s, 5, 7) if s % 2 == 0 else W.tiny_nnls(s, 5, 7)
+        A, y, l, u = P.A, P.y, P.l, P.u
+        x = _rand_box_point(rng, l, u)
+        th = rng.standard_normal(5)
+        if s % 2:
+            th, _ = ob.translate(A, th, -np.ones(5), ~np.isfinite(u))
+        c = [sum(Fr(A[i, j]) * Fr(th[i]) for i in range(5)) for j in range(7)]
+        r = [Fr(y[i]) - sum(Fr(A[i, j]) * Fr(x[j]) for j in range(7)) for i in range(5)]
+        Pv = sum(ri * ri for ri in r) / 2
+        Dv = sum(Fr(y[i]) ** 2 - (Fr(y[i]) - Fr(th[i])) ** 2 for i in range(5)) / 2
+        for j in range(7):
+            Dv -= Fr(l[j]) * min(c[j], Fr(0))
+            if np.isfinite(u[j]):
+                Dv -= Fr(u[j]) * max(c[j], Fr(0))
+        exact = float(Pv - Dv)
+        assert ob.gap_per_coordinate(A, y, l, u, x, th) == pytest.approx(exact, rel=1e-12, abs=1e-14)

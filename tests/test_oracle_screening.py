@@ -131,15 +131,3 @@ def test_planted_mistake_min_translation_is_caught(monkeypatch):
     z = rng.standard_normal(12)
     th, _ = ob.translate(A, z, -np.ones(12), np.ones(25, bool))
     assert np.max(A.T @ th) > 1e-6                         # Prop. 1 pin fails
-
-
-def test_planted_mistake_radius_without_factor_two_is_caught(monkeypatch):
-    monkeypatch.setattr(ob, "safe_radius", lambda gap, alpha=1.0: np.sqrt(max(gap, 0) / alpha) * 0.2)
-    found = False
-    for seed in range(3):
-        A, y, l, u, xs, ths = _planted(seed, nf=40, scale=0.5)
-        res = ob.solve(A, y, l, u, eps_gap=1e-10, max_iter=50000, keep_theta=True)
-        for h in res.history:
-            if np.linalg.norm(h["theta"] - ths) > h["radius"]:
-                found = True
-    assert found
