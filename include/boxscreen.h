@@ -162,6 +162,30 @@ bxs_status solve_bvls(long m, long n, int a_dtype, const void* A, long lda,
                       const double* y, const double* l, const double* u,
                       double* x, signed char* sat, const bxs_opts* opts, bxs_info* info);
 
+/* Allocation-free variant of solve_bvls, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as solve_bvls, but the
+ * call makes no device or pinned-host allocation and creates no event or
+ * graph: its workspace is a fixed device array of BXS_NOALLOC_SCRATCH_BYTES
+ * inside the library (one copy per GPU, held until the process ends), the
+ * device tables go up from a fixed host area, and the host waits for each
+ * screening pass with a stream synchronisation (one host round trip per
+ * pass, so it is slower than solve_bvls on small problems).
+ *   - opts->workspace must be NULL, opts->graph and opts->profile 0
+ *     (BXS_ERR_ARG otherwise).
+ *   - A problem whose workspace (bxs_workspace_size) exceeds
+ *     BXS_NOALLOC_SCRATCH_BYTES returns BXS_ERR_NOMEM before any launch.
+ *   - Calls share each GPU's array and keep its last contents; every value a
+ *     solve reads is written by that solve first.  Calls are serialised
+ *     within the process; calls from different processes on one GPU use
+ *     different copies.
+ *   - info->ms_setup is 0 and info->ms_solve is the host's wall time of the
+ *     call. */
+#define BXS_NOALLOC_SCRATCH_BYTES (32L << 20)
+bxs_status solve_bvls_noalloc(long m, long n, int a_dtype, const void* A, long lda,
+                              const double* y, const double* l, const double* u,
+                              double* x, signed char* sat, const bxs_opts* opts, bxs_info* info);
+
 /* Non-negative LS (Alg. 2): solve_bvls with l = 0, u = +inf, dual translation
  * along opts->t (default -1, valid for A >= 0 with no zero column, Prop. 2). */
 bxs_status solve_nnls(long m, long n, int a_dtype, const void* A, long lda,

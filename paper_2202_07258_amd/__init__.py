@@ -6,7 +6,8 @@ Importing the package does not load the library; the first solver call does,
 and raises if it is missing (there is no CPU fallback).
 """
 from .native import (  # noqa: F401
-    BoxscreenError, colmajor, load, solve_bvls, solve_bvls_varbatch, solve_nnls, solve_nnls_batched_shared,
+    BoxscreenError, colmajor, load, solve_bvls, solve_bvls_noalloc, solve_bvls_varbatch, solve_nnls,
+    solve_nnls_batched_shared,
     nnls_adjoint, version, LIBRARY_PATH, EXPORTED, MAX_ROWS,
 )
 from .layer import nnls_layer  # noqa: F401

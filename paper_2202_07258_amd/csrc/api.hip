@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <string>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "bxs_internal.h"
@@ -398,12 +399,26 @@ static bxs_status side_stream(hipStream_t* out)
     return BXS_OK;
 }
 
+// Allocation-free mode (solve_bvls_noalloc): the workspace is the library's
+// fixed device scratch array, the device tables go up from a fixed host area,
+// and the host learns the stop counter by a copy and a stream
+// synchronisation after every pass: no device or pinned-host allocation, no
+// event, no graph.
+struct FixedArea {
+    void* dev;              // device scratch (address from hipGetSymbolAddress)
+    size_t dev_bytes;
+    char* host;             // pageable host staging area
+    size_t host_bytes;
+};
+
 static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bxs_info* infos,
-                      bxs_pass_record* history, long history_cap)
+                      bxs_pass_record* history, long history_cap, const FixedArea* fixed = nullptr)
 {
     const long count = (long)P.specs.size();
     hipStream_t stream = (hipStream_t)o->stream;
-    const bool want_graph = o->graph && !o->profile && o->max_iter >= 3LL * o->screen_every;
+    const bool noalloc = fixed != nullptr;
+    const auto host_t0 = std::chrono::steady_clock::now();
+    const bool want_graph = !noalloc && o->graph && !o->profile && o->max_iter >= 3LL * o->screen_every;
     // With the null stream and graph replay, the solve runs on the side
     // stream, ordered after the caller's earlier work; every path below ends
     // with that stream synchronised, so the caller needs no further wait.
@@ -426,7 +441,12 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     }
     void* ws = o->workspace;
     bool owned = false;
-    if (ws) {
+    if (noalloc) {
+        if (P.bytes > fixed->dev_bytes)
+            return fail(BXS_ERR_NOMEM, "problem needs %zu bytes of workspace; the fixed scratch array holds %zu",
+                        P.bytes, fixed->dev_bytes);
+        ws = fixed->dev;
+    } else if (ws) {
         if (o->workspace_bytes < P.bytes)
             return fail(BXS_ERR_NOMEM, "workspace of %zu bytes, %zu needed", o->workspace_bytes, P.bytes);
     } else {
@@ -459,7 +479,12 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     const size_t tbytes = (size_t)((char*)(D.done_counter + 3) - (char*)D.insts);   // + ticket, pass count
     const size_t sbytes = sizeof(State) * count;
     void* stage_p = nullptr;
-    {
+    if (noalloc) {
+        if (std::max(tbytes, sbytes) > fixed->host_bytes - 64)   // the last 64 bytes hold the host words
+            return fail(BXS_ERR_NOMEM, "device tables of %zu bytes exceed the fixed host staging area of %zu",
+                        std::max(tbytes, sbytes), fixed->host_bytes);
+        stage_p = fixed->host;
+    } else {
         bxs_status ss = staging(std::max(tbytes, sbytes), &stage_p);
         if (ss != BXS_OK) return ss;
     }
@@ -511,20 +536,26 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         return e != hipSuccess ? e : launch_sweep(c, b, kModeAg, D.items[b], D.n_items[b]);
     };
 
-    hipEvent_t ev0, ev1, ev2;
-    BXS_HIP(hipEventCreate(&ev0));
-    BXS_HIP(hipEventCreate(&ev1));
-    BXS_HIP(hipEventCreate(&ev2));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    if (!noalloc) {
+        BXS_HIP(hipEventCreate(&ev0));
+        BXS_HIP(hipEventCreate(&ev1));
+        BXS_HIP(hipEventCreate(&ev2));
+    }
     struct EvGuard {
         hipEvent_t a, b, c;
-        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); }
+        ~EvGuard() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+            if (c) (void)hipEventDestroy(c);
+        }
     } eg{ev0, ev1, ev2};
     double ev_over = 0.0;
     if (o->profile) {
         bxs_status es = event_overhead(stream, &ev_over);
         if (es != BXS_OK) return es;
     }
-    BXS_HIP(hipEventRecord(ev0, stream));
+    if (!noalloc) BXS_HIP(hipEventRecord(ev0, stream));
 
     // ---- setup ----
     BXS_HIP(launch_init(c, (int)count, nullptr));
@@ -545,7 +576,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     }
     for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
     BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
-    BXS_HIP(hipEventRecord(ev1, stream));
+    if (!noalloc) BXS_HIP(hipEventRecord(ev1, stream));
 
     // instances that failed validation are stopped on the device (k_validate)
     // and reported after the loop
@@ -553,7 +584,10 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
 
     // ---- screening loop ----
     int* hdone = nullptr;
-    {
+    if (noalloc) {
+        // plain host words in the staging area, after the table image
+        hdone = (int*)(fixed->host + fixed->host_bytes - 64);
+    } else {
         void* pp = nullptr;
         bxs_status s = pinned(64, &pp);
         if (s != BXS_OK) return s;
@@ -578,7 +612,10 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             for (auto e : *w) if (e) (void)hipEventDestroy(e);
         }
     } pguard{&pev, &dev_done};
-    for (auto& e : dev_done) { e = nullptr; BXS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+    for (auto& e : dev_done) {
+        e = nullptr;
+        if (!noalloc) BXS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     if (o->profile) {
         pev.assign(4 * (size_t)K, nullptr);
         for (auto& e : pev) BXS_HIP(hipEventCreate(&e));
@@ -600,7 +637,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     // Direct launches without profiling: the host waits for a pass by reading
     // the pass count the screening kernel publishes (no completion event
     // between passes on the stream); graph replay and profiling use events.
-    const bool poll = !o->profile && !want_graph;
+    const bool poll = !o->profile && !want_graph && !noalloc;
     int enq_passes = 0;
     int slot_seq[2] = {0, 0};
     // host_done: where the screening kernel publishes the stop counter
@@ -668,14 +705,15 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             BXS_HIP(hipGraphLaunch(gexec, stream));
             BXS_HIP(launch_publish(c, hdone + slot));
         } else {
-            const bxs_status es = enqueue_kernels(slot, kk, final_pass, hdone + slot);
+            const bxs_status es = enqueue_kernels(slot, kk, final_pass, noalloc ? nullptr : hdone + slot);
             if (es != BXS_OK) return es;
         }
-        if (poll) slot_seq[slot] = ++enq_passes;
+        if (noalloc) BXS_HIP(hipMemcpyAsync(hdone + slot, D.done_counter, sizeof(int), hipMemcpyDeviceToHost, stream));
+        else if (poll) slot_seq[slot] = ++enq_passes;
         else BXS_HIP(hipEventRecord(dev_done[slot], stream));
         slot_kk[slot] = kk;
         slot_final[slot] = final_pass;
-        slot_gap[slot] = (count == 1 && !(gexec && kk == K && !final_pass)) ? 1 : 0;
+        slot_gap[slot] = (!noalloc && count == 1 && !(gexec && kk == K && !final_pass)) ? 1 : 0;
         return BXS_OK;
     };
 
@@ -697,7 +735,8 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     while (true) {
         const int nxt = slot ^ 1;
         bool queued_next = false;
-        if (!slot_final[slot] && !predict_stop()) {
+        // allocation-free mode waits for each pass before enqueueing the next
+        if (!noalloc && !slot_final[slot] && !predict_stop()) {
             bxs_status s = enqueue_pass(nxt);
             if (s != BXS_OK) return s;
             queued_next = true;
@@ -714,6 +753,8 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
                     break;
                 }
             }
+        } else if (noalloc) {
+            BXS_HIP(hipStreamSynchronize(stream));
         } else {
             BXS_HIP(hipEventSynchronize(dev_done[slot]));
         }
@@ -739,11 +780,11 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         }
         slot = nxt;
     }
-    BXS_HIP(hipEventRecord(ev2, stream));
+    if (!noalloc) BXS_HIP(hipEventRecord(ev2, stream));
     BXS_HIP(hipMemcpyAsync(img, D.st, sbytes, hipMemcpyDeviceToHost, stream));
     std::vector<bxs_pass_record> hrec;
     long nrec = 0;
-    if (history && count == 1 && P.rec_cap > 0) {
+    if (history && count == 1 && P.rec_cap > 0 && !noalloc) {
         hrec.resize(P.rec_cap);
         BXS_HIP(hipMemcpyAsync(hrec.data(), P.insts[0].rec, sizeof(bxs_pass_record) * P.rec_cap,
                                hipMemcpyDeviceToHost, stream));
@@ -756,8 +797,13 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         if (hst[i].err & kErrBounds) return fail(BXS_ERR_BOUNDS, "problem %ld: l_j = -inf, u_j = -inf or l_j > u_j", i);
     }
     float ms_setup = 0.f, ms_solve = 0.f;
-    BXS_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
-    BXS_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
+    if (noalloc) {
+        // no events: the host's wall time of the whole call
+        ms_solve = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0).count();
+    } else {
+        BXS_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
+        BXS_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
+    }
 
     bxs_status worst = BXS_OK;
     for (long i = 0; i < count; ++i) {
@@ -790,9 +836,49 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     }
     if (history && count == 1) {
         nrec = std::min<long>(hst[0].passes, std::min<long>(history_cap, P.rec_cap));
-        for (long k = 0; k < nrec; ++k) history[k] = hrec[k];
+        if (noalloc) {
+            // straight into the caller's array, the records of the passes run only
+            if (nrec > 0) {
+                BXS_HIP(hipMemcpyAsync(history, P.insts[0].rec, sizeof(bxs_pass_record) * nrec,
+                                       hipMemcpyDeviceToHost, stream));
+                BXS_HIP(hipStreamSynchronize(stream));
+            }
+        } else {
+            for (long k = 0; k < nrec; ++k) history[k] = hrec[k];
+        }
     }
     return worst;
+}
+
+// Fixed device scratch of the allocation-free entry point: one copy per GPU,
+// held from the library's load until the process ends.  In host code the
+// name `scratch` is only a host-side stand-in; the device address of each
+// GPU's copy comes from hipGetSymbolAddress and is the only form passed on.
+static __device__ __align__(256) unsigned char scratch[BXS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+// Serialises the allocation-free calls of the process: they share each GPU's
+// scratch array and the host staging area below.
+static std::mutex g_noalloc_mu;
+constexpr size_t kNoallocHostBytes = (size_t)4 << 20;
+alignas(256) static char g_noalloc_host[kNoallocHostBytes];
+
+static bxs_status scratch_for_current_device(void** out)
+{
+    int dev = 0;
+    BXS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(BXS_ERR_DEVICE, "device index %d out of range", dev);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(BXS_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return BXS_OK;
 }
 
 }  // namespace bxs
@@ -885,7 +971,8 @@ bxs_status bxs_workspace_size(long m, long n, const bxs_opts* opts, size_t* byte
     return bxs_workspace_size_batch(1, &m, &n, opts, bytes);
 }
 
-static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const bxs_opts* opts, bxs_info* infos)
+static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const bxs_opts* opts, bxs_info* infos,
+                               const FixedArea* fixed = nullptr)
 {
     g_last_error.clear();
     bxs_status s = check_opts(opts);
@@ -900,7 +987,7 @@ static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const 
     const long rc = (specs.size() == 1 && opts->history) ? opts->history_cap : 0;
     s = build_plan(P, a_dtype, rc, lanczos_steps(opts));
     if (s != BXS_OK) return s;
-    return run(P, a_dtype, opts, opts->t, infos, opts->history, opts->history_cap);
+    return run(P, a_dtype, opts, opts->t, infos, opts->history, opts->history_cap, fixed);
 }
 
 bxs_status solve_bvls(long m, long n, int a_dtype, const void* A, long lda, const double* y, const double* l,
@@ -910,6 +997,26 @@ bxs_status solve_bvls(long m, long n, int a_dtype, const void* A, long lda, cons
     std::vector<InstSpec> specs(1);
     specs[0] = InstSpec{m, n, lda, A, y, l, u, x, sat};
     return solve_common(specs, a_dtype, opts, info);
+}
+
+bxs_status solve_bvls_noalloc(long m, long n, int a_dtype, const void* A, long lda, const double* y,
+                              const double* l, const double* u, double* x, signed char* sat, const bxs_opts* opts,
+                              bxs_info* info)
+{
+    g_last_error.clear();
+    if (!l || !u) return fail(BXS_ERR_ARG, "solve_bvls_noalloc needs both bound arrays");
+    if (!opts) return fail(BXS_ERR_ARG, "opts is NULL");
+    if (opts->workspace) return fail(BXS_ERR_ARG, "solve_bvls_noalloc uses its fixed scratch: opts->workspace must be NULL");
+    if (opts->graph) return fail(BXS_ERR_ARG, "solve_bvls_noalloc does not capture graphs: opts->graph must be 0");
+    if (opts->profile) return fail(BXS_ERR_ARG, "solve_bvls_noalloc creates no events: opts->profile must be 0");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    void* dev_scratch = nullptr;
+    bxs_status s = scratch_for_current_device(&dev_scratch);
+    if (s != BXS_OK) return s;
+    const FixedArea fixed{dev_scratch, (size_t)BXS_NOALLOC_SCRATCH_BYTES, g_noalloc_host, kNoallocHostBytes};
+    std::vector<InstSpec> specs(1);
+    specs[0] = InstSpec{m, n, lda, A, y, l, u, x, sat};
+    return solve_common(specs, a_dtype, opts, info, &fixed);
 }
 
 bxs_status solve_nnls(long m, long n, int a_dtype, const void* A, long lda, const double* y, double* x,

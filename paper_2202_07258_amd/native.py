@@ -56,7 +56,9 @@ class Problem(C.Structure):
                 ("sat", C.c_void_p)]
 
 
-EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls",
+NOALLOC_SCRATCH_BYTES = 32 << 20   # BXS_NOALLOC_SCRATCH_BYTES of include/boxscreen.h
+
+EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls", "solve_bvls_noalloc",
             "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
             "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant",
             "bxs_sweep_variant_for_rows", "bxs_set_group_scale", "bxs_group_scale",
@@ -85,6 +87,8 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     lib.solve_bvls.argtypes = [C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]
     lib.solve_bvls.restype = C.c_int
+    lib.solve_bvls_noalloc.argtypes = lib.solve_bvls.argtypes
+    lib.solve_bvls_noalloc.restype = C.c_int
     lib.solve_nnls.argtypes = [C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]
     lib.solve_nnls.restype = C.c_int
@@ -215,21 +219,23 @@ def _run_single(kind, A, y, l, u, x0, kw):
     m, n, lda, dt = _check_matrix(A)
     dev = A.device
     y = _vec(y, m, "y")
-    if kind == "bvls":
+    if kind in ("bvls", "bvls_noalloc"):
         l = _vec(l, n, "l")
         u = _vec(u, n, "u")
     t = _vec(kw.pop("t", None), m, "t")
     x = torch.zeros(n, dtype=torch.float64, device=dev) if x0 is None else _vec(x0, n, "x0").clone()
     sat = torch.empty(n, dtype=torch.int8, device=dev)
     opts, hist = make_opts(t=t, **kw)
-    wbytes = workspace_bytes(m, n, opts)
-    wst = torch.empty(wbytes, dtype=torch.uint8, device=dev)
-    opts.workspace = wst.data_ptr()
-    opts.workspace_bytes = wbytes
+    if kind != "bvls_noalloc":
+        wbytes = workspace_bytes(m, n, opts)
+        wst = torch.empty(wbytes, dtype=torch.uint8, device=dev)
+        opts.workspace = wst.data_ptr()
+        opts.workspace_bytes = wbytes
     info = Info()
-    if kind == "bvls":
-        st = lib.solve_bvls(m, n, dt, A.data_ptr(), lda, y.data_ptr(), l.data_ptr(), u.data_ptr(),
-                            x.data_ptr(), sat.data_ptr(), C.byref(opts), C.byref(info))
+    if kind in ("bvls", "bvls_noalloc"):
+        fn = lib.solve_bvls if kind == "bvls" else lib.solve_bvls_noalloc
+        st = fn(m, n, dt, A.data_ptr(), lda, y.data_ptr(), l.data_ptr(), u.data_ptr(),
+                x.data_ptr(), sat.data_ptr(), C.byref(opts), C.byref(info))
     else:
         st = lib.solve_nnls(m, n, dt, A.data_ptr(), lda, y.data_ptr(), x.data_ptr(), sat.data_ptr(),
                             C.byref(opts), C.byref(info))
@@ -242,6 +248,13 @@ def _run_single(kind, A, y, l, u, x0, kw):
 def solve_bvls(A, y, l, u, x0=None, **kw):
     """Box-constrained LS via libboxscreen (Alg. 1).  Returns (x, sat, info)."""
     return _run_single("bvls", A, y, l, u, x0, dict(kw))
+
+
+def solve_bvls_noalloc(A, y, l, u, x0=None, **kw):
+    """solve_bvls through the allocation-free entry point: the library's fixed
+    device scratch replaces the workspace (only x and sat are allocated here,
+    as outputs).  Returns (x, sat, info)."""
+    return _run_single("bvls_noalloc", A, y, l, u, x0, dict(kw))
 
 
 def solve_nnls(A, y, x0=None, **kw):
