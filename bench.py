@@ -65,7 +65,7 @@ def time_solves(dev_inputs, steps, warmup, **kw):
     return dt, infos, out
 
 
-def sweep_roofline(infos, m, elem_bytes):
+def sweep_roofline(infos, m, n, elem_bytes):
     """Algorithmic bytes of one fused PG sweep launch: every preserved column
     once (m * elem_bytes), its x read and write, l, u and index (36 B), plus
     the residual m-vector (8 m), with the preserved-set size averaged over
@@ -85,7 +85,9 @@ def sweep_roofline(infos, m, elem_bytes):
     # time around an empty kernel)
     overhead = max(i.get("event_overhead_ms", 0.0) for i in infos) * 1e-3
     achieved = per_launch / avg_s / 1e9
-    traffic = measured_traffic(sweep_kernel_name(m), m)
+    # the counter summary was taken on an unscreened sweep over all n columns:
+    # it describes only launches that still read every column
+    traffic = measured_traffic(sweep_kernel_name(m), m) if col_iters == iters * n else None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": sweep_kernel_name(m),
@@ -230,7 +232,7 @@ def main():
                                         screen_every=10)
     value = args.steps / dt
     dtp, infos, _ = time_solves(dev, args.steps, 0, screening=True, eps_gap=1e-6, screen_every=10, profile=True)
-    roof = sweep_roofline(infos, m, 4)
+    roof = sweep_roofline(infos, m, n, 4)
     if roof:
         roof["profiled_ms_per_step"] = round(1e3 * dtp / args.steps, 3)
     xg = x.cpu().numpy()
@@ -271,7 +273,7 @@ def main():
                              "iters": iq["iters"], "n_screened": iq["n_lower"] + iq["n_upper"],
                              "gap": iq["gap"],
                              "max_abs_err_vs_planted_optimum": float(np.max(np.abs(xq.cpu().numpy() - Q.x_true)))},
-                "roofline_screened": sweep_roofline(infs, Q.m, 4)}
+                "roofline_screened": sweep_roofline(infs, Q.m, Q.n, 4)}
         if not args.no_unscreened:
             dtu, _, (_, _, iu) = time_solves(devq, args.steps, args.warmup, screening=False, eps_gap=1e-6,
                                              screen_every=10)

@@ -147,3 +147,56 @@ def save(table: dict, path: str) -> None:
 def load(path: str) -> dict:
     with open(path) as f:
         return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Persistent table, keyed by what the timings depend on
+# --------------------------------------------------------------------------
+def cache_key(device: str = "cuda:0", batch: bool = False) -> str:
+    """GPU architecture, HIP runtime, library version and tuning setting:
+    a table tuned under one key is reused only under the same key."""
+    props = torch.cuda.get_device_properties(torch.device(device))
+    arch = getattr(props, "gcnArchName", props.name)
+    return "|".join([arch, f"hip {torch.version.hip}", native.version(), "batch" if batch else "single"])
+
+
+def default_cache_path() -> str:
+    import os
+    return os.environ.get("BOXSCREEN_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "boxscreen", "autotune.json"))
+
+
+def tuned(device: str = "cuda:0", classes=None, batch: bool = False, path: str | None = None, log=None,
+          **tune_kw) -> dict:
+    """Install tuned shapes and spreads for `classes`, reusing the rows of
+    the persistent table stored under this device's key and tuning (then
+    storing) only the classes it lacks.  Returns {"classes", "seconds",
+    "key", "cached": [classes reused], "tuned": [classes tuned now]}."""
+    import os
+    path = path or default_cache_path()
+    key = cache_key(device, batch)
+    store = {}
+    try:
+        store = load(path)
+    except (OSError, ValueError):
+        store = {}
+    rows = {int(c): r for c, r in store.get(key, {}).items()}
+    want = list(range(9)) if classes is None else sorted(set(int(c) for c in classes))
+    missing = [c for c in want if c not in rows]
+    t0 = time.perf_counter()
+    if missing:
+        fresh = tune(device=device, classes=missing, batch=batch, log=log, **tune_kw)
+        rows.update({int(c): r for c, r in fresh["classes"].items()})
+        store[key] = {str(c): r for c, r in sorted(rows.items())}
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + ".tmp"
+            save(store, tmp)
+            os.replace(tmp, path)
+        except OSError:
+            pass                                  # read-only home: the table lives for this process
+    table = {"classes": {c: rows[c] for c in want}}
+    apply_table(table)
+    table.update({"seconds": round(time.perf_counter() - t0, 3), "key": key,
+                  "cached": [c for c in want if c not in missing], "tuned": missing})
+    return table

@@ -145,8 +145,10 @@ constexpr double kUnit = 1.1102230246251565e-16;
 // Depth of the summation tree of one column dot product in a sweep: R <= 16
 // sequential FMAs per thread, a 6-level wave butterfly, and at most 16
 // cross-wave additions.  The rounding error of every correlation a_j^T r is
-// therefore at most gamma(kDotDepth) * sum_i |a_ij r_i|.
+// therefore at most gamma(kDotDepth) * sum_i |a_ij r_i|.  Every sweep shape
+// (fused and two-pass forms alike) is checked against it below.
 constexpr double kDotDepth = 64.0;
+constexpr int dot_depth(int tpc, int rows) { return rows + 6 + tpc / 64; }
 
 // Column-sweep kernel variants: TPC threads share one column, NG column
 // groups per workgroup, R rows per thread (capacity TPC * R rows), CBI
@@ -196,6 +198,16 @@ constexpr VariantSpec kVariants[kNumVariants] = {
     BXS_SWEEP_VARIANTS(BXS_VS)
 #undef BXS_VS
 };
+
+// The rounding margin of the screening test assumes every correlation sum is
+// at most kDotDepth deep: a new sweep shape must stay within it.
+constexpr bool variants_within_dot_depth()
+{
+    for (int v = 0; v < kNumVariants; ++v)
+        if (dot_depth(kVariants[v].tpc, kVariants[v].rows) > (int)kDotDepth) return false;
+    return true;
+}
+static_assert(variants_within_dot_depth(), "a sweep variant's dot products are deeper than kDotDepth");
 
 // Translation units the 16-byte-load sweep variants are split over.
 constexpr int kSweepParts = 3;

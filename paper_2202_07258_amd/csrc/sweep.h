@@ -50,6 +50,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     constexpr int NW = TPC / 64;
     static_assert(R % V == 0, "rows per thread must be a multiple of the vector width");
     static_assert(TPC % 64 == 0, "a column group is whole waves");
+    static_assert(dot_depth(TPC, R) <= (int)kDotDepth, "correlation sums deeper than the screening margin assumes");
 
     // a single instance's items are {0, blockIdx.x}: no table load on the
     // critical path of the launch

@@ -85,3 +85,21 @@ def test_layer_gradient_finite_differences():
         E = np.zeros_like(A); E[i, j] = h
         fd = (L(_exact(A + E, y)) - L(_exact(A - E, y))) / (2 * h)
         assert fd == pytest.approx(gA[i, j], rel=1e-4, abs=1e-6)
+
+
+def test_layer_warns_when_the_forward_did_not_converge():
+    """A forward solve stopped by max_iter gives no exact gradient: backward
+    warns by default and raises on request."""
+    import paper_2202_07258_amd as bx
+    from paper_2202_07258_amd.layer import InexactGradientWarning
+    rng = np.random.default_rng(4)
+    A = np.abs(rng.standard_normal((40, 90)))
+    Y = rng.random((40, 3))
+    At = torch.tensor(A, device="cuda", requires_grad=True)
+    Yt = torch.tensor(Y, device="cuda", requires_grad=True)
+    X = bx.nnls_layer(At, Yt, eps_gap=1e-12, max_iter=5, screen_every=5)
+    with pytest.warns(InexactGradientWarning, match="did not reach the gap tolerance"):
+        X.sum().backward()
+    X = bx.nnls_layer(At, Yt, eps_gap=1e-12, max_iter=5, screen_every=5, on_inexact="raise")
+    with pytest.raises(bx.BoxscreenError, match="not exact"):
+        X.sum().backward()

@@ -40,3 +40,25 @@ def test_autotune_installs_valid_shapes_and_keeps_parity():
         for c, v in before.items():
             N.set_sweep_variant(c, v)
             N.set_group_scale(c, scale_before[c])
+
+
+def test_tuning_table_is_stored_and_reused(tmp_path):
+    """The persistent table: a class tuned once under this GPU's key (arch,
+    HIP runtime, library version, setting) is reused by the next call without
+    timing anything, and re-applied."""
+    import paper_2202_07258_amd as bx
+    from paper_2202_07258_amd import native as N
+    path = str(tmp_path / "tune.json")
+    before = (N.variant_for_rows(128), N.group_scale(1))
+    try:
+        t1 = bx.autotune.tuned(classes=[1], path=path, iters=10, reps=1)
+        assert t1["tuned"] == [1] and t1["cached"] == []
+        assert "gfx950" in t1["key"]
+        N.set_sweep_variant(1, -1)
+        t2 = bx.autotune.tuned(classes=[1], path=path)
+        assert t2["tuned"] == [] and t2["cached"] == [1] and t2["key"] == t1["key"]
+        assert N.variant_for_rows(128) == int(t1["classes"][1]["best"])
+        assert bx.autotune.load(path)[t1["key"]]["1"]["best"] == t1["classes"][1]["best"]
+    finally:
+        N.set_sweep_variant(1, before[0])
+        N.set_group_scale(1, before[1])

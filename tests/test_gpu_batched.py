@@ -147,6 +147,19 @@ def test_batched_full_c3_size_sampled():
     for b in rng.choice(8192, size=3, replace=False):
         P = W.Problem(A, Y[:, b].copy(), np.zeros(n), np.full(n, np.inf))
         res = ob.solve(A64, P.y, P.l, P.u, K=10, eps_gap=1e-6, max_iter=40, step=eta)
-        assert float(np.abs(X64[:, b] - res.x).max()) <= 1e-9 * max(1.0, float(np.abs(res.x).max()))
+        xs = max(1.0, float(np.abs(res.x).max()))
+        assert float(np.abs(X64[:, b] - res.x).max()) <= 1e-9 * xs
         np.testing.assert_array_equal(S64[:, b], res.sat)
         assert abs(inf64[b]["gap"] - res.gap) <= 1e-6 * res.gap + 1e-11
+        # the BF16x3 column against the oracle directly: same iterate to the
+        # engine's 2^-16-level splitting error, same screened set, and the
+        # oracle's own gap at that iterate (reduced problem, t = -1) lies
+        # below the GPU's certified gap
+        assert float(np.abs(X3[:, b] - res.x).max()) <= 1e-6 * xs
+        np.testing.assert_array_equal(S3[:, b], res.sat)
+        keep = S3[:, b] == 0
+        theta, _, ok = ob.dual_point(A64[:, keep], P.y, np.full(keep.sum(), np.inf), X3[keep, b], -np.ones(m))
+        assert ok
+        g_ora = ob.duality_gap(A64[:, keep], P.y, np.zeros(keep.sum()), np.full(keep.sum(), np.inf),
+                               X3[keep, b], theta)
+        assert g_ora <= inf3[b]["gap"] * (1 + 1e-9)

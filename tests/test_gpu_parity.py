@@ -136,6 +136,18 @@ def test_cd_parity(m, n):
     xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, **kw)
 
 
+@pytest.mark.parametrize("m,n", [(700, 1500), (2000, 1300), (4000, 900), (6000, 800), (9000, 700)])
+def test_cd_parity_multiwave(m, n):
+    """CD buckets whose workgroup spans several waves (m > 512: 256, 512 and
+    1024 threads), where each dot product adds the per-wave sums through LDS.
+    Tall shapes keep |F| = 0.4 min(m, n) free coordinates."""
+    print(f"\n[cd bvls multi-wave] m={m} n={n}", flush=True)
+    P = planted(23, m, n, nf_frac=0.4 * min(m, n) / m)
+    kw = dict(solver="cd", screen_every=1, eps_gap=1e-10, max_iter=2000)
+    xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, **kw)
+    assert res.status == "ok" and np.count_nonzero(res.sat) > 0
+
+
 def test_cd_nnls_parity():
     P = W.c1_companion(2, 150, 400)
     kw = dict(solver="cd", screen_every=1, eps_gap=1e-9, max_iter=3000)
@@ -286,6 +298,52 @@ def test_varbatch_parity():
     for P, x, s, info in zip(probs, xs, sats, infos):
         parity_vs_oracle(P, x.cpu().numpy(), s.cpu().numpy(), info, **kw)
     assert status == "ok"
+    # the same batch with every regular pass replayed from one captured graph:
+    # bit-identical results, twice, with unrelated eager work in between
+    for _ in range(2):
+        xg, sg, ig, stg = bx.solve_bvls_varbatch(dev, graph=True, **kw)
+        torch.cuda.synchronize()
+        assert stg == status
+        for a, b, c, d, i1, i2 in zip(xs, xg, sats, sg, infos, ig):
+            assert torch.equal(a, b) and torch.equal(c, d)
+            assert (i1["iters"], i1["passes"], i1["gap"]) == (i2["iters"], i2["passes"], i2["gap"])
+        run_gpu(planted(17, 100, 300), "bvls", eps_gap=1e-8, max_iter=500)
+
+
+def _padded_colmajor(A, device="cuda"):
+    """Column-major device copy with the leading dimension rounded up to 4
+    elements (16-byte aligned columns), as the uneven-batch benchmark lays
+    its matrices out."""
+    m, n = A.shape
+    lda = (m + 3) // 4 * 4
+    T = torch.zeros((n, lda), dtype=torch.float32, device=device)
+    T[:, :m] = torch.from_numpy(np.ascontiguousarray(np.asarray(A, dtype=np.float32).T)).to(device)
+    return T[:, :m].t()
+
+
+def test_c4_stratified_sample():
+    """Instances of the C4 uneven batch (2048 BVLS problems, m log-uniform in
+    [64, 2048], n/m log-uniform in [2, 8], Gaussian unit columns in FP32,
+    bounds [0, 1], 30% of x* saturated, y = A x*), 24 of them spread evenly
+    over the sizes m*n of the whole batch (smallest and largest included),
+    solved together in one call to gap 1e-6 with each instance's own step
+    from the library's Lanczos estimate, in the benchmark's layout (16-byte
+    aligned columns).  Each must follow the oracle run with that step."""
+    import paper_2202_07258_amd as bx
+    ms, ns = W.c4_sizes(0, 2048)
+    order = np.argsort(ms * ns, kind="stable")
+    pick = order[np.linspace(0, len(order) - 1, 24).round().astype(int)]
+    probs = [W.c4_instance(0, int(i), int(ms[i]), int(ns[i])) for i in pick]
+    dev = [{"A": _padded_colmajor(P.A), "y": torch.tensor(P.y, device="cuda"),
+            "l": torch.tensor(P.l, device="cuda"), "u": torch.tensor(P.u, device="cuda")} for P in probs]
+    kw = dict(screen_every=10, eps_gap=1e-6, max_iter=20000)
+    print(f"\n[c4 sample] {len(probs)} instances, m {ms[pick].min()}..{ms[pick].max()}", flush=True)
+    xs, sats, infos, status = bx.solve_bvls_varbatch(dev, **kw)
+    torch.cuda.synchronize()
+    assert status == "ok"
+    for P, x, s, info in zip(probs, xs, sats, infos):
+        assert info["step"] > 0
+        parity_vs_oracle(P, x.cpu().numpy(), s.cpu().numpy(), info, step=info["step"], **kw)
 
 
 @pytest.mark.parametrize("m,n", [(9000, 1200), (16384, 800)])
