@@ -170,7 +170,7 @@ def bench_c3(args, device):
         else:
             r["roofline"] = {"bound": "mfma", "achieved": r["useful_tflops"], "peak": FP64_PEAK_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(r["useful_tflops"] / FP64_PEAK_TFLOPS, 4),
-                             "traffic": None, "kernel": "rocBLAS DGEMM pair"}
+                             "traffic": None, "kernel": "k_dgemm<0,0>/<1,0> (R = Y - A X and G = A^T R, FP64 MFMA 16x16x4)"}
         res[prec] = r
         keep[prec] = X
         keep[prec + "_gaps"] = gaps

@@ -258,11 +258,16 @@ bxs_status bxs_workspace_size_batched(long m, long n, long B, const bxs_opts* op
  * so for an upstream gradient dL/dX:
  *     v_b = (A_F^T A_F)^{-1} (dL/dx_b)_F   (masked conjugate gradients, FP64)
  *     dL/dY = A V,   dL/dA = (Y - A X) V^T - (dL/dY) X^T   (summed over b)
+ *     dL/dl_b = (dL/dx_b - A^T dL/dy_b) on the coordinates at 0
  * Coordinates at 0 are treated as saturated (one-sided derivative where a
  * coordinate is weakly active).  opts->max_iter bounds the CG iterations and
  * opts->eps_gap is the CG tolerance relative to ||(dL/dx_b)_F||.
  *   A [lda*n] (a_dtype)  Y [ldy*B]  X [ldx*B] (forward solution)
  *   dX [ldg*B] in   dY [lddy*B] out   dA [ldda*n] out or NULL
+ *   dl [lddl*B] out or NULL: the gradient with respect to the lower bounds
+ *        l = 0 of each right-hand side, dL/dl_jb = (dL/dx_b)_j - a_j^T dL/dy_b
+ *        where x_jb sits on its bound and 0 on the free set (u = +inf has no
+ *        gradient).
  *   cg_iters host out or NULL.  Each right-hand side runs CG until its
  *   residual is below the tolerance, or until it breaks down: p^T A_F^T A_F p
  *   at or below the rounding level 2 gamma_{m+2} ||p||^2 ||A||_F^2 of its
@@ -275,7 +280,7 @@ bxs_status bxs_workspace_size_batched(long m, long n, long B, const bxs_opts* op
 bxs_status nnls_adjoint(long m, long n, long B, int a_dtype, const void* A, long lda,
                         const double* Y, long ldy, const double* X, long ldx,
                         const double* dX, long ldg, double* dY, long lddy, double* dA, long ldda,
-                        const bxs_opts* opts, long* cg_iters);
+                        double* dl, long lddl, const bxs_opts* opts, long* cg_iters);
 bxs_status bxs_workspace_size_adjoint(long m, long n, long B, size_t* bytes);
 
 /* Thread-local description of the last error (empty string if none). */

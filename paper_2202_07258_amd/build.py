@@ -66,7 +66,7 @@ def build_library(verbose: bool = False) -> str:
             objs = list(ex.map(compile_one, srcs))
         tmp = LIB + ".tmp"
         cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
-               "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+               "-Wl,-rpath,/opt/rocm/lib"]
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)

@@ -4,9 +4,10 @@
 // all right-hand sides at once, so that every matrix product is a GEMM.
 //
 // Two iteration engines share one FP64 certification pass:
-//  * FP64: R = Y - A X and G = A^T R as FP64 GEMMs (rocBLAS), the projected
-//    step as an elementwise kernel.  Same arithmetic as the FP64 oracle.
-//  * BF16x3: hand-written MFMA GEMMs on gfx950 (v_mfma_f32_16x16x16bf16_1k)
+//  * FP64: R = Y - A X and G = A^T R as FP64 MFMA GEMMs (dgemm.hip) on the
+//    right-hand sides still active, the projected step as an elementwise
+//    kernel.  Same arithmetic as the FP64 oracle up to summation order.
+//  * BF16x3: hand-written MFMA GEMMs on gfx950 (v_mfma_f32_16x16x32_bf16)
 //    with every FP32 operand split into bf16 hi + lo parts and the three
 //    leading partial products accumulated in FP32 (~2^-16 relative error
 //    instead of 2^-8 for plain bf16).  The GEMMs act on increments: each pass
@@ -22,7 +23,6 @@
 // rounding margins, the safe radius and the lower-saturation test of Alg. 2.
 // Screened coordinates are fixed at 0 (no fold is needed, Alg. 2).
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <math.h>
 #include <string.h>
@@ -508,8 +508,8 @@ __global__ void k_b_output(const double* __restrict__ X64, double* __restrict__ 
     }
 }
 
-// power iteration on A^T A with FP64 GEMVs is done by the host through
-// rocBLAS; this normalises v and records the Rayleigh quotient.
+// one power-iteration step on A^T A (FP64 GEMV pair of dgemm.hip) is
+// followed by this kernel: it normalises v and records the Rayleigh quotient.
 __global__ __launch_bounds__(256)
 void k_b_normalize(double* __restrict__ v, const double* __restrict__ av, int n, int m, double* __restrict__ lam)
 {
@@ -691,26 +691,40 @@ __global__ void k_b_iota(int* __restrict__ act, int B, int* __restrict__ nact)
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
-static thread_local rocblas_handle g_blas = nullptr;
+struct DgemmArgs {
+    const double* A;
+    long long lda;
+    const double* B;
+    long long ldb;
+    double* C;
+    long long ldc;
+    const double* Cin;
+    long long ldcin;
+    int M, N, K;
+    double alpha, beta;
+    const int* cols;
+    const int* ncols;
+};
+hipError_t launch_dgemm(int ta, int tb, const DgemmArgs& a, hipStream_t s);   // dgemm.hip
+size_t dgemv_partial_doubles(long m, long n);
+hipError_t launch_dgemv_normal(const double* A, long long lda, int m, int n, const double* v, double* w,
+                               double* partial, double* out, hipStream_t s);
 
-static bxs_status blas_handle(hipStream_t s, rocblas_handle* out)
+// C[M x N] = alpha op(A) op(B) + beta Cin (Cin = C when nullptr), FP64
+static DgemmArgs gemm_args(const double* A, long long lda, const double* B, long long ldb, double* C, long long ldc,
+                           long M, long N, long K, double alpha, double beta, const double* Cin = nullptr,
+                           long long ldcin = 0, const int* cols = nullptr, const int* ncols = nullptr)
 {
-    if (!g_blas) {
-        if (rocblas_create_handle(&g_blas) != rocblas_status_success) return set_error(BXS_ERR_DEVICE, "rocblas_create_handle failed");
-    }
-    if (rocblas_set_stream(g_blas, s) != rocblas_status_success) return set_error(BXS_ERR_DEVICE, "rocblas_set_stream failed");
-    *out = g_blas;
-    return BXS_OK;
+    DgemmArgs a;
+    a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc; a.Cin = Cin; a.ldcin = ldcin;
+    a.M = (int)M; a.N = (int)N; a.K = (int)K; a.alpha = alpha; a.beta = beta; a.cols = cols; a.ncols = ncols;
+    return a;
 }
 
 #define BXS_HIPB(call)                                                                           \
     do {                                                                                         \
         hipError_t e_ = (call);                                                                  \
         if (e_ != hipSuccess) return set_error(BXS_ERR_DEVICE, hipGetErrorString(e_));           \
-    } while (0)
-#define BXS_BLAS(call)                                                                           \
-    do {                                                                                         \
-        if ((call) != rocblas_status_success) return set_error(BXS_ERR_DEVICE, #call " failed"); \
     } while (0)
 
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
@@ -733,6 +747,7 @@ size_t batched_workspace_bytes(long m, long n, long B, int iter_precision)
         b += al(sizeof(float) * n * B);       // G32
     }
     b += al(sizeof(double) * (4 * (size_t)n + m + 16));   // cn, w, power vectors, scalars
+    b += al(sizeof(double) * dgemv_partial_doubles(m, n));  // power-iteration partial products
     b += al(sizeof(BState) * B);
     b += al(sizeof(int) * (B + 16));
     return b + 1024;
@@ -783,6 +798,7 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     double* pv = sc + 2 * n;         // n
     double* pav = sc + 3 * n;        // m (A v)
     double* scal = sc + 3 * n + m;   // [0] tnorm, [1] lambda
+    double* gv_part = (double*)take(sizeof(double) * dgemv_partial_doubles(m, n));
     BState* st = (BState*)take(sizeof(BState) * B);
     int* ints = (int*)take(sizeof(int) * (B + 16));
     int* act = ints;
@@ -791,10 +807,7 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     int* err = ints + B + 2;
     const long long lda32 = (a_dtype == BXS_F32) ? lda : m;   // A32 layout
 
-    rocblas_handle h;
-    bxs_status bs = blas_handle(s, &h);
-    if (bs != BXS_OK) return bs;
-
+    bxs_status bs = BXS_OK;
     hipEvent_t e0, e1, e2;
     BXS_HIPB(hipEventCreate(&e0));
     BXS_HIPB(hipEventCreate(&e1));
@@ -830,12 +843,11 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     double eta = o->step;
     double lam_h = 0.0;
     if (!(eta > 0.0)) {
-        const double one = 1.0, zero = 0.0;
         k_b_init_vec<<<16, 256, 0, s>>>(pv, (int)n);
         const int np = o->power_iters > 0 ? o->power_iters : 20;
         for (int k = 0; k < np; ++k) {
-            BXS_BLAS(rocblas_dgemv(h, rocblas_operation_none, (int)m, (int)n, &one, A64, (int)m, pv, 1, &zero, pav, 1));
-            BXS_BLAS(rocblas_dgemv(h, rocblas_operation_transpose, (int)m, (int)n, &one, A64, (int)m, pav, 1, &zero, pv, 1));
+            // pav = A v, v <- A^T pav, then normalise
+            BXS_HIPB(launch_dgemv_normal(A64, m, (int)m, (int)n, pv, pav, gv_part, pv, s));
             k_b_normalize<<<1, 256, 0, s>>>(pv, pav, (int)n, (int)m, scal + 1);
         }
         BXS_HIPB(hipMemcpyAsync(&lam_h, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -847,13 +859,12 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     if (!(eta > 0.0)) eta = lam_h > 0.0 ? 1.0 / (1.05 * lam_h) : 1.0;
     BXS_HIPB(hipEventRecord(e1, s));
 
-    const double one = 1.0, mone = -1.0, zero = 0.0;
+    // R = Y - A X and G = A^T R on the active right-hand sides (the list
+    // `act` and its device count; hnact bounds the count from the host)
+    int hnact = (int)B;
     auto residual_and_corr = [&]() -> bxs_status {
-        k_b_copy<<<grid, 256, 0, s>>>(Y64, R64, (long long)m * B);
-        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)m, (int)B, (int)n, &mone, A64,
-                               (int)m, X64, (int)n, &one, R64, (int)m));
-        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, (int)n, (int)B, (int)m, &one,
-                               A64, (int)m, R64, (int)m, &zero, G64, (int)n));
+        BXS_HIPB(launch_dgemm(0, 0, gemm_args(A64, m, X64, n, R64, m, m, hnact, n, -1.0, 1.0, Y64, m, act, nact), s));
+        BXS_HIPB(launch_dgemm(1, 0, gemm_args(A64, m, R64, m, G64, n, n, hnact, m, 1.0, 0.0, nullptr, 0, act, nact), s));
         return BXS_OK;
     };
 
@@ -870,7 +881,6 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     }
     int* hdone = nullptr;
     BXS_HIPB(hipHostMalloc((void**)&hdone, 2 * sizeof(int), hipHostMallocDefault));
-    int hnact = (int)B;
     struct HG { int* p; ~HG() { (void)hipHostFree(p); } } hg{hdone};
     const int K = o->screen_every;
     long long iters = 0;
@@ -1152,9 +1162,22 @@ size_t adjoint_workspace_bytes(long m, long n, long B)
     return b + 1024;
 }
 
+// dL/dl = dL/dx - A^T dL/dy on the coordinates at their bound 0, 0 on the free set
+__global__ void k_adj_bound_grad(const double* __restrict__ dX, long long ldg, const double* __restrict__ AtdY,
+                                 const signed char* __restrict__ F, int n, int B, double* __restrict__ dl,
+                                 long long lddl)
+{
+    const long long tot = (long long)n * B;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(k % n);
+        const long long b = k / n;
+        dl[j + b * lddl] = F[k] ? 0.0 : dX[j + b * ldg] - AtdY[k];
+    }
+}
+
 bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
                        const double* X, long ldx, const double* dX, long ldg, double* dY, long lddy, double* dA,
-                       long ldda, const bxs_opts* o, long* cg_iters)
+                       long ldda, double* dl, long lddl, const bxs_opts* o, long* cg_iters)
 {
     hipStream_t s = (hipStream_t)o->stream;
     const size_t need = adjoint_workspace_bytes(m, n, B);
@@ -1187,9 +1210,6 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     int* done = (int*)take(sizeof(int) * B);
     int* counters = (int*)take(sizeof(int) * 16);
 
-    rocblas_handle h;
-    bxs_status bs = blas_handle(s, &h);
-    if (bs != BXS_OK) return bs;
     const int grid = 2048;
     if (a_dtype == BXS_F32)
         k_b_convert_a<float><<<grid, 256, 0, s>>>((const float*)A, lda, (int)m, (int)n, A64, nullptr);
@@ -1202,7 +1222,6 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     k_adj_frob<<<1, 1024, 0, s>>>(A64, (long long)m * n, frob);
     BXS_HIPB(hipMemsetAsync(done, 0, sizeof(int) * B, s));
     BXS_HIPB(hipGetLastError());
-    const double one = 1.0, zero = 0.0, mone = -1.0;
     const double tol = o->eps_gap > 0.0 ? o->eps_gap : 1e-12;
     const long maxit = o->max_iter;
     int* hflag = nullptr;
@@ -1213,10 +1232,8 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     long it = 0;
     for (; it < maxit; ++it) {
         // S = mask(A^T (A P))
-        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)m, (int)B, (int)n, &one, A64,
-                               (int)m, P, (int)n, &zero, Q, (int)m));
-        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, (int)n, (int)B, (int)m, &one,
-                               A64, (int)m, Q, (int)m, &zero, S, (int)n));
+        BXS_HIPB(launch_dgemm(0, 0, gemm_args(A64, m, P, n, Q, m, m, B, n, 1.0, 0.0), s));
+        BXS_HIPB(launch_dgemm(1, 0, gemm_args(A64, m, Q, m, S, n, n, B, m, 1.0, 0.0), s));
         k_adj_mask<<<grid, 256, 0, s>>>(S, F, (long long)n * B);
         k_adj_dot2<<<(int)B, 256, 0, s>>>(P, S, (int)n, pq, pp);
         k_adj_step<<<grid, 256, 0, s>>>(S, F, rs, pq, pp, frob, (int)m, done, V, Rc, P, (int)n, (int)B);
@@ -1235,18 +1252,18 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     k_adj_zero_broken<<<grid, 256, 0, s>>>(V, done, (int)n, (int)B);
     BXS_HIPB(hipGetLastError());
     // dL/dY = A V
-    BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)m, (int)B, (int)n, &one, A64, (int)m,
-                           V, (int)n, &zero, Q, (int)m));
-    k_adj_copy2<<<grid, 256, 0, s>>>(Q, m, dY, lddy, (int)m, (int)B);
+    BXS_HIPB(launch_dgemm(0, 0, gemm_args(A64, m, V, n, dY, lddy, m, B, n, 1.0, 0.0), s));
     if (dA) {
         // R = Y - A X, then dL/dA = R V^T - (dL/dY) X^T
-        k_adj_copy2<<<grid, 256, 0, s>>>(Y, ldy, R, m, (int)m, (int)B);
-        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)m, (int)B, (int)n, &mone, A64,
-                               (int)m, Xc, (int)n, &one, R, (int)m));
-        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (int)m, (int)n, (int)B, &one, R,
-                               (int)m, V, (int)n, &zero, dA, (int)ldda));
-        BXS_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (int)m, (int)n, (int)B, &mone, Q,
-                               (int)m, Xc, (int)n, &one, dA, (int)ldda));
+        BXS_HIPB(launch_dgemm(0, 0, gemm_args(A64, m, Xc, n, R, m, m, B, n, -1.0, 1.0, Y, ldy), s));
+        BXS_HIPB(launch_dgemm(0, 1, gemm_args(R, m, V, n, dA, ldda, m, n, B, 1.0, 0.0), s));
+        BXS_HIPB(launch_dgemm(0, 1, gemm_args(dY, lddy, Xc, n, dA, ldda, m, n, B, -1.0, 1.0), s));
+    }
+    if (dl) {
+        // S = A^T dL/dY (S is free once the CG is done)
+        BXS_HIPB(launch_dgemm(1, 0, gemm_args(A64, m, dY, lddy, S, n, n, B, m, 1.0, 0.0), s));
+        k_adj_bound_grad<<<grid, 256, 0, s>>>(dX, ldg, S, F, (int)n, (int)B, dl, lddl);
+        BXS_HIPB(hipGetLastError());
     }
     BXS_HIPB(hipStreamSynchronize(s));
     if (cg_iters) *cg_iters = it;

@@ -120,7 +120,7 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     lib.bxs_workspace_size_batched.restype = C.c_int
     lib.nnls_adjoint.argtypes = [C.c_long, C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long, C.c_void_p, C.c_long,
                                  C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p,
-                                 C.c_long, C.POINTER(Opts), C.POINTER(C.c_long)]
+                                 C.c_long, C.c_void_p, C.c_long, C.POINTER(Opts), C.POINTER(C.c_long)]
     lib.nnls_adjoint.restype = C.c_int
     lib.bxs_workspace_size_adjoint.argtypes = [C.c_long, C.c_long, C.c_long, C.POINTER(C.c_size_t)]
     lib.bxs_workspace_size_adjoint.restype = C.c_int
@@ -392,11 +392,12 @@ def _colmajor64(T: torch.Tensor, rows: int, name: str) -> torch.Tensor:
     return T.to(torch.float64).t().contiguous().t()
 
 
-def nnls_adjoint(A, Y, X, dX, *, max_iter=10000, tol=1e-12, need_dA=True, stream=None):
+def nnls_adjoint(A, Y, X, dX, *, max_iter=10000, tol=1e-12, need_dA=True, need_dl=False, stream=None):
     """Implicit-differentiation adjoint of the batched NNLS map (C ABI
     nnls_adjoint).  A (m, n) column-major GPU tensor; Y (m, B), X (n, B),
     dX (n, B) GPU tensors.  Returns (dY (m, B) float64, dA (m, n) float64 or
-    None, cg_iterations, status)."""
+    None, cg_iterations, status), and with need_dl=True also dl (n, B)
+    float64, the gradient with respect to the lower bounds l = 0."""
     lib = load()
     m, n, lda, dt = _check_matrix(A)
     Y64 = _colmajor64(Y, m, "Y")
@@ -405,6 +406,7 @@ def nnls_adjoint(A, Y, X, dX, *, max_iter=10000, tol=1e-12, need_dA=True, stream
     G64 = _colmajor64(dX, n, "dX")
     dY = torch.empty((B, m), dtype=torch.float64, device=A.device).t()
     dA = torch.empty((n, m), dtype=torch.float64, device=A.device).t() if need_dA else None
+    dl = torch.empty((B, n), dtype=torch.float64, device=A.device).t() if need_dl else None
     o, _ = make_opts(max_iter=max_iter, eps_gap=tol, stream=stream)
     b = C.c_size_t(0)
     st = lib.bxs_workspace_size_adjoint(m, n, B, C.byref(b))
@@ -415,7 +417,10 @@ def nnls_adjoint(A, Y, X, dX, *, max_iter=10000, tol=1e-12, need_dA=True, stream
     o.workspace_bytes = int(b.value)
     it = C.c_long(0)
     st = lib.nnls_adjoint(m, n, B, dt, A.data_ptr(), lda, Y64.data_ptr(), m, X64.data_ptr(), n, G64.data_ptr(), n,
-                          dY.data_ptr(), m, dA.data_ptr() if dA is not None else None, m, C.byref(o), C.byref(it))
+                          dY.data_ptr(), m, dA.data_ptr() if dA is not None else None, m,
+                          dl.data_ptr() if dl is not None else None, n, C.byref(o), C.byref(it))
     if st not in (BXS_OK, BXS_MAXITER, BXS_SINGULAR):
         _raise(lib, st)
+    if need_dl:
+        return dY, dA, int(it.value), STATUS_NAMES[st], dl
     return dY, dA, int(it.value), STATUS_NAMES[st]

@@ -34,15 +34,19 @@ def test_adjoint_matches_oracle_formula(m, n, B):
     X = np.stack([_exact(A, Y[:, b]) for b in range(B)], axis=1)
     G = 2.0 * (X - T)
     dA = torch.tensor(A.T.copy(), device="cuda").t()
-    dY, dAgrad, iters, status = bx.nnls_adjoint(dA, torch.tensor(Y, device="cuda"), torch.tensor(X, device="cuda"),
-                                                torch.tensor(G, device="cuda"))
+    dY, dAgrad, iters, status, dl = bx.nnls_adjoint(dA, torch.tensor(Y, device="cuda"),
+                                                    torch.tensor(X, device="cuda"), torch.tensor(G, device="cuda"),
+                                                    need_dl=True)
     assert status == "ok"
     dY = dY.cpu().numpy()
     dAg = dAgrad.cpu().numpy()
+    dl = dl.cpu().numpy()
     dA_ref = np.zeros_like(A)
     for b in range(B):
-        gy, gA, _, _ = oa.solution_grad(A, Y[:, b], np.zeros(n), np.full(n, np.inf), X[:, b], G[:, b])
+        gy, gA, gl, _ = oa.solution_grad(A, Y[:, b], np.zeros(n), np.full(n, np.inf), X[:, b], G[:, b])
         np.testing.assert_allclose(dY[:, b], gy, rtol=1e-8, atol=1e-9 * (1 + np.abs(gy).max()))
+        np.testing.assert_allclose(dl[:, b], gl, rtol=1e-8, atol=1e-9 * (1 + np.abs(gl).max()))
+        assert np.count_nonzero(gl) > 0
         dA_ref += gA
     np.testing.assert_allclose(dAg, dA_ref, rtol=1e-8, atol=1e-9 * (1 + np.abs(dA_ref).max()))
 
