@@ -182,8 +182,11 @@ def main():
     ap.add_argument("--no-unscreened", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="bound the oracle baseline to this many iterations (0: full solve)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "table2"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "table2", "fig1", "sweep"],
                     help="c2 (default): the headline workload; the others are measured separately")
+    ap.add_argument("--sweep-m", type=int, default=8000)
+    ap.add_argument("--sweep-n", type=int, default=16000)
+    ap.add_argument("--sweep-iters", type=int, default=50)
     ap.add_argument("--c3-rhs", type=int, default=8192)
     ap.add_argument("--c3-iters", type=int, default=200)
     ap.add_argument("--c4-count", type=int, default=2048)

@@ -319,6 +319,144 @@ def bench_c5(args, device):
 
 
 # --------------------------------------------------------------------------
+def _fig1_point(A, y, P, b, device, reps):
+    n = P.n
+    l = torch.full((n,), -b, dtype=torch.float64, device=device)
+    u = torch.full((n,), b, dtype=torch.float64, device=device)
+    out = {"b": b}
+    for screening in (True, False):
+        kw = dict(screening=screening, screen_every=10, eps_gap=1e-6, max_iter=200000)
+        bx.solve_bvls(A, y, l, u, **dict(kw, max_iter=20))
+        _sync()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            x, sat, info = bx.solve_bvls(A, y, l, u, **kw)
+            _sync()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        xs = x.cpu().numpy()
+        rec = {"seconds": round(best, 5), "iters": info["iters"], "status": info["status_name"],
+               "gap": info["gap"], "n_screened": info["n_lower"] + info["n_upper"],
+               "ms_setup": round(info["ms_setup"], 3),
+               "mean_preserved_fraction": round(info["col_iters"] / max(info["iters"], 1) / n, 4),
+               # wall time per primal iteration, setup (column norms, Lanczos) excluded
+               "us_per_iter": round((1e6 * best - 1e3 * info["ms_setup"]) / max(info["iters"], 1), 2)}
+        if screening:
+            rec["saturation_ratio"] = round(float(np.mean(np.abs(np.abs(xs) - b) <= 1e-12 * b)), 4)
+        out["screened" if screening else "unscreened"] = rec
+    out["speedup"] = round(out["unscreened"]["seconds"] / out["screened"]["seconds"], 3)
+    out["speedup_per_iter"] = round(out["unscreened"]["us_per_iter"] / out["screened"]["us_per_iter"], 3)
+    return out
+
+
+def bench_fig1(args, device):
+    """Sec. 5.1, Fig. 1: speedup of screening against the saturation ratio,
+    PG on BVLS with a_ij ~ N(0,1), y ~ N(0,1) and the box b [-1, 1]; at the
+    paper's size (4000 x 2000, FP64) and at sizes where a sweep is
+    HBM-bound: C2's shape (4000 x 16000 FP32, 256 MB) and 8000 x 16000 FP32
+    (512 MB, twice the 256 MiB Infinity Cache)."""
+    sizes = [(4000, 2000, np.float64, [0.0005, 0.001, 0.002, 0.005, 0.01, 0.05]),
+             (4000, 16000, np.float32, [0.0005, 0.001, 0.002, 0.005, 0.01]),
+             (8000, 16000, np.float32, [0.0005, 0.001, 0.002, 0.005, 0.01])]
+    out = {"workload": "Fig. 1 law (Sec. 5.1): BVLS, a_ij ~ N(0,1), y ~ N(0,1), box b[-1,1]; PG K=10 to gap 1e-6; "
+                       "wall time per solve (best of 3), per-iteration times exclude setup",
+           "sizes": []}
+    for (m, n, dt, bs) in sizes:
+        P = W.fig1_bvls(0, m, n, 1.0, dtype=dt)
+        A = bx.colmajor(P.A, device=device)
+        y = torch.tensor(P.y, dtype=torch.float64, device=device)
+        pts = []
+        for b in bs:
+            pt = _fig1_point(A, y, P, b, device, reps=3)
+            log(f"[fig1] {m}x{n} {np.dtype(dt).name} b={b}: sat {pt['screened']['saturation_ratio']} "
+                f"speedup {pt['speedup']} (per iter {pt['speedup_per_iter']}), "
+                f"{pt['screened']['us_per_iter']} vs {pt['unscreened']['us_per_iter']} us/iter at preserved "
+                f"{pt['screened']['mean_preserved_fraction']}")
+            pts.append(pt)
+        entry = {"m": m, "n": n, "a_storage": np.dtype(dt).name, "points": pts}
+        # per-iteration time against the preserved fraction: t = a + c f (least squares over the points,
+        # screened and unscreened runs alike)
+        f = np.array([p["screened"]["mean_preserved_fraction"] for p in pts] + [1.0] * len(pts))
+        t = np.array([p["screened"]["us_per_iter"] for p in pts] + [p["unscreened"]["us_per_iter"] for p in pts])
+        c, a = np.polyfit(f, t, 1)
+        entry["per_iter_fit_us"] = {"fixed": round(float(a), 2), "per_unit_preserved_fraction": round(float(c), 2)}
+        if (m, n) == (8000, 16000):
+            # sweep roofline above the Infinity Cache size, unscreened
+            l = torch.full((n,), -0.01, dtype=torch.float64, device=device)
+            _, _, info = bx.solve_bvls(A, y, l, -l, screening=False, screen_every=10, eps_gap=0.0,
+                                       max_iter=200, profile=True)
+            _sync()
+            per_launch = n * (m * 4 + 36) + 8 * m
+            avg_s = info["sweep_ms"] * 1e-3 / max(info["sweep_launches"], 1)
+            ach = per_launch / avg_s / 1e9
+            entry["sweep_roofline_unscreened"] = {
+                "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK, 4), "algorithmic_bytes_per_launch": per_launch,
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": info["sweep_launches"],
+                "note": "A is 512 MB, twice the Infinity Cache: every sweep streams it from HBM"}
+        out["sizes"].append(entry)
+        del A
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        from oracle import boxls as ob
+        P = W.fig1_bvls(0, 4000, 2000, 0.002)
+        A64 = P.A64()
+        eta = 1.0 / (1.05 * ob.lipschitz(A64))
+        res = {}
+        for screening in (True, False):
+            t0 = time.perf_counter()
+            r = ob.solve(A64, P.y, P.l, P.u, K=10, eps_gap=1e-6, step=eta, screening=screening)
+            res[screening] = (time.perf_counter() - t0, r)
+        out["cpu_baseline"] = {"value": round(1.0 / res[True][0], 3), "unit": "solves/s", "cores": _cores(),
+                               "kind": "oracle",
+                               "sample": f"one screened oracle solve at 4000x2000 FP64, b=0.002 "
+                                         f"({res[True][1].iters} iterations)",
+                               "oracle_screened_s": round(res[True][0], 3),
+                               "oracle_unscreened_s": round(res[False][0], 3),
+                               "oracle_speedup": round(res[False][0] / res[True][0], 3)}
+    return out
+
+
+def bench_sweep(args, device):
+    """The fused PG sweep alone on a Fig. 1-law instance of any size (FP32
+    storage), unscreened, a fixed number of iterations: the command the
+    rocprofv3 traffic counters are read on for sizes above and below the
+    256 MiB Infinity Cache."""
+    m, n = args.sweep_m, args.sweep_n
+    P = W.fig1_bvls(0, m, n, 0.01, dtype=np.float32)
+    A = bx.colmajor(P.A, device=device)
+    y, l, u = (torch.tensor(v, dtype=torch.float64, device=device) for v in (P.y, P.l, P.u))
+    kw = dict(screening=False, screen_every=10, eps_gap=0.0, max_iter=args.sweep_iters, step=1e-6)
+    bx.solve_bvls(A, y, l, u, **dict(kw, max_iter=10))
+    _sync()
+    _, _, info = bx.solve_bvls(A, y, l, u, profile=True, **kw)
+    _sync()
+    per_launch = n * (m * 4 + 36) + 8 * m
+    avg_s = info["sweep_ms"] * 1e-3 / max(info["sweep_launches"], 1)
+    ach = per_launch / avg_s / 1e9
+    # reference: a plain device copy of A's size (read + write), event-timed
+    src = A.t().contiguous().view(-1)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    _sync()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    return {"workload": f"fused PG sweep, Fig. 1-law {m}x{n} FP32 ({4 * m * n / 2**20:.0f} MiB of A), "
+                        f"{args.sweep_iters} unscreened iterations",
+            "kernel": f"k_sweep variant {N.variant_for_rows(m)} for {m} rows",
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK, 4), "algorithmic_bytes_per_launch": per_launch,
+                         "avg_launch_us": round(avg_s * 1e6, 2), "launches": info["sweep_launches"],
+                         "empty_kernel_events_us": round(1e3 * info["event_overhead_ms"], 2)},
+            "device_copy_gbs_same_size": round(copy_gbs, 1)}
+
+
+# --------------------------------------------------------------------------
 def bench_table2(args, device):
     out = {"workload": "Paper Table 2 setup: BVLS m=1000 n=3000, |N(0,1)| entries, x-bar 5% U(0,1), "
                        "noise N(0,1), bounds [0,1]; PG K=10, gap 1e-6",
@@ -349,4 +487,5 @@ def bench_table2(args, device):
 
 
 def run(name, args, device):
-    return {"c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "table2": bench_table2}[name](args, device)
+    return {"c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "table2": bench_table2,
+            "fig1": bench_fig1, "sweep": bench_sweep}[name](args, device)

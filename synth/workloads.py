@@ -29,7 +29,7 @@ __all__ = [
     "c1_nnls", "c1_companion", "c2_bvls", "c2_planted",
     "c3_shared", "c4_sizes", "c4_instance", "c4_planted_instance", "c5_layer",
     "tiny_bvls", "tiny_nnls", "planted_bvls", "orthonormal_bvls",
-    "table1_nnls", "table2_bvls", "interior_direction",
+    "table1_nnls", "table2_bvls", "fig1_bvls", "interior_direction",
 ]
 
 
@@ -285,6 +285,18 @@ def table2_bvls(rep: int, m: int, n: int) -> Problem:
     x[s] = rng.random(k)
     y = A @ x + rng.standard_normal(m)
     return Problem(A, y, np.zeros(n), np.ones(n), x, False, {"name": "table2", "kind": "bvls"})
+
+
+def fig1_bvls(rep: int, m: int, n: int, b: float, dtype=np.float64) -> Problem:
+    """The saturation-ratio experiment of Sec. 5.1 (Fig. 1): a_ij ~ N(0,1)
+    (columns not normalised), y_i ~ N(0,1) drawn independently of A, box
+    b [-1, 1]; a smaller b saturates more coordinates of the optimum.  The
+    matrix and y depend on (rep, m, n) only, so every b shares them."""
+    rng = rng_for(31, rep, m, n)
+    A = _colmajor(_gaussian(rng, m, n), dtype)
+    y = rng.standard_normal(m)
+    return Problem(A, y, np.full(n, -float(b)), np.full(n, float(b)), None, False,
+                   {"name": f"fig1[b={b}]", "kind": "bvls"})
 
 
 # --------------------------------------------------------------------------
