@@ -283,6 +283,16 @@ def main():
             comp["unscreened"] = {"value": round(args.steps / dtu, 3),
                                   "ms_per_step": round(1e3 * dtu / args.steps, 3), "iters": iu["iters"]}
             comp["speedup_screened"] = round(dtu / dts, 3)
+        # the ceiling of the dual update (Sec. 5.1, Fig. 3): the same solve
+        # screened with the planted dual optimum in place of the dual update
+        ts = torch.tensor(Q.meta["theta"], dtype=torch.float64, device=device)
+        dto, _, (_, _, io) = time_solves(devq, 1, 1, screening=True, eps_gap=1e-6, screen_every=10, theta_star=ts)
+        comp["screened_oracle_dual_point"] = {"value": round(1 / dto, 3), "ms_per_step": round(1e3 * dto, 3),
+                                              "iters": io["iters"], "n_screened": io["n_lower"] + io["n_upper"],
+                                              "mean_preserved_fraction":
+                                                  round(io["col_iters"] / max(io["iters"], 1) / Q.n, 4)}
+        if "unscreened" in comp:
+            comp["speedup_oracle_dual_point"] = round(dtu / args.steps / dto, 3)
         result["companion"] = comp
         del devq
         torch.cuda.empty_cache()

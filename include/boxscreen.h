@@ -113,6 +113,16 @@ typedef struct {
                                 which measured faster on MI355X (ROCm 7.2) for every size
                                 tried, since the host stays a pass ahead of the device.
                                 Profile mode always launches directly.                         */
+    const double* theta_star;/* device m-vector or NULL.  Diagnostic of the dual update's
+                                headroom (Sec. 5.1, oracle dual point of Fig. 3): every screening
+                                pass of solve_bvls / solve_nnls / solve_bvls_varbatch uses this
+                                vector, a known dual optimum y - A x* (translated along t for
+                                u_j = +inf columns if rounding left some a_j^T theta_star > 0),
+                                in place of the point built from the residual; the gap, radius
+                                and test are computed from it with the same rounding margins.
+                                Screening stays safe for any dual-feasible vector; a vector that
+                                is not the optimum only weakens it.  Same vector for every
+                                problem of a batch.                                           */
 } bxs_opts;
 
 typedef struct {

@@ -122,7 +122,7 @@ static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap, int 
     p.items_cap = (int)std::max<long>(cap, 1);
     size_t b = 0;
     b += align_up(sizeof(double) * 3 * m, 256);                   // yp, r, r2
-    b += align_up(sizeof(double) * 7 * n, 256);                   // g, w, cn, cn2, fval, fdx, xs
+    b += align_up(sizeof(double) * 8 * n, 256);                   // g, w, cn, cn2, fval, fdx, xs, gs
     b += align_up(sizeof(int) * 2 * n, 256);                      // idx, fidx
     b += align_up(sizeof(double) * 2 * (size_t)p.items_cap * m, 256);  // part, part2
     b += align_up(sizeof(double) * kItemScalars * p.items_cap, 256);  // iscal
@@ -309,9 +309,9 @@ static void layout(Plan& P, char* base)
         I.yp = (double*)take(sizeof(double) * 3 * s.m);
         I.r = I.yp + s.m;
         I.r2 = I.yp + 2 * s.m;
-        double* nv = (double*)take(sizeof(double) * 7 * s.n);
+        double* nv = (double*)take(sizeof(double) * 8 * s.n);
         I.g = nv; I.w = nv + s.n; I.cn = nv + 2 * s.n; I.cn2 = nv + 3 * s.n;
-        I.fval = nv + 4 * s.n; I.fdx = nv + 5 * s.n; I.xs = nv + 6 * s.n;
+        I.fval = nv + 4 * s.n; I.fdx = nv + 5 * s.n; I.xs = nv + 6 * s.n; I.gs = nv + 7 * s.n;
         int* iv = (int*)take(sizeof(int) * 2 * s.n);
         I.idx = iv; I.fidx = iv + s.n;
         I.part = (double*)take(sizeof(double) * 2 * (size_t)z.items_cap * s.m);
@@ -459,7 +459,10 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     } guard{ws, owned, stream};
 
     layout(P, (char*)ws);
-    for (long i = 0; i < count; ++i) P.insts[i].t = t;
+    for (long i = 0; i < count; ++i) {
+        P.insts[i].t = t;
+        P.insts[i].ts = o->theta_star;
+    }
 
     // device tables
     DevTables D;

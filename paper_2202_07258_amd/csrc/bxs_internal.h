@@ -32,6 +32,7 @@ struct Inst {
     const double* l;        // [n] or nullptr (0)
     const double* u;        // [n] or nullptr (+inf)
     const double* t;        // [m] or nullptr (-1)
+    const double* ts;       // [m] known dual optimum used in place of the dual update, or nullptr
     double* x;              // [n] caller iterate (original index space)
     signed char* sat;       // [n]
     double* yp;             // [m] data with the screened part folded in (Remark 3)
@@ -40,6 +41,7 @@ struct Inst {
     double* xs;             // [n] iterate at the screening point (before that step)
     double* g;              // [n] correlations a_j^T r
     double* w;              // [n] a_j^T t
+    double* gs;             // [n] a_j^T ts (when ts is given)
     double* cn;             // [n] rigorous upper bound of ||a_j||_2
     double* cn2;            // [n] FP64 sum of squares of column j (CD curvature)
     int* idx;               // [n] preserved set, ascending original index
@@ -76,6 +78,7 @@ struct State {
     double lipschitz;       // Lanczos estimate of ||A||_2^2
     double gap, radius, eps, primal;
     double tnorm;           // upper bound of ||t||_2
+    double tsnorm;          // upper bound of ||ts||_2
     double ynorm;           // upper bound of ||y||_2
     double mass_screened;   // sum over screened j of |x_j| * cn_j
 };

@@ -131,6 +131,7 @@ void k_init(const Inst* __restrict__ insts, State* __restrict__ st)
         I.yp[k] = yv;
         I.r[k] = 0.0;
         if (I.t && !isfinite(I.t[k])) err |= kErrNonfinite;
+        if (I.ts && !isfinite(I.ts[k])) err |= kErrNonfinite;
     }
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < I.n; j += stride) {
         const double lj = lo_of(I.l, j), uj = up_of(I.u, j), xj = I.x[j];
@@ -203,11 +204,12 @@ void k_colstats(const Inst* __restrict__ insts, State* __restrict__ st, const It
     const double gm = gamma_k((double)(I.m / 64) + 8.0);
     int err = 0;
     const int m = I.m;
+    const double* __restrict__ ts = I.ts;
     for (int j = pos0 + wv; j < pos1; j += 4) {
         const TA* col = A + (long long)j * I.lda;
-        double s2[V], sw[V];
+        double s2[V], sw[V], ss[V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) { s2[e] = 0.0; sw[e] = 0.0; }
+        for (int e = 0; e < V; ++e) { s2[e] = 0.0; sw[e] = 0.0; ss[e] = 0.0; }
         for (int k0 = 0; k0 * 64 * V < m; k0 += U) {
             TA a[U][V];
             double tv[U][V];
@@ -231,16 +233,30 @@ void k_colstats(const Inst* __restrict__ insts, State* __restrict__ st, const It
                     s2[e] = fma(av, av, s2[e]);
                     sw[e] = fma(av, tv[u][e], sw[e]);
                 }
-        }
-        double s2l = 0.0, swl = 0.0;
+            if (ts) {
+                // correlations with the given dual optimum (diagnostic mode)
 #pragma unroll
-        for (int e = 0; e < V; ++e) { s2l += s2[e]; swl += sw[e]; }
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        const int row = ((k0 + u) * 64 + lane) * V + e;
+                        const bool ok = row < m;
+                        const double av = ok ? (double)a[u][e] : 0.0;
+                        ss[e] = fma(av, ok ? ts[row] : 0.0, ss[e]);
+                    }
+            }
+        }
+        double s2l = 0.0, swl = 0.0, ssl = 0.0;
+#pragma unroll
+        for (int e = 0; e < V; ++e) { s2l += s2[e]; swl += sw[e]; ssl += ss[e]; }
         const double s2t = wave_sum(s2l);
         const double swt = wave_sum(swl);
+        const double sst = ts ? wave_sum(ssl) : 0.0;
         if (lane == 0) {
             I.cn2[j] = s2t;
             I.cn[j] = sqrt(s2t * (1.0 + gm)) * (1.0 + 2.0 * kUnit);
             I.w[j] = swt;
+            if (ts) I.gs[j] = sst;
         }
     }
     if (err) atomicOr(&S.err, err);
@@ -257,11 +273,12 @@ void k_inst_scalars(const Inst* __restrict__ insts, State* __restrict__ st, int 
     const Inst& I = insts[blockIdx.x];
     State& S = st[blockIdx.x];
     const int m = I.m;
-    double sy = 0.0, stt = 0.0, su = 0.0;
+    double sy = 0.0, stt = 0.0, su = 0.0, sts = 0.0;
     for (int i = threadIdx.x; i < m; i += 256) {
         const double yv = I.y[i], tv = t_of(I.t, i);
         sy = fma(yv, yv, sy);
         stt = fma(tv, tv, stt);
+        if (I.ts) sts = fma(I.ts[i], I.ts[i], sts);
         if (do_pow) {
             // deterministic start: 1 +- 1/4 by a multiplicative hash of the row
             const unsigned h = (unsigned)i * 2654435761u;
@@ -273,6 +290,7 @@ void k_inst_scalars(const Inst* __restrict__ insts, State* __restrict__ st, int 
     sy = block_sum<256>(sy, sh);
     stt = block_sum<256>(stt, sh);
     su = block_sum<256>(su, sh);
+    sts = block_sum<256>(sts, sh);
     if (do_pow) {
         const double inv = 1.0 / sqrt(su);
         double* q0 = I.lz + 2 * I.lz_steps;
@@ -286,6 +304,7 @@ void k_inst_scalars(const Inst* __restrict__ insts, State* __restrict__ st, int 
         const double gm = gamma_k((double)m + 32.0);
         S.ynorm = sqrt(sy * (1.0 + gm)) * (1.0 + 2.0 * kUnit);
         S.tnorm = sqrt(stt * (1.0 + gm)) * (1.0 + 2.0 * kUnit);
+        S.tsnorm = sqrt(sts * (1.0 + gm)) * (1.0 + 2.0 * kUnit);
         if (!do_pow) {
             S.step = user_step;
             S.lipschitz = 0.0;
@@ -429,13 +448,28 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
     const double tnorm = S.tnorm;
     const double u1 = kUnit;
     const bool nnls_like = (I.u == nullptr);   // every u_j = +inf
+    // diagnostic mode: a given dual optimum ts replaces the residual as the
+    // point the dual update starts from (correlations gs_j = a_j^T ts from
+    // the setup), so the item partials of the sweep do not apply
+    const double* __restrict__ ts = I.ts;
+    const bool oracle_dual = ts != nullptr;
 
     // ||r||^2 and the per-item quantities written by the correlation sweep
     // (mass, interior flag of t, largest translation ratio, presence of
     // u = +inf columns, gap terms and largest screening score at eps = 0),
     // combined over the workgroup in one reduction
-    double a = 0.0;
-    for (int i = tid; i < m; i += NT) a = fma(I.r[i], I.r[i], a);
+    double a = 0.0, a2 = 0.0;
+    for (int i = tid; i < m; i += NT) {
+        const double ri = I.r[i];
+        a = fma(ri, ri, a);
+        if (oracle_dual) {
+            const double d = ri - ts[i];
+            a2 = fma(d, d, a2);
+        }
+    }
+    // ||r - ts|| bound (diagnostic mode only)
+    const double rts = oracle_dual
+        ? sqrt(block_sum<NT>(a2, sh) * (1.0 + gamma_k((double)(m / NT) + 24.0))) * (1.0 + 2.0 * u1) : 0.0;
     const int T = (nA + S.cb - 1) / S.cb;
     double red7[7] = {a, 0.0, 0.0, 1.0, 0.0, 0.0, -__builtin_inf()};   // rsq mass gap0 | tv | emax hasinf z0
     for (int t = tid; t < T; t += NT) {
@@ -488,6 +522,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
     // Per-chunk gather of the preserved columns' data: each thread takes E
     // consecutive positions and issues all of its loads before using them.
     struct Col { int j; double g, w, cn, x, l, u; };
+    const double* __restrict__ gsrc = oracle_dual ? I.gs : I.g;
     auto gather = [&](int base, Col (&c)[E], bool (&valid)[E]) {
         int jj[E];
 #pragma unroll
@@ -500,7 +535,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
         for (int e = 0; e < E; ++e) {
             const int j = jj[e];
             c[e].j = j;
-            c[e].g = valid[e] ? I.g[j] : 0.0;
+            c[e].g = valid[e] ? gsrc[j] : 0.0;
             c[e].w = valid[e] ? I.w[j] : 0.0;
             c[e].cn = valid[e] ? I.cn[j] : 0.0;
             c[e].x = valid[e] ? (ahead ? I.xs[j] : I.x[j]) : 0.0;
@@ -509,17 +544,40 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
         }
     };
 
-    const double tv = red7[3], emax = red7[4], mass = red7[1], hasinf = red7[5], gap0 = red7[2], z0 = red7[6];
+    double tv = red7[3], emax = red7[4];
+    const double mass = red7[1], hasinf = red7[5], gap0 = red7[2], z0 = red7[6];
     const bool has_inf = hasinf > 0.5;
+    // correlations of the given dual optimum carry the error of their setup
+    // dot products (depth m/64 + 8, like w)
+    const double e_ts = oracle_dual ? gw * S.tsnorm : 0.0;
+    if (oracle_dual && has_inf) {
+        // interior check of t and translation coefficient from gs
+        double tvl = 1.0, eml = 0.0;
+        for (int base = 0; base < nA; base += CH) {
+            Col c[E];
+            bool valid[E];
+            gather(base, c, valid);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (!valid[e] || !isinf(c[e].u)) continue;
+                const double ewj = gw * c[e].cn * tnorm;
+                if (!(c[e].w + ewj < 0.0)) tvl = 0.0;
+                else eml = fmax(eml, fmax(c[e].g + c[e].cn * e_ts + 4.0 * u1 * fabs(c[e].g), 0.0) / (-c[e].w - ewj));
+            }
+        }
+        tv = block_min<NT>(tvl, sh);
+        emax = block_max<NT>(eml, sh);
+    }
     const bool fallback = has_inf && !(tv > 0.5);
     const double eps = (has_inf && !fallback) ? emax * (1.0 + 4.0 * u1) : 0.0;
     const double massall = (mass + S.mass_screened) * (1.0 + gamma_k((double)n + 64.0));
     const double delta_r = gamma_k(2.0 * n + 4.0 * passes + 64.0) * (S.ynorm + 2.0 * massall);
 
     // a_j^T theta for theta = r + eps t, and its rounding bound
+    const double e_g = oracle_dual ? e_ts : gm * rnorm;     // per unit column norm
     auto corr = [&](const Col& c, double& cj, double& ej) {
         cj = fma(eps, c.w, c.g);
-        ej = c.cn * (gm * rnorm + gw * eps * tnorm) + 4.0 * u1 * (fabs(c.g) + eps * fabs(c.w));
+        ej = c.cn * (e_g + gw * eps * tnorm) + 4.0 * u1 * (fabs(c.g) + eps * fabs(c.w));
     };
 
     // gap: at eps = 0 the sweep already summed the per-column terms; with a
@@ -530,7 +588,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
         G = 0.5 * tt * tt * (1.0 + 4.0 * u1);
     } else {
         double gsum = gap0;
-        if (eps > 0.0) {
+        if (eps > 0.0 || oracle_dual) {
             double acc = 0.0, zz = -__builtin_inf();
             for (int base = 0; base < nA; base += CH) {
                 Col c[E];
@@ -554,7 +612,8 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
             gsum = block_sum<NT>(acc, sh);
             zmax = block_max<NT>(zz, sh);
         }
-        const double tt = delta_r + eps * tnorm;
+        // || (y' - A x) - theta || <= delta_r + ||r - ts|| + eps ||t||  (ts = r outside the diagnostic mode)
+        const double tt = delta_r + rts + eps * tnorm;
         G = (gsum * (1.0 + 3.0 * u1) + 0.5 * tt * tt * (1.0 + 4.0 * u1)) * (1.0 + gamma_k((double)n + 64.0));
     }
     const double rad = sqrt(2.0 * G) * (1.0 + 2.0 * u1);

@@ -38,7 +38,7 @@ class Opts(C.Structure):
                 ("power_iters", C.c_int), ("t", C.c_void_p), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("history", C.POINTER(PassRecord)), ("history_cap", C.c_long), ("profile", C.c_int),
-                ("iter_precision", C.c_int), ("graph", C.c_int)]
+                ("iter_precision", C.c_int), ("graph", C.c_int), ("theta_star", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -168,7 +168,8 @@ def colmajor(A: Any, device="cuda", dtype=None) -> torch.Tensor:
 
 def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, eps_gap=1e-6, step=0.0,
               power_iters=0, t: torch.Tensor | None = None, history=0, stream=None,
-              profile=False, iter_precision="f64", graph=False) -> tuple[Opts, Any]:
+              profile=False, iter_precision="f64", graph=False,
+              theta_star: torch.Tensor | None = None) -> tuple[Opts, Any]:
     lib = load()
     o = Opts()
     lib.bxs_default_opts(C.byref(o))
@@ -184,6 +185,7 @@ def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, 
     o.profile = 1 if profile else 0
     o.iter_precision = {"f64": 0, "bf16x3": 1}[iter_precision] if isinstance(iter_precision, str) else int(iter_precision)
     o.graph = 1 if graph else 0
+    o.theta_star = _ptr(theta_star)
     hist = None
     if history:
         hist = (PassRecord * int(history))()
@@ -223,6 +225,8 @@ def _run_single(kind, A, y, l, u, x0, kw):
         l = _vec(l, n, "l")
         u = _vec(u, n, "u")
     t = _vec(kw.pop("t", None), m, "t")
+    if kw.get("theta_star") is not None:
+        _vec(kw["theta_star"], m, "theta_star")
     x = torch.zeros(n, dtype=torch.float64, device=dev) if x0 is None else _vec(x0, n, "x0").clone()
     sat = torch.empty(n, dtype=torch.int8, device=dev)
     opts, hist = make_opts(t=t, **kw)

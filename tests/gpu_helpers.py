@@ -24,6 +24,9 @@ def run_gpu(P, kind, **kw):
     t = kw.pop("t", None)
     if t is not None:
         kw["t"] = torch.tensor(t, dtype=torch.float64, device="cuda")
+    ts = kw.pop("theta_star", None)
+    if ts is not None:
+        kw["theta_star"] = torch.tensor(ts, dtype=torch.float64, device="cuda")
     if kind == "nnls":
         x, sat, info = bx.solve_nnls(A, y, x0, **kw)
     else:
@@ -33,9 +36,9 @@ def run_gpu(P, kind, **kw):
 
 
 def run_oracle(P, *, solver="pg", screen_every=10, eps_gap=1e-6, max_iter=100000, step=None,
-               screening=True, x0=None, t=None):
+               screening=True, x0=None, t=None, theta_star=None):
     return ob.solve(P.A64(), P.y, P.l, P.u, solver=solver, K=screen_every, eps_gap=eps_gap,
-                    max_iter=max_iter, step=step, screening=screening, x0=x0, t=t)
+                    max_iter=max_iter, step=step, screening=screening, x0=x0, t=t, theta_star=theta_star)
 
 
 def assert_parity(P, xg, satg, info, res, xtol=1e-9, gap_rtol=1e-6, check_status=True):
@@ -54,7 +57,7 @@ def assert_parity(P, xg, satg, info, res, xtol=1e-9, gap_rtol=1e-6, check_status
     assert bool(info["t_valid"]) == res.t_valid
 
 
-ORACLE_KEYS = ("solver", "screen_every", "eps_gap", "max_iter", "step", "screening", "x0", "t")
+ORACLE_KEYS = ("solver", "screen_every", "eps_gap", "max_iter", "step", "screening", "x0", "t", "theta_star")
 
 
 def parity_vs_oracle(P, xg, sg, info, xtol=1e-9, **kw):

@@ -148,6 +148,32 @@ def test_cd_parity_multiwave(m, n):
     assert res.status == "ok" and np.count_nonzero(res.sat) > 0
 
 
+@pytest.mark.parametrize("solver,dtype", [("pg", np.float32), ("pg", np.float64), ("cd", np.float64)])
+def test_oracle_dual_point_parity(solver, dtype):
+    """Screening informed with the planted dual optimum theta* (Sec. 5.1,
+    Fig. 3) in place of the dual update: same passes, gaps and screened sets
+    as the oracle run with the same theta*, and at least as many coordinates
+    screened as with the usual dual update."""
+    rng = W.rng_for(91, 0, 400, 1300)
+    A = np.asfortranarray(W.unit_columns(rng.standard_normal((400, 1300))).astype(dtype))
+    l, u = -rng.random(1300), rng.random(1300)
+    y, x_star, theta, F = W.planted_bvls(A.astype(np.float64), l, u, 160, 0.05, rng)
+    P = W.Problem(A, y, l, u, x_star, True, {})
+    kw = dict(solver=solver, screen_every=10 if solver == "pg" else 1, eps_gap=1e-9, max_iter=20000)
+    if solver == "pg":
+        kw["step"] = step_of(P)
+    xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, theta_star=theta, history=2000, **kw)
+    assert res.status == "ok"
+    h = info["history"]
+    for hg, ho in zip(h, res.history):
+        assert hg["n_active"] == ho["n_active"]
+        assert hg["gap"] == pytest.approx(ho["gap"], rel=1e-6, abs=1e-11)
+    lo, hi = sg == -1, sg == 1
+    assert np.all(x_star[lo] == l[lo]) and np.all(x_star[hi] == u[hi])
+    usual = run_oracle(P, **{k: v for k, v in kw.items()})
+    assert np.count_nonzero(sg) >= np.count_nonzero(usual.sat)
+
+
 def test_cd_nnls_parity():
     P = W.c1_companion(2, 150, 400)
     kw = dict(solver="cd", screen_every=1, eps_gap=1e-9, max_iter=3000)
