@@ -67,6 +67,21 @@ typedef enum { BXS_F64 = 0, BXS_F32 = 1 } bxs_dtype;  /* storage type of A      
  * (the certification pass is FP64 in both cases). */
 typedef enum { BXS_ITER_F64 = 0, BXS_ITER_BF16X3 = 1 } bxs_iter_precision;
 
+/* Translation direction t of the dual update for u_j = +inf columns
+ * (Sec. 4.2), computed by the library from A (Prop. 2 and the choices of
+ * Sec. 5.1, Fig. 2); columns are taken normalised, a_k / ||a_k||:
+ *   BXS_T_GIVEN                 opts->t, or -1 when it is NULL (Prop. 2, case 3)
+ *   BXS_T_NEG_MEAN_COLUMN       t = -(1/n) sum_k a_k / ||a_k||   (case 2 for orthogonal A)
+ *   BXS_T_NEG_MOST_CORRELATED   t = -a_+ / ||a_+||, a_+ the column whose summed correlation
+ *                               sum_{k != j} a_j^T a_k / (||a_j|| ||a_k||) with the others is
+ *                               largest (case 4 when that column of A^T A is positive)
+ *   BXS_T_NEG_LEAST_CORRELATED  t = -a_- / ||a_-||, the smallest summed correlation
+ * Ties go to the smallest column index.  The computed t goes through the
+ * same interior check as a given one (info.t_valid).  solve_bvls / solve_nnls
+ * / solve_bvls_noalloc only (one problem per call). */
+typedef enum { BXS_T_GIVEN = 0, BXS_T_NEG_MEAN_COLUMN = 1, BXS_T_NEG_MOST_CORRELATED = 2,
+               BXS_T_NEG_LEAST_CORRELATED = 3 } bxs_translation;
+
 /* Largest number of rows a single instance may have. */
 #define BXS_MAX_ROWS 16384
 
@@ -123,6 +138,8 @@ typedef struct {
                                 Screening stays safe for any dual-feasible vector; a vector that
                                 is not the optimum only weakens it.  Same vector for every
                                 problem of a batch.                                           */
+    int     t_choice;        /* bxs_translation; with BXS_T_GIVEN opts->t applies, otherwise
+                                opts->t must be NULL                                           */
 } bxs_opts;
 
 typedef struct {
@@ -151,6 +168,8 @@ typedef struct {
     double event_overhead_ms; /* opts->profile: average HIP-event elapsed time around an
                            empty kernel on the same stream (dispatch latency included in
                            every timed launch); measured once per process and device    */
+    long   t_column;    /* column whose negative is t (BXS_T_NEG_MOST/LEAST_CORRELATED),
+                           else -1                                                      */
 } bxs_info;
 
 /* Fill *opts with defaults: PG, screening on, K = 10, max_iter = 100000,

@@ -126,6 +126,33 @@ def interior_direction_ok(A, u, t) -> bool:
     return bool(np.all(A[:, J].T @ t < 0.0))
 
 
+def translation_direction(A, choice: str):
+    """Translation directions t for the dual update (Sec. 4.2) computed from A
+    (Prop. 2 and the choices compared in Sec. 5.1, Fig. 2), with the columns
+    normalised, b_k = a_k / ||a_k||:
+      "neg_mean_column":       t = -(1/n) sum_k b_k    (Prop. 2, case 2: a negative
+                               combination of the columns of an orthogonal A)
+      "neg_most_correlated":   t = -b_+, "neg_least_correlated": t = -b_-, where
+                               b_+ (b_-) maximises (minimises) the summed correlation
+                               with the other columns, sum_{k != j} b_j^T b_k
+                               (Prop. 2, case 4, when that column of A^T A is positive);
+    ties go to the smallest index.  Returns (t, j) with j = -1 for the mean."""
+    A = np.asarray(A, dtype=np.float64)
+    nrm = np.sqrt(np.sum(A * A, axis=0))
+    B = A / np.where(nrm > 0, nrm, 1.0)
+    if choice == "neg_mean_column":
+        return -np.sum(B, axis=1) / A.shape[1], -1
+    G = B.T @ B                                    # correlations of the normalised columns
+    score = np.sum(G, axis=1) - np.diag(G)         # leave out the k = j term
+    if choice == "neg_most_correlated":
+        j = int(np.argmax(score))                  # first maximiser: smallest index on ties
+    elif choice == "neg_least_correlated":
+        j = int(np.argmin(score))
+    else:
+        raise ValueError(choice)
+    return -B[:, j].copy(), j
+
+
 def dual_point(A, y, u, x, t):
     """The dual update Theta(x) used by the screening loop.
 

@@ -113,7 +113,7 @@ struct PlanSizes {
 };
 
 // Per-instance device bytes.
-static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap, int lz_steps)
+static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap, int lz_steps, int tdir)
 {
     PlanSizes p;
     p.g_target = g_target;
@@ -128,6 +128,7 @@ static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap, int 
     b += align_up(sizeof(double) * kItemScalars * p.items_cap, 256);  // iscal
     b += align_up(sizeof(bxs_pass_record) * std::max<long>(rec_cap, 0), 256);
     if (lz_steps > 0) b += align_up(sizeof(double) * (2 * (size_t)lz_steps + 2 * m), 256);  // Lanczos
+    if (tdir) b += align_up(sizeof(double) * ((size_t)m + tdir_scratch_doubles(m, n)), 256);  // t and its scratch
     p.bytes = b;
     return p;
 }
@@ -215,6 +216,9 @@ static bxs_status check_opts(const bxs_opts* o)
     if (o->iter_precision != BXS_ITER_F64 && o->iter_precision != BXS_ITER_BF16X3)
         return fail(BXS_ERR_ARG, "unknown iter_precision %d", o->iter_precision);
     if (o->power_iters > kLanczosMax) return fail(BXS_ERR_ARG, "power_iters must be <= %d", kLanczosMax);
+    if (o->t_choice < BXS_T_GIVEN || o->t_choice > BXS_T_NEG_LEAST_CORRELATED)
+        return fail(BXS_ERR_ARG, "unknown t_choice %d", o->t_choice);
+    if (o->t_choice != BXS_T_GIVEN && o->t) return fail(BXS_ERR_ARG, "t_choice computes t: opts->t must be NULL");
     return BXS_OK;
 }
 
@@ -246,11 +250,14 @@ struct Plan {
     std::vector<int> variant;                // sweep variant per instance
     long rec_cap = 0;
     int lz_steps = 0;
+    int tdir = 0;                            // bxs_translation computed by the library (one instance)
+    double* tbuf = nullptr;                  // its t (device) and scratch
+    double* tscratch = nullptr;
     int vec = 1;
     size_t bytes = 0;
 };
 
-static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps)
+static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps, int tdir = 0)
 {
     const long count = (long)P.specs.size();
     const int cus = device_cus();
@@ -259,6 +266,7 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps)
     std::vector<int> g = group_targets(P.specs, P.variant, cus);
     P.rec_cap = rec_cap;
     P.lz_steps = lz_steps;
+    P.tdir = (count == 1) ? tdir : 0;
     P.sizes.resize(count);
     long total_items = 0;
     size_t inst_bytes = 0;
@@ -267,7 +275,7 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps)
     P.vec = 1;
     for (long i = 0; i < count; ++i) {
         const InstSpec& s = P.specs[i];
-        P.sizes[i] = instance_sizes(s.m, s.n, g[i], (i == 0 && count == 1) ? rec_cap : 0, lz_steps);
+        P.sizes[i] = instance_sizes(s.m, s.n, g[i], (i == 0 && count == 1) ? rec_cap : 0, lz_steps, P.tdir);
         total_items += P.sizes[i].items_cap;
         inst_bytes += P.sizes[i].bytes;
         if ((s.lda % vecw) != 0 || ((uintptr_t)s.A % 16) != 0) P.vec = 0;
@@ -324,6 +332,10 @@ static void layout(Plan& P, char* base)
         I.g_target = z.g_target;
         I.lz_steps = P.lz_steps;
         I.lz = P.lz_steps > 0 ? (double*)take(sizeof(double) * (2 * (size_t)P.lz_steps + 2 * s.m)) : nullptr;
+        if (P.tdir) {
+            P.tbuf = (double*)take(sizeof(double) * ((size_t)s.m + tdir_scratch_doubles(s.m, s.n)));
+            P.tscratch = P.tbuf + s.m;
+        }
         const int b = P.variant[i];
         I.item_base = (int)P.items[b].size();
         for (int t = 0; t < z.items_cap; ++t) P.items[b].push_back(Item{(int)i, t});
@@ -460,7 +472,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
 
     layout(P, (char*)ws);
     for (long i = 0; i < count; ++i) {
-        P.insts[i].t = t;
+        P.insts[i].t = P.tdir ? P.tbuf : t;
         P.insts[i].ts = o->theta_star;
     }
 
@@ -561,8 +573,14 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     if (!noalloc) BXS_HIP(hipEventRecord(ev0, stream));
 
     // ---- setup ----
+    if (P.tdir) BXS_HIP(launch_fill(P.tbuf, P.specs[0].m, -1.0, stream));   // finite until computed
     BXS_HIP(launch_init(c, (int)count, nullptr));
     for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_colstats(c, b, D.items[b], D.n_items[b]));
+    if (P.tdir) {
+        // t from the column norms, then the column statistics again for w = A^T t
+        BXS_HIP(launch_tdir(c, P.tdir, P.specs[0].m, P.specs[0].n, P.tscratch, P.tbuf, &D.st[0].t_column));
+        for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_colstats(c, b, D.items[b], D.n_items[b]));
+    }
     BXS_HIP(launch_validate(c, (int)count));
     const bool do_pow = !(o->step > 0.0);
     if (do_pow) {
@@ -835,6 +853,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             f.sweep_ms = sweep_ms;
             f.sweep_launches = sweep_launches;
             f.event_overhead_ms = ev_over;
+            f.t_column = P.tdir ? S.t_column : -1;
         }
     }
     if (history && count == 1) {
@@ -964,7 +983,8 @@ bxs_status bxs_workspace_size_batch(long count, const long* m, const long* n, co
         sp.m = m[i]; sp.n = n[i]; sp.lda = m[i];
         if (sp.m < 1 || sp.n < 1 || sp.m > BXS_MAX_ROWS) return fail(BXS_ERR_SHAPE, "problem %ld: bad shape", i);
     }
-    build_plan(P, BXS_F64, (count == 1 && opts->history) ? opts->history_cap : 0, lanczos_steps(opts));
+    build_plan(P, BXS_F64, (count == 1 && opts->history) ? opts->history_cap : 0, lanczos_steps(opts),
+               opts->t_choice);
     *bytes = P.bytes;
     return BXS_OK;
 }
@@ -985,10 +1005,12 @@ static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const 
         s = check_spec(specs[i], (long)i);
         if (s != BXS_OK) return s;
     }
+    if (opts->t_choice != BXS_T_GIVEN && specs.size() != 1)
+        return fail(BXS_ERR_ARG, "t_choice is available for single problems only");
     Plan P;
     P.specs = specs;
     const long rc = (specs.size() == 1 && opts->history) ? opts->history_cap : 0;
-    s = build_plan(P, a_dtype, rc, lanczos_steps(opts));
+    s = build_plan(P, a_dtype, rc, lanczos_steps(opts), opts->t_choice);
     if (s != BXS_OK) return s;
     return run(P, a_dtype, opts, opts->t, infos, opts->history, opts->history_cap, fixed);
 }

@@ -81,6 +81,7 @@ struct State {
     double tsnorm;          // upper bound of ||ts||_2
     double ynorm;           // upper bound of ||y||_2
     double mass_screened;   // sum over screened j of |x_j| * cn_j
+    int t_column;           // column picked for t by the library (bxs_translation), or -1
 };
 
 // Per-item scalars written by the correlation sweep for the screening pass:
@@ -273,5 +274,9 @@ hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int scre
                          int final_pass, int K, int kk, int ahead, int* host_done, double* host_gap,
                          int* host_seq);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
+// translation direction computed from A (tdir.hip, one instance)
+size_t tdir_scratch_doubles(long m, long n);
+hipError_t launch_tdir(const LaunchCtx& c, int choice, long m, long n, double* scratch, double* t, int* picked);
+hipError_t launch_fill(double* p, long n, double v, hipStream_t s);
 
 }  // namespace bxs

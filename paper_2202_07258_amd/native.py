@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "ok", 1: "err_arg", 2: "err_shape", 3: "err_nonfinite", 4: "e
 BXS_PG, BXS_CD = 0, 1
 BXS_F64, BXS_F32 = 0, 1
 MAX_ROWS = 16384
+T_CHOICES = {"given": 0, "neg_mean_column": 1, "neg_most_correlated": 2, "neg_least_correlated": 3}
 
 
 class PassRecord(C.Structure):
@@ -38,7 +39,8 @@ class Opts(C.Structure):
                 ("power_iters", C.c_int), ("t", C.c_void_p), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("history", C.POINTER(PassRecord)), ("history_cap", C.c_long), ("profile", C.c_int),
-                ("iter_precision", C.c_int), ("graph", C.c_int), ("theta_star", C.c_void_p)]
+                ("iter_precision", C.c_int), ("graph", C.c_int), ("theta_star", C.c_void_p),
+                ("t_choice", C.c_int)]
 
 
 class Info(C.Structure):
@@ -47,7 +49,7 @@ class Info(C.Structure):
                 ("gap", C.c_double), ("primal", C.c_double), ("radius", C.c_double), ("eps", C.c_double),
                 ("step", C.c_double), ("lipschitz", C.c_double), ("ms_setup", C.c_double),
                 ("ms_solve", C.c_double), ("col_iters", C.c_long), ("sweep_ms", C.c_double),
-                ("sweep_launches", C.c_long), ("event_overhead_ms", C.c_double)]
+                ("sweep_launches", C.c_long), ("event_overhead_ms", C.c_double), ("t_column", C.c_long)]
 
 
 class Problem(C.Structure):
@@ -169,7 +171,7 @@ def colmajor(A: Any, device="cuda", dtype=None) -> torch.Tensor:
 def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, eps_gap=1e-6, step=0.0,
               power_iters=0, t: torch.Tensor | None = None, history=0, stream=None,
               profile=False, iter_precision="f64", graph=False,
-              theta_star: torch.Tensor | None = None) -> tuple[Opts, Any]:
+              theta_star: torch.Tensor | None = None, t_choice="given") -> tuple[Opts, Any]:
     lib = load()
     o = Opts()
     lib.bxs_default_opts(C.byref(o))
@@ -186,6 +188,7 @@ def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, 
     o.iter_precision = {"f64": 0, "bf16x3": 1}[iter_precision] if isinstance(iter_precision, str) else int(iter_precision)
     o.graph = 1 if graph else 0
     o.theta_star = _ptr(theta_star)
+    o.t_choice = T_CHOICES[t_choice] if isinstance(t_choice, str) else int(t_choice)
     hist = None
     if history:
         hist = (PassRecord * int(history))()

@@ -174,6 +174,50 @@ def test_oracle_dual_point_parity(solver, dtype):
     assert np.count_nonzero(sg) >= np.count_nonzero(usual.sat)
 
 
+@pytest.mark.parametrize("choice", ["neg_mean_column", "neg_most_correlated", "neg_least_correlated"])
+def test_library_translation_direction(choice):
+    """t computed by the library from A (Prop. 2 and the choices of Sec. 5.1,
+    Fig. 2) on a non-negative NNLS instance: the same column as the oracle's
+    choice, and the trajectory of the oracle run with the oracle's t."""
+    P = W.c1_companion(4, 150, 400)
+    t_ora, j = ob.translation_direction(P.A64(), choice)
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=3000, step=step_of(P))
+    xg, sg, info = run_gpu(P, "nnls", t_choice=choice, **kw)
+    assert info["t_column"] == j and info["t_valid"] == 1
+    parity_vs_oracle(P, xg, sg, info, t=t_ora, **kw)
+
+
+def test_library_translation_direction_prop2_cases_2_and_4():
+    """Prop. 2 case 2 (orthogonal A: the negative mean column is interior) and
+    case 4 (a signed A whose Gram matrix has a positive column: minus that
+    column is interior), both chosen by the library."""
+    rng = W.rng_for(92, 0)
+    Q, _ = np.linalg.qr(rng.standard_normal((300, 300)))
+    y = rng.standard_normal(300)
+    P = W.Problem(np.asfortranarray(Q), y, np.zeros(300), np.full(300, np.inf))
+    t_ora, _ = ob.translation_direction(Q, "neg_mean_column")
+    # a small step keeps PG from converging in one pass, so screening fires
+    kw = dict(screen_every=1, eps_gap=1e-9, max_iter=2000, step=0.2)
+    xg, sg, info = run_gpu(P, "nnls", t_choice="neg_mean_column", **kw)
+    assert info["t_valid"] == 1 and np.count_nonzero(sg) > 0
+    parity_vs_oracle(P, xg, sg, info, t=t_ora, **kw)
+    # the closed-form optimum of an orthogonal problem, x* = max(Q^T y, 0)
+    assert np.max(np.abs(xg - np.maximum(Q.T @ y, 0.0))) <= 1e-4
+    rng = W.rng_for(92, 1)
+    c = rng.standard_normal(200)
+    A = c[:, None] + 2.0 * rng.standard_normal((200, 500))
+    A[:, 3] = c
+    y = A @ (np.abs(rng.standard_normal(500)) * (rng.random(500) < 0.05)) + 0.5 * rng.standard_normal(200)
+    P = W.Problem(np.asfortranarray(A), y, np.zeros(500), np.full(500, np.inf))
+    t_ora, j = ob.translation_direction(A, "neg_most_correlated")
+    assert j == 3 and np.all(A.T @ t_ora < 0) and not np.all(A >= 0)
+    # a fixed budget: PG needs ~1e5 iterations to a small gap on this matrix
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=3000, step=step_of(P))
+    xg, sg, info = run_gpu(P, "nnls", t_choice="neg_most_correlated", **kw)
+    assert info["t_column"] == j and info["t_valid"] == 1
+    parity_vs_oracle(P, xg, sg, info, t=t_ora, **kw)
+
+
 def test_cd_nnls_parity():
     P = W.c1_companion(2, 150, 400)
     kw = dict(solver="cd", screen_every=1, eps_gap=1e-9, max_iter=3000)

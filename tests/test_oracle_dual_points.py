@@ -98,3 +98,71 @@ def test_translation_converges_to_theta_star():
         assert ok and dist < prev
         prev = dist
     assert prev < 1e-2
+
+
+# ---------------------------------------------------------------------------
+# Translation directions computed from A (Prop. 2, Sec. 5.1 Fig. 2)
+# ---------------------------------------------------------------------------
+def _brute_scores(A):
+    n = A.shape[1]
+    s = np.zeros(n)
+    for j in range(n):
+        bj = A[:, j] / np.linalg.norm(A[:, j])
+        for k in range(n):
+            if k != j:
+                s[j] += bj @ (A[:, k] / np.linalg.norm(A[:, k]))
+    return s
+
+
+def test_correlated_columns_match_brute_force():
+    rng = np.random.default_rng(40)
+    A = rng.standard_normal((9, 14))
+    s = _brute_scores(A)
+    t, j = ob.translation_direction(A, "neg_most_correlated")
+    assert j == int(np.argmax(s))
+    assert np.allclose(t, -A[:, j] / np.linalg.norm(A[:, j]))
+    t, j = ob.translation_direction(A, "neg_least_correlated")
+    assert j == int(np.argmin(s))
+    t, j = ob.translation_direction(A, "neg_mean_column")
+    assert j == -1
+    assert np.allclose(t, -sum(A[:, k] / np.linalg.norm(A[:, k]) for k in range(14)) / 14)
+
+
+def test_planted_mistake_argmin_for_most_correlated_is_caught(monkeypatch):
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((9, 14))
+    real = ob.translation_direction
+    monkeypatch.setattr(ob, "translation_direction",
+                        lambda A, c: real(A, "neg_least_correlated" if c == "neg_most_correlated" else c))
+    _, j = ob.translation_direction(A, "neg_most_correlated")
+    assert j != int(np.argmax(_brute_scores(A)))
+
+
+def test_prop2_case2_orthogonal_mean_column():
+    rng = np.random.default_rng(42)
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    t, _ = ob.translation_direction(Q, "neg_mean_column")
+    # a_i^T t = -1/n for every column of an orthogonal matrix
+    assert np.allclose(Q.T @ t, -np.ones(12) / 12, atol=1e-14)
+    assert ob.interior_direction_ok(Q, np.full(12, np.inf), t)
+
+
+def test_prop2_case4_positive_gram_column():
+    # a signed matrix whose column 3 is positively correlated with every other
+    rng = np.random.default_rng(43)
+    c = rng.standard_normal(20)
+    A = c[:, None] + 0.3 * rng.standard_normal((20, 30))
+    A[:, 3] = c
+    assert np.all((A.T @ A)[:, 3] > 0)
+    assert not np.all(A >= 0)
+    t, j = ob.translation_direction(A, "neg_most_correlated")
+    assert np.all(A.T @ t < 0)                       # -a_j interior (case 4)
+    assert ob.interior_direction_ok(A, np.full(30, np.inf), t)
+
+
+def test_prop2_case3_every_choice_interior_for_nonnegative_A():
+    rng = np.random.default_rng(44)
+    A = np.abs(rng.standard_normal((15, 40)))
+    for choice in ("neg_mean_column", "neg_most_correlated", "neg_least_correlated"):
+        t, _ = ob.translation_direction(A, choice)
+        assert np.all(A.T @ t < 0), choice
