@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <string>
+#include <chrono>
 #include <vector>
 
 #include "bxs_internal.h"
@@ -93,7 +94,8 @@ constexpr int kG3K = 32;   // K step (one 16x16x32 MFMA)
 struct G3Args {
     const u16* Ahi; const u16* Alo; long long lda;     // Aop, lda = padded K
     int tiles_m, tiles_n, K;                            // K = padded K (multiple of 32)
-    const int* act; int nact;                           // active right-hand sides
+    const int* act; int nact;                           // active right-hand sides (host bound)
+    const int* nact_dev;                                // their device count (<= nact)
     const u16* Bhi; const u16* Blo; long long ldb;     // Bop column b at b * ldb
     u16* Ohi; u16* Olo; long long ldo;                 // EPI 0 output split (U), EPI 1: D
     float* G; double* X; const signed char* sat; long long ldsat;   // EPI 1 (n x B, ld n)
@@ -130,7 +132,11 @@ void k_gemm3(G3Args p)
     const int t = (tiles % 8 == 0) ? (id % 8) * (tiles / 8) + id / 8 : id;
     const int row0 = (t % p.tiles_m) * TM, col0 = (t / p.tiles_m) * TM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < TM) s_act[tid] = (col0 + tid < p.nact) ? p.act[col0 + tid] : -1;
+    // the grid is sized from a host bound that may lag the device count by a
+    // pass (the host enqueues one pass ahead); tiles past the count return
+    const int nact = min(p.nact, *p.nact_dev);
+    if (col0 >= nact) return;
+    if (tid < TM) s_act[tid] = (col0 + tid < nact) ? p.act[col0 + tid] : -1;
     __syncthreads();
     auto soff = [](int r, int c) { return r * kG3K + 8 * ((c + (r >> 2)) & 3); };
 
@@ -659,9 +665,13 @@ void k_b_screen(int m, int n, int B, const double* __restrict__ R64, const doubl
     }
 }
 
-// compact the active right-hand-side list (one workgroup, order kept)
+// compact the active right-hand-side list (one workgroup, order kept); with
+// host_words set, then publish the active count and the stop counter to
+// coherent host memory and, last, with a system-scope release, the number of
+// passes run (the host waits on that word instead of a synchronisation)
 __global__ __launch_bounds__(1024)
-void k_b_compact_rhs(int B, const BState* __restrict__ st, int* __restrict__ act, int* __restrict__ nact)
+void k_b_compact_rhs(int B, const BState* __restrict__ st, int* __restrict__ act, int* __restrict__ nact,
+                     const int* __restrict__ done_counter, int* __restrict__ host_words, int seq)
 {
     __shared__ int wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -679,7 +689,15 @@ void k_b_compact_rhs(int B, const BState* __restrict__ st, int* __restrict__ act
         out += tot;
         __syncthreads();
     }
-    if (tid == 0) *nact = out;
+    if (tid == 0) {
+        *nact = out;
+        if (host_words) {
+            host_words[1] = out;
+            host_words[2] = *done_counter;
+            __threadfence_system();
+            __hip_atomic_store(host_words, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 __global__ void k_b_iota(int* __restrict__ act, int B, int* __restrict__ nact)
@@ -879,11 +897,26 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
         BXS_HIPB(hipGetDevice(&dev));
         BXS_HIPB(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     }
-    int* hdone = nullptr;
-    BXS_HIPB(hipHostMalloc((void**)&hdone, 2 * sizeof(int), hipHostMallocDefault));
-    struct HG { int* p; ~HG() { (void)hipHostFree(p); } } hg{hdone};
+    // Coherent host words the compaction kernel publishes after every pass:
+    // [0] passes run, [1] active right-hand sides, [2] stopped ones.
+    int* hw = nullptr;
+    {
+        static thread_local struct Words {
+            int* p = nullptr;
+            ~Words() { if (p) (void)hipHostFree(p); }
+        } words;
+        if (!words.p) BXS_HIPB(hipHostMalloc((void**)&words.p, 64, hipHostMallocCoherent));
+        hw = words.p;
+    }
+    __atomic_store_n(&hw[0], 0, __ATOMIC_RELEASE);
+    int hcnt[2] = {(int)B, 0};          // profile mode: copied back after each pass
     const int K = o->screen_every;
     long long iters = 0;
+    // Passes are enqueued one ahead of the host's stop check (its GEMM grids
+    // are sized from the active count of the pass before, an upper bound; the
+    // kernels bound themselves by the device count).  Profile mode
+    // synchronises every pass to read its events.
+    const bool ahead = !o->profile;
     // optional HIP-event timing of the iteration GEMM pairs
     std::vector<hipEvent_t> pev;
     struct PG2 { std::vector<hipEvent_t>* v; ~PG2() { for (auto e : *v) if (e) (void)hipEventDestroy(e); } } pg2{&pev};
@@ -893,7 +926,9 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     }
     double gemm_ms = 0.0;
     long gemm_pairs = 0;
-    while (true) {
+    std::vector<long long> pass_kk;      // per enqueued pass: iterations
+    std::vector<int> pass_final;
+    auto enqueue_pass = [&](int seq) -> bxs_status {
         const long long kk = std::min<long long>(K, o->max_iter - iters);
         if (prec == 1) {
             // step 1 from the exact gradient, then kk-1 x [U = A D; G -= A^T U and step]
@@ -901,9 +936,11 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
                 k_b_step_split<<<grid, 256, 0, s>>>(X64, G32, (int)n, act, nact, sat, ldsat, eta, Dh, Dl, np);
             G3Args g0{};
             g0.Ahi = ARh; g0.Alo = ARl; g0.lda = np; g0.K = (int)np; g0.act = act; g0.nact = hnact;
+            g0.nact_dev = nact;
             g0.Bhi = Dh; g0.Blo = Dl; g0.ldb = np; g0.Ohi = Uh; g0.Olo = Ul; g0.ldo = mp;
             G3Args g1{};
             g1.Ahi = ACh; g1.Alo = ACl; g1.lda = mp; g1.K = (int)mp; g1.act = act; g1.nact = hnact;
+            g1.nact_dev = nact;
             g1.Bhi = Uh; g1.Blo = Ul; g1.ldb = mp; g1.Ohi = Dh; g1.Olo = Dl; g1.ldo = np;
             g1.G = G32; g1.X = X64; g1.sat = sat; g1.ldsat = ldsat; g1.n = (int)n; g1.eta = eta;
             for (long long k = 1; k < kk && hnact > 0; ++k) {
@@ -915,34 +952,71 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
         } else {
             for (long long k = 0; k < kk; ++k) {
                 if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k], s));
-                bs = residual_and_corr();
-                if (bs != BXS_OK) return bs;
+                bxs_status b2 = residual_and_corr();
+                if (b2 != BXS_OK) return b2;
                 if (o->profile) BXS_HIPB(hipEventRecord(pev[2 * k + 1], s));
                 k_b_update64<<<grid, 256, 0, s>>>(X64, G64, (int)n, (int)B, sat, ldsat, st, eta);
             }
         }
         iters += kk;
-        bs = residual_and_corr();
-        if (bs != BXS_OK) return bs;
+        bxs_status b3 = residual_and_corr();
+        if (b3 != BXS_OK) return b3;
         const int final_pass = iters >= o->max_iter;
         k_b_screen<<<(int)B, 256, 0, s>>>((int)m, (int)n, (int)B, R64, G64, X64, X32, Y64, cn, w, scal, sat, ldsat, st,
                                           done_counter, o->eps_gap, o->screening, final_pass, iters, (int)kk);
-        k_b_compact_rhs<<<1, 1024, 0, s>>>((int)B, st, act, nact);
+        k_b_compact_rhs<<<1, 1024, 0, s>>>((int)B, st, act, nact, done_counter, ahead ? hw : nullptr, seq);
         // the next pass of the BF16x3 engine restarts from the exact gradient
         if (prec == 1) k_b_g64_to_32<<<grid, 256, 0, s>>>(G64, G32, (int)n, act, nact);
         BXS_HIPB(hipGetLastError());
-        BXS_HIPB(hipMemcpyAsync(hdone, nact, 2 * sizeof(int), hipMemcpyDeviceToHost, s));   // nact, done count
-        BXS_HIPB(hipStreamSynchronize(s));
-        hnact = hdone[0];
-        if (o->profile) {
-            for (long long k = (prec == 1) ? 1 : 0; k < kk; ++k) {
+        if (!ahead) {
+            BXS_HIPB(hipMemcpyAsync(hcnt, nact, sizeof(int), hipMemcpyDeviceToHost, s));
+            BXS_HIPB(hipMemcpyAsync(hcnt + 1, done_counter, sizeof(int), hipMemcpyDeviceToHost, s));
+        }
+        pass_kk.push_back(kk);
+        pass_final.push_back(final_pass);
+        return BXS_OK;
+    };
+
+    bs = enqueue_pass(1);
+    if (bs != BXS_OK) return bs;
+    for (int cur = 1;; ++cur) {
+        // the next pass goes out before this one is waited for
+        if (ahead && !pass_final[cur - 1]) {
+            bs = enqueue_pass(cur + 1);
+            if (bs != BXS_OK) return bs;
+        }
+        int n_active = 0, n_done = 0;
+        if (ahead) {
+            const auto t0 = std::chrono::steady_clock::now();
+            long spins = 0;
+            while (__atomic_load_n(&hw[0], __ATOMIC_ACQUIRE) < cur) {
+                __builtin_ia32_pause();
+                // should the word not advance (it always does), the stream's
+                // completion makes every published value final
+                if ((++spins & 4095) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+                    BXS_HIPB(hipStreamSynchronize(s));
+                    break;
+                }
+            }
+            n_active = __atomic_load_n(&hw[1], __ATOMIC_ACQUIRE);
+            n_done = __atomic_load_n(&hw[2], __ATOMIC_ACQUIRE);
+        } else {
+            BXS_HIPB(hipStreamSynchronize(s));
+            n_active = hcnt[0];
+            n_done = hcnt[1];
+            for (long long k = (prec == 1) ? 1 : 0; k < pass_kk[cur - 1]; ++k) {
                 float ms = 0.f;
                 BXS_HIPB(hipEventElapsedTime(&ms, pev[2 * k], pev[2 * k + 1]));
                 gemm_ms += ms;
                 ++gemm_pairs;
             }
         }
-        if (hdone[1] >= B || final_pass) break;
+        hnact = n_active;
+        if (n_done >= B || pass_final[cur - 1]) break;
+        if (!ahead) {
+            bs = enqueue_pass(cur + 1);
+            if (bs != BXS_OK) return bs;
+        }
     }
     k_b_output<<<grid, 256, 0, s>>>(X64, X, ldx, (int)n, (int)B);
     BXS_HIPB(hipEventRecord(e2, s));
