@@ -61,7 +61,11 @@ typedef enum {
     BXS_SINGULAR      = 8   /* adjoint: a free-set normal matrix is singular       */
 } bxs_status;
 
-typedef enum { BXS_PG = 0, BXS_CD = 1 } bxs_solver;   /* projected gradient / cyclic coordinate descent */
+/* projected gradient / cyclic coordinate descent / Chambolle-Pock primal-dual
+ * (Sec. 5: x+ = Pi(x - tau A^T v), v+ = (v + sigma (A (2 x+ - x) - y)) / (1 + sigma),
+ * tau = sigma = opts->step or 1 / (1.05 sqrt(L_est)); the screening test uses
+ * the residual dual point of Sec. 4 like the other solvers) */
+typedef enum { BXS_PG = 0, BXS_CD = 1, BXS_CP = 2 } bxs_solver;
 typedef enum { BXS_F64 = 0, BXS_F32 = 1 } bxs_dtype;  /* storage type of A                               */
 /* Arithmetic of the primal iterations of the batched shared-matrix solver
  * (the certification pass is FP64 in both cases). */

@@ -211,6 +211,24 @@ def pg_step(A, y, l, u, x, eta):
     return project(x + eta * g, l, u)
 
 
+def cp_step(A, y, l, u, x, v, tau, sigma):
+    """One Chambolle-Pock primal-dual iteration (Chambolle & Pock 2011, the
+    paper's second BVLS solver in Sec. 5) on min_x F(Ax) + G(x) with
+    F(z) = 1/2 ||z - y||^2 and G the indicator of [l, u], in the order primal
+    step, extrapolation, dual step:
+        x+ = Pi_[l,u](x - tau A^T v)
+        xb = 2 x+ - x
+        v+ = prox_{sigma F*}(v + sigma A xb) = (v + sigma (A xb - y)) / (1 + sigma)
+    since F*(v) = 1/2 ||v||^2 + v^T y.  Converges for tau sigma ||A||_2^2 < 1;
+    at a saddle point v = A x* - y, the negated dual optimum of eq. Dual_obj.
+    Returns (x+, v+)."""
+    A = np.asarray(A, dtype=np.float64)
+    xn = project(x - tau * (A.T @ v), l, u)
+    xb = 2.0 * xn - x
+    vn = (v + sigma * (A @ xb - y)) / (1.0 + sigma)
+    return xn, vn
+
+
 def cd_sweep(A, y, l, u, x):
     """One cyclic sweep of exact coordinate minimisation, j = 0..n-1 in order:
     x_j <- Pi_[l_j,u_j](x_j + a_j^T r / ||a_j||^2), r <- r - delta_j a_j,
@@ -342,7 +360,12 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
 
     ``screening=False`` is the unscreened baseline: the same iterations and the
     same gap evaluation for stopping, but step 5 is skipped.
-    ``step`` defaults to 1/||A||_2^2; ``t`` defaults to -1 (Sec. 5).
+    ``step`` defaults to 1/||A||_2^2 (PG); for Chambolle-Pock (solver "cp",
+    Sec. 5's primal-dual BVLS solver, ``cp_step``) it is tau = sigma, default
+    1/(1.05 ||A||_2); its dual iterate v is kept across screening passes (it
+    lives in R^m, which the reduction does not change), while the dual point
+    of the screening test is the residual one of Sec. 4 as for every solver.
+    ``t`` defaults to -1 (Sec. 5).
     ``keep_theta`` stores each pass's dual point, iterate and preserved set in
     the history (for the safe-sphere checks).
     ``theta_star`` (a known dual optimum) replaces the dual update by
@@ -354,10 +377,16 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
     l = np.asarray(l, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
     t = -np.ones(m) if t is None else np.asarray(t, dtype=np.float64)
-    if solver not in ("pg", "cd"):
+    if solver not in ("pg", "cd", "cp"):
         raise ValueError(solver)
-    eta = (1.0 / lipschitz(A)) if step is None else float(step)
+    if solver == "cp":
+        # tau = sigma = step, default 1 / (1.05 ||A||_2): tau sigma ||A||^2 < 1
+        eta = (1.0 / (1.05 * np.sqrt(lipschitz(A)))) if step is None else float(step)
+    else:
+        eta = (1.0 / lipschitz(A)) if step is None else float(step)
     x = project(np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64), l, u)
+    # Chambolle-Pock dual iterate: the dual step from x0 with v = 0
+    v = eta * (A @ x - y) / (1.0 + eta) if solver == "cp" else None
     sat = np.zeros(n, dtype=np.int8)
     P = np.arange(n)
     yp = y.copy()
@@ -371,7 +400,12 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
         xP = x[P]
         kk = min(K, max_iter - iters)
         for _ in range(kk):
-            xP = pg_step(AP, yp, lP, uP, xP, eta) if solver == "pg" else cd_sweep(AP, yp, lP, uP, xP)
+            if solver == "pg":
+                xP = pg_step(AP, yp, lP, uP, xP, eta)
+            elif solver == "cd":
+                xP = cd_sweep(AP, yp, lP, uP, xP)
+            else:
+                xP, v = cp_step(AP, yp, lP, uP, xP, v, eta, eta)
         iters += kk
         x[P] = xP
         if theta_star is None:

@@ -205,7 +205,8 @@ static size_t common_bytes(long count, long total_items, long total_ritems)
 static bxs_status check_opts(const bxs_opts* o)
 {
     if (!o) return fail(BXS_ERR_ARG, "opts is NULL");
-    if (o->solver != BXS_PG && o->solver != BXS_CD) return fail(BXS_ERR_ARG, "unknown solver %d", o->solver);
+    if (o->solver != BXS_PG && o->solver != BXS_CD && o->solver != BXS_CP)
+        return fail(BXS_ERR_ARG, "unknown solver %d", o->solver);
     if (o->screening != 0 && o->screening != 1) return fail(BXS_ERR_ARG, "screening must be 0 or 1");
     if (o->screen_every < 1) return fail(BXS_ERR_ARG, "screen_every must be >= 1");
     if (o->max_iter < 1) return fail(BXS_ERR_ARG, "max_iter must be >= 1");
@@ -545,6 +546,11 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         const hipError_t e = launch_sweep(c, b, kModeStepS, D.items[b], D.n_items[b]);
         return e != hipSuccess ? e : launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]);
     };
+    auto sweep_cp = [&](int b) -> hipError_t {
+        if (!variant_two_pass(b)) return launch_sweep(c, b, kModeCP, D.items[b], D.n_items[b]);
+        const hipError_t e = launch_sweep(c, b, kModeStepCP, D.items[b], D.n_items[b]);
+        return e != hipSuccess ? e : launch_sweep(c, b, kModeAxS, D.items[b], D.n_items[b]);
+    };
     auto sweep_pow = [&](int b) -> hipError_t {
         if (!variant_two_pass(b)) return launch_sweep(c, b, kModePow, D.items[b], D.n_items[b]);
         const hipError_t e = launch_sweep(c, b, kModePowG, D.items[b], D.n_items[b]);
@@ -590,13 +596,14 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         for (int k = 0; k < np; ++k) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pow(b));
             BXS_HIP(launch_reduce(c, kRedPow, D.ritems, D.n_ritems));
-            BXS_HIP(launch_lanczos(c, (int)count, k, k == np - 1));
+            BXS_HIP(launch_lanczos(c, (int)count, k, k == np - 1, o->solver == BXS_CP));
         }
     } else {
         BXS_HIP(launch_set_step(c, (int)count, o->step));
     }
     for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
     BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+    if (o->solver == BXS_CP) BXS_HIP(launch_cp_init(c, (int)count));
     if (!noalloc) BXS_HIP(hipEventRecord(ev1, stream));
 
     // instances that failed validation are stopped on the device (k_validate)
@@ -655,6 +662,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     // instead of kk + 1.  Every iterate is the one of the plain order (test,
     // fold, step): the step is only kept when the test fixed nothing.
     const bool pg = o->solver == BXS_PG;
+    const bool cp = o->solver == BXS_CP;
     // Direct launches without profiling: the host waits for a pass by reading
     // the pass count the screening kernel publishes (no completion event
     // between passes on the stream); graph replay and profiling use events.
@@ -669,12 +677,16 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k], stream));
             if (pg) {
                 for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pg(b, first));
+            } else if (cp) {
+                for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_cp(b));
             } else {
                 for (int b = 0; b < kNumCdBuckets; ++b) BXS_HIP(launch_cd(c, b, D.lists[b], D.n_list[b], 1));
             }
             if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k + 1], stream));
             if (pg) {
                 BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, first));
+            } else if (cp) {
+                BXS_HIP(launch_reduce(c, kRedCP, D.ritems, D.n_ritems));
             } else {
                 // fresh residual from the updated iterate
                 for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
@@ -685,6 +697,11 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pgs(b));
             BXS_HIP(launch_reduce(c, kRedAhead, D.ritems, D.n_ritems));
         } else {
+            if (cp) {
+                // the screening test needs the residual at x (the iteration carries A x-bar)
+                for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
+                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+            }
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
         }
         BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk, pg ? 1 : 0,

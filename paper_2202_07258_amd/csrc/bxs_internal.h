@@ -121,9 +121,14 @@ enum SweepMode : int {
     kModeStepS = 7,         // kModePGS without the product
     kModePowG = 8,          // g = A^T r stored
     kModeAg = 9,            // partial += A g
-    kModePG1 = 10           // kModePG for the first iteration of a pass: returns at once
+    kModePG1 = 10,          // kModePG for the first iteration of a pass: returns at once
                             // when the previous screening pass took this step (a kernel
                             // of its own, so profiles separate it from the full sweeps)
+    // Chambolle-Pock iteration (the dual iterate v lives in r2): x+ = Pi(x - tau A^T v),
+    // partial += A (2 x+ - x); the two-pass form keeps 2 x+ - x in xs for the product pass
+    kModeCP = 11,
+    kModeStepCP = 12,       // kModeCP without the product
+    kModeAxS = 13           // partial += A xs
 };
 
 // Shapes that run the PG step, the screening sweep and the products with
@@ -134,7 +139,8 @@ enum ReduceMode : int {
     kRedResidual = 0,       // r = yp - sum
     kRedFold = 1,           // yp -= sum, r -= sum2
     kRedPow = 2,            // r = sum (= A A^T r)
-    kRedAhead = 3           // r2 = yp - sum
+    kRedAhead = 3,          // r2 = yp - sum
+    kRedCP = 4              // Chambolle-Pock dual step: r2 = (r2 + s (sum - yp)) / (1 + s), s = step
 };
 
 // gamma_k = k u / (1 - k u), u = 2^-53: the standard bound on the relative
@@ -264,7 +270,10 @@ hipError_t launch_validate(const LaunchCtx& c, int count);
 hipError_t launch_publish(const LaunchCtx& c, int* host_dst);
 hipError_t launch_pow_init(const LaunchCtx& c, int count);
 hipError_t launch_set_step(const LaunchCtx& c, int count, double step);
-hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last);
+// cp = 1: the step is the Chambolle-Pock tau = sigma = 1 / (1.05 sqrt(L_est))
+hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last, int cp = 0);
+// Chambolle-Pock start: v = sigma (A x0 - y') / (1 + sigma) = -sigma r / (1 + sigma) into r2
+hipError_t launch_cp_init(const LaunchCtx& c, int count);
 // host_done: pinned host word that receives the stop counter at the end of
 // the pass (nullptr: the caller copies it itself); host_gap: pinned host
 // double that receives the gap of instance 0 (single-instance calls), or

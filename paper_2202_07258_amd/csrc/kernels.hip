@@ -107,6 +107,10 @@ void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RIte
         } else if constexpr (MODE == kRedFold) {
             I.yp[row] = ypv - tot;
             I.r[row] -= tot2;
+        } else if constexpr (MODE == kRedCP) {
+            // dual step of Chambolle-Pock: prox of sigma F*, F*(v) = 1/2 ||v||^2 + v^T y'
+            const double sg = S.step;
+            I.r2[row] = (I.r2[row] + sg * (tot - ypv)) / (1.0 + sg);
         } else {
             I.r[row] = tot;
         }
@@ -359,7 +363,7 @@ __device__ double tridiag_max_eig(const double* a, const double* b, int s)
 // to it than the power iteration with as many products) gives the PG step
 // 1 / (1.05 L).  One workgroup per instance.
 __global__ __launch_bounds__(1024)
-void k_lanczos(const Inst* __restrict__ insts, State* __restrict__ st, int k, int last)
+void k_lanczos(const Inst* __restrict__ insts, State* __restrict__ st, int k, int last, int cp)
 {
     constexpr int NT = 1024;
     __shared__ double sh[NT / 64];
@@ -401,7 +405,8 @@ void k_lanczos(const Inst* __restrict__ insts, State* __restrict__ st, int k, in
             const double lam = tridiag_max_eig(al, be, k + 1);
             if (tid == 0) {
                 S.lipschitz = lam;
-                S.step = (lam > 0.0) ? 1.0 / (1.05 * lam) : 1.0;
+                // PG: 1 / (1.05 L); Chambolle-Pock: tau = sigma = 1 / (1.05 sqrt(L)), tau sigma L < 1
+                S.step = (lam > 0.0) ? (cp ? 1.0 / (1.05 * sqrt(lam)) : 1.0 / (1.05 * lam)) : 1.0;
             }
         }
     }
@@ -974,6 +979,7 @@ hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int 
     case kRedFold: k_reduce<kRedFold><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first, c.single); break;
     case kRedPow: k_reduce<kRedPow><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first, c.single); break;
     case kRedAhead: k_reduce<kRedAhead><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first, c.single); break;
+    case kRedCP: k_reduce<kRedCP><<<grid, block, 0, c.stream>>>(c.insts, c.st, ritems, first, c.single); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1024,9 +1030,25 @@ hipError_t launch_set_step(const LaunchCtx& c, int count, double step)
     return hipGetLastError();
 }
 
-hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last)
+hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last, int cp)
 {
-    k_lanczos<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, k, last);
+    k_lanczos<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, k, last, cp);
+    return hipGetLastError();
+}
+
+// Chambolle-Pock start: the dual step from x0 with v = 0,
+// v = sigma (A x0 - y') / (1 + sigma) = -sigma r / (1 + sigma); grid (blocks, count)
+__global__ __launch_bounds__(256)
+void k_cp_init(const Inst* __restrict__ insts, const State* __restrict__ st)
+{
+    const Inst& I = insts[blockIdx.y];
+    const double sg = st[blockIdx.y].step;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < I.m; i += gridDim.x * 256) I.r2[i] = -sg * I.r[i] / (1.0 + sg);
+}
+
+hipError_t launch_cp_init(const LaunchCtx& c, int count)
+{
+    k_cp_init<<<dim3(16, count), dim3(256), 0, c.stream>>>(c.insts, c.st);
     return hipGetLastError();
 }
 

@@ -39,12 +39,14 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 {
     constexpr int RO = R / V;
     constexpr bool SCR = (MODE == kModeCorr || MODE == kModePGS || MODE == kModeStepS);  // screening at x
+    constexpr bool CPM = (MODE == kModeCP || MODE == kModeStepCP);   // Chambolle-Pock: v in r2
     constexpr bool STP = (MODE == kModePG || MODE == kModePG1 || MODE == kModePGS || MODE == kModeStep ||
-                          MODE == kModeStepS);
+                          MODE == kModeStepS || CPM);
     constexpr bool KEEPX = (MODE == kModePGS || MODE == kModeStepS);  // x kept in xs
     constexpr bool DOT = (STP || SCR || MODE == kModePow || MODE == kModePowG);
-    constexpr bool ACC = !(MODE == kModeCorr || MODE == kModeStep || MODE == kModeStepS || MODE == kModePowG);
-    constexpr bool COEF = (MODE == kModeAx || MODE == kModeAg);      // partial += A c, c staged per column
+    constexpr bool ACC = !(MODE == kModeCorr || MODE == kModeStep || MODE == kModeStepS || MODE == kModePowG ||
+                           MODE == kModeStepCP);
+    constexpr bool COEF = (MODE == kModeAx || MODE == kModeAg || MODE == kModeAxS);  // partial += A c, c staged
     // residual rows staged in LDS (shapes too large for it to stay in registers)
     constexpr bool RLDS = DOT && two_pass_shape(TPC, R);
     constexpr int NW = TPC / 64;
@@ -76,7 +78,9 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     const long long lda = I.lda;
     const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
     const int* __restrict__ list = (MODE == kModeFold) ? I.fidx : I.idx;
-    const double eta = STP ? S.step : 0.0;
+    // PG ascends along A^T r; Chambolle-Pock descends along A^T v
+    const double eta = STP ? (CPM ? -S.step : S.step) : 0.0;
+    const double* __restrict__ rsrc = CPM ? I.r2 : I.r;
     const double tnorm_c = SCR ? S.tnorm : 0.0;
 
     bool rowok[R];
@@ -95,7 +99,7 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int row = (k * TPC + L) * V + e;
-                const double v = (row < m) ? I.r[row] : 0.0;
+                const double v = (row < m) ? rsrc[row] : 0.0;
                 if constexpr (RLDS) s_r[(k * V + e) * TPC + L] = v; else rl[k * V + e] = v;
             }
     }
@@ -170,6 +174,8 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
             s_x[k] = I.x[j];
         } else if constexpr (MODE == kModeAg) {
             s_x[k] = I.g[j];
+        } else if constexpr (MODE == kModeAxS) {
+            s_x[k] = I.xs[j];
         } else if constexpr (MODE == kModeFold) {
             s_x[k] = I.fval[q];
             s_l[k] = I.fdx[q];
@@ -239,9 +245,11 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
             if (vo) {
                 if constexpr (STP) {
                     const double xn = fmin(fmax(xo + eta * tot, lo), uo);
-                    cown = xn;
+                    // Chambolle-Pock multiplies A by the extrapolated point 2 x+ - x
+                    cown = CPM ? 2.0 * xn - xo : xn;
                     if (owner) gstore(I.x + s_j[jo], xn);
                     if (KEEPX && owner) gstore(I.xs + s_j[jo], xo);
+                    if (MODE == kModeStepCP && owner) gstore(I.xs + s_j[jo], cown);
                 }
                 if constexpr (SCR) {
                     if (owner) {
@@ -435,6 +443,9 @@ static hipError_t sweep_launch_t(const LaunchCtx& c, int mode, const Item* items
     case kModePG1: if constexpr (!TWO) { BXS_SW(kModePG1); break; } else { return hipErrorInvalidValue; }
     case kModePow: if constexpr (!TWO) { BXS_SW(kModePow); break; } else { return hipErrorInvalidValue; }
     case kModePGS: if constexpr (!TWO) { BXS_SW(kModePGS); break; } else { return hipErrorInvalidValue; }
+    case kModeCP: if constexpr (!TWO) { BXS_SW(kModeCP); break; } else { return hipErrorInvalidValue; }
+    case kModeStepCP: if constexpr (TWO) { BXS_SW(kModeStepCP); break; } else { return hipErrorInvalidValue; }
+    case kModeAxS: if constexpr (TWO) { BXS_SW(kModeAxS); break; } else { return hipErrorInvalidValue; }
     case kModeStep: if constexpr (TWO) { BXS_SW(kModeStep); break; } else { return hipErrorInvalidValue; }
     case kModeStepS: if constexpr (TWO) { BXS_SW(kModeStepS); break; } else { return hipErrorInvalidValue; }
     case kModePowG: if constexpr (TWO) { BXS_SW(kModePowG); break; } else { return hipErrorInvalidValue; }

@@ -22,7 +22,7 @@ BXS_OK, BXS_ERR_ARG, BXS_ERR_SHAPE, BXS_ERR_NONFINITE, BXS_ERR_BOUNDS, BXS_ERR_D
     BXS_SINGULAR = range(9)
 STATUS_NAMES = {0: "ok", 1: "err_arg", 2: "err_shape", 3: "err_nonfinite", 4: "err_bounds",
                 5: "err_device", 6: "err_nomem", 7: "maxiter", 8: "singular"}
-BXS_PG, BXS_CD = 0, 1
+BXS_PG, BXS_CD, BXS_CP = 0, 1, 2
 BXS_F64, BXS_F32 = 0, 1
 MAX_ROWS = 16384
 T_CHOICES = {"given": 0, "neg_mean_column": 1, "neg_most_correlated": 2, "neg_least_correlated": 3}
@@ -175,7 +175,7 @@ def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, 
     lib = load()
     o = Opts()
     lib.bxs_default_opts(C.byref(o))
-    o.solver = {"pg": BXS_PG, "cd": BXS_CD}[solver] if isinstance(solver, str) else int(solver)
+    o.solver = {"pg": BXS_PG, "cd": BXS_CD, "cp": BXS_CP}[solver] if isinstance(solver, str) else int(solver)
     o.screening = 1 if screening else 0
     o.screen_every = int(screen_every)
     o.max_iter = int(max_iter)
