@@ -487,6 +487,29 @@ def bench_table2(args, device):
     out["speedup"] = round(out["unscreened"]["seconds"] / out["screened"]["seconds"], 3)
     out["note"] = ("A is 1000 x 3000 (24 MB): an iteration is a few microseconds of HBM traffic plus a fixed "
                    "launch cost, so screening trims only the traffic part")
+    # the primal-dual rows of Tab. 2: Chambolle-Pock, n = 500 ... 3000
+    paper_pd = {500: (0.26, 0.08), 1000: (0.84, 0.19), 2000: (2.92, 0.59), 3000: (5.20, 0.95)}
+    rows = []
+    for n in (500, 1000, 2000, 3000):
+        Q = W.table2_bvls(0, 1000, n)
+        A, y, l, u = _upload(Q, device)
+        row = {"n": n, "paper_baseline_s": paper_pd[n][0], "paper_screened_s": paper_pd[n][1]}
+        for screening in (True, False):
+            kw = dict(solver="cp", screening=screening, screen_every=10, eps_gap=1e-6, max_iter=2000000)
+            bx.solve_bvls(A, y, l, u, **dict(kw, max_iter=20))
+            _sync()
+            t0 = time.perf_counter()
+            x, sat, info = bx.solve_bvls(A, y, l, u, **kw)
+            _sync()
+            dt = time.perf_counter() - t0
+            row["screened" if screening else "unscreened"] = {
+                "seconds": round(dt, 4), "iters": info["iters"], "status": info["status_name"],
+                "n_screened": info["n_lower"] + info["n_upper"],
+                "mean_preserved_fraction": round(info["col_iters"] / max(info["iters"], 1) / n, 4)}
+        row["speedup"] = round(row["unscreened"]["seconds"] / row["screened"]["seconds"], 3)
+        log(f"[table2] CP n={n}: {row}")
+        rows.append(row)
+    out["chambolle_pock"] = rows
     return out
 
 

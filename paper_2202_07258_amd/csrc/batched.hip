@@ -722,20 +722,26 @@ struct DgemmArgs {
     double alpha, beta;
     const int* cols;
     const int* ncols;
+    double* splitk;
+    int kparts, kslice;
 };
 hipError_t launch_dgemm(int ta, int tb, const DgemmArgs& a, hipStream_t s);   // dgemm.hip
+size_t dgemm_splitk_doubles();
 size_t dgemv_partial_doubles(long m, long n);
 hipError_t launch_dgemv_normal(const double* A, long long lda, int m, int n, const double* v, double* w,
                                double* partial, double* out, hipStream_t s);
 
-// C[M x N] = alpha op(A) op(B) + beta Cin (Cin = C when nullptr), FP64
-static DgemmArgs gemm_args(const double* A, long long lda, const double* B, long long ldb, double* C, long long ldc,
-                           long M, long N, long K, double alpha, double beta, const double* Cin = nullptr,
-                           long long ldcin = 0, const int* cols = nullptr, const int* ncols = nullptr)
+// C[M x N] = alpha op(A) op(B) + beta Cin (Cin = C when nullptr), FP64;
+// `splitk` (dgemm_splitk_doubles() doubles) lets small products split K
+static DgemmArgs gemm_args(double* splitk, const double* A, long long lda, const double* B, long long ldb, double* C,
+                           long long ldc, long M, long N, long K, double alpha, double beta,
+                           const double* Cin = nullptr, long long ldcin = 0, const int* cols = nullptr,
+                           const int* ncols = nullptr)
 {
     DgemmArgs a;
     a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc; a.Cin = Cin; a.ldcin = ldcin;
     a.M = (int)M; a.N = (int)N; a.K = (int)K; a.alpha = alpha; a.beta = beta; a.cols = cols; a.ncols = ncols;
+    a.splitk = splitk; a.kparts = 1; a.kslice = (int)K;
     return a;
 }
 
@@ -766,6 +772,7 @@ size_t batched_workspace_bytes(long m, long n, long B, int iter_precision)
     }
     b += al(sizeof(double) * (4 * (size_t)n + m + 16));   // cn, w, power vectors, scalars
     b += al(sizeof(double) * dgemv_partial_doubles(m, n));  // power-iteration partial products
+    b += al(sizeof(double) * dgemm_splitk_doubles());        // split-K slices of small GEMMs
     b += al(sizeof(BState) * B);
     b += al(sizeof(int) * (B + 16));
     return b + 1024;
@@ -817,6 +824,7 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     double* pav = sc + 3 * n;        // m (A v)
     double* scal = sc + 3 * n + m;   // [0] tnorm, [1] lambda
     double* gv_part = (double*)take(sizeof(double) * dgemv_partial_doubles(m, n));
+    double* skw = (double*)take(sizeof(double) * dgemm_splitk_doubles());
     BState* st = (BState*)take(sizeof(BState) * B);
     int* ints = (int*)take(sizeof(int) * (B + 16));
     int* act = ints;
@@ -881,8 +889,9 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
     // `act` and its device count; hnact bounds the count from the host)
     int hnact = (int)B;
     auto residual_and_corr = [&]() -> bxs_status {
-        BXS_HIPB(launch_dgemm(0, 0, gemm_args(A64, m, X64, n, R64, m, m, hnact, n, -1.0, 1.0, Y64, m, act, nact), s));
-        BXS_HIPB(launch_dgemm(1, 0, gemm_args(A64, m, R64, m, G64, n, n, hnact, m, 1.0, 0.0, nullptr, 0, act, nact), s));
+        BXS_HIPB(launch_dgemm(0, 0, gemm_args(skw, A64, m, X64, n, R64, m, m, hnact, n, -1.0, 1.0, Y64, m, act, nact), s));
+        BXS_HIPB(launch_dgemm(1, 0, gemm_args(skw, A64, m, R64, m, G64, n, n, hnact, m, 1.0, 0.0, nullptr, 0, act, nact),
+                              s));
         return BXS_OK;
     };
 
@@ -1233,6 +1242,7 @@ size_t adjoint_workspace_bytes(long m, long n, long B)
     b += al(sizeof(double) * 4);           // ||A||_F^2
     b += al(sizeof(int) * B);              // done
     b += al(sizeof(int) * 16);
+    b += al(sizeof(double) * dgemm_splitk_doubles());   // split-K slices of small GEMMs
     return b + 1024;
 }
 
@@ -1283,6 +1293,7 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     double* frob = (double*)take(sizeof(double) * 4);
     int* done = (int*)take(sizeof(int) * B);
     int* counters = (int*)take(sizeof(int) * 16);
+    double* skw = (double*)take(sizeof(double) * dgemm_splitk_doubles());
 
     const int grid = 2048;
     if (a_dtype == BXS_F32)
@@ -1306,8 +1317,8 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     long it = 0;
     for (; it < maxit; ++it) {
         // S = mask(A^T (A P))
-        BXS_HIPB(launch_dgemm(0, 0, gemm_args(A64, m, P, n, Q, m, m, B, n, 1.0, 0.0), s));
-        BXS_HIPB(launch_dgemm(1, 0, gemm_args(A64, m, Q, m, S, n, n, B, m, 1.0, 0.0), s));
+        BXS_HIPB(launch_dgemm(0, 0, gemm_args(skw, A64, m, P, n, Q, m, m, B, n, 1.0, 0.0), s));
+        BXS_HIPB(launch_dgemm(1, 0, gemm_args(skw, A64, m, Q, m, S, n, n, B, m, 1.0, 0.0), s));
         k_adj_mask<<<grid, 256, 0, s>>>(S, F, (long long)n * B);
         k_adj_dot2<<<(int)B, 256, 0, s>>>(P, S, (int)n, pq, pp);
         k_adj_step<<<grid, 256, 0, s>>>(S, F, rs, pq, pp, frob, (int)m, done, V, Rc, P, (int)n, (int)B);
@@ -1326,16 +1337,16 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     k_adj_zero_broken<<<grid, 256, 0, s>>>(V, done, (int)n, (int)B);
     BXS_HIPB(hipGetLastError());
     // dL/dY = A V
-    BXS_HIPB(launch_dgemm(0, 0, gemm_args(A64, m, V, n, dY, lddy, m, B, n, 1.0, 0.0), s));
+    BXS_HIPB(launch_dgemm(0, 0, gemm_args(skw, A64, m, V, n, dY, lddy, m, B, n, 1.0, 0.0), s));
     if (dA) {
         // R = Y - A X, then dL/dA = R V^T - (dL/dY) X^T
-        BXS_HIPB(launch_dgemm(0, 0, gemm_args(A64, m, Xc, n, R, m, m, B, n, -1.0, 1.0, Y, ldy), s));
-        BXS_HIPB(launch_dgemm(0, 1, gemm_args(R, m, V, n, dA, ldda, m, n, B, 1.0, 0.0), s));
-        BXS_HIPB(launch_dgemm(0, 1, gemm_args(dY, lddy, Xc, n, dA, ldda, m, n, B, -1.0, 1.0), s));
+        BXS_HIPB(launch_dgemm(0, 0, gemm_args(skw, A64, m, Xc, n, R, m, m, B, n, -1.0, 1.0, Y, ldy), s));
+        BXS_HIPB(launch_dgemm(0, 1, gemm_args(skw, R, m, V, n, dA, ldda, m, n, B, 1.0, 0.0), s));
+        BXS_HIPB(launch_dgemm(0, 1, gemm_args(skw, dY, lddy, Xc, n, dA, ldda, m, n, B, -1.0, 1.0), s));
     }
     if (dl) {
         // S = A^T dL/dY (S is free once the CG is done)
-        BXS_HIPB(launch_dgemm(1, 0, gemm_args(A64, m, dY, lddy, S, n, n, B, m, 1.0, 0.0), s));
+        BXS_HIPB(launch_dgemm(1, 0, gemm_args(skw, A64, m, dY, lddy, S, n, n, B, m, 1.0, 0.0), s));
         k_adj_bound_grad<<<grid, 256, 0, s>>>(dX, ldg, S, F, (int)n, (int)B, dl, lddl);
         BXS_HIPB(hipGetLastError());
     }

@@ -29,6 +29,8 @@
 // and the panel of op(B) that a run of tiles shares stays in one XCD's L2.
 #include "dev_common.h"
 
+#include <algorithm>
+
 namespace bxs {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -46,9 +48,15 @@ struct DgemmArgs {
     double alpha, beta;
     const int* cols;        // logical -> physical column of op(B) and C, or nullptr (TB = 0 only)
     const int* ncols;       // device count of logical columns in use (<= N), or nullptr
+    double* splitk;         // scratch of kDgemmSplitScratch doubles for split-K launches, or nullptr
+    int kparts;             // set by the launcher: K split into this many slices (1: no split)
+    int kslice;             // K per slice (multiple of the K step)
 };
 
 constexpr int kGM = 128, kGN = 128, kGK = 16, kGPad = 2;
+// split-K scratch: at most 256 (tile, slice) pairs of 128 x 128 doubles
+constexpr size_t kDgemmSplitScratch = (size_t)256 * kGM * kGN;
+size_t dgemm_splitk_doubles() { return kDgemmSplitScratch; }
 
 template <int TA, int TB>
 __global__ __launch_bounds__(256, 2)
@@ -63,6 +71,10 @@ void k_dgemm(DgemmArgs p)
     const int tilesM = (p.M + kGM - 1) / kGM;
     const int tilesN = (p.N + kGN - 1) / kGN;
     const int total = tilesM * tilesN;
+    // split-K: blockIdx.y is the K slice; its partial tile goes to the scratch
+    const int ks = blockIdx.y;
+    const int kbeg = ks * p.kslice;
+    const int kend = min(p.K, kbeg + p.kslice);
     // XCD-aware renumbering: workgroup b runs on XCD b % 8
     const int b = blockIdx.x;
     const int per = (total + 7) / 8;
@@ -91,7 +103,7 @@ void k_dgemm(DgemmArgs p)
                 const int k = c >> 6, i = (c & 63) * 2;
                 const int gk = k0 + k, gi = i0 + i;
                 const double* src = p.A + (long long)gk * p.lda + gi;
-                const bool kin = gk < p.K;
+                const bool kin = gk < kend;
                 ra[2 * q] = (kin && gi < p.M) ? src[0] : 0.0;
                 ra[2 * q + 1] = (kin && gi + 1 < p.M) ? src[1] : 0.0;
             } else {                                  // k contiguous: chunk = (i, k pair)
@@ -99,20 +111,20 @@ void k_dgemm(DgemmArgs p)
                 const int gk = k0 + k, gi = i0 + i;
                 const double* src = p.A + (long long)gi * p.lda + gk;
                 const bool iin = gi < p.M;
-                ra[2 * q] = (iin && gk < p.K) ? src[0] : 0.0;
-                ra[2 * q + 1] = (iin && gk + 1 < p.K) ? src[1] : 0.0;
+                ra[2 * q] = (iin && gk < kend) ? src[0] : 0.0;
+                ra[2 * q + 1] = (iin && gk + 1 < kend) ? src[1] : 0.0;
             }
             if (TB == 0) {                            // k contiguous: chunk = (j, k pair)
                 const int j = c >> 3, k = (c & 7) * 2;
                 const int gk = k0 + k, pj = sCol[j];
                 const double* src = p.B + (long long)(pj < 0 ? 0 : pj) * p.ldb + gk;
-                rb[2 * q] = (pj >= 0 && gk < p.K) ? src[0] : 0.0;
-                rb[2 * q + 1] = (pj >= 0 && gk + 1 < p.K) ? src[1] : 0.0;
+                rb[2 * q] = (pj >= 0 && gk < kend) ? src[0] : 0.0;
+                rb[2 * q + 1] = (pj >= 0 && gk + 1 < kend) ? src[1] : 0.0;
             } else {                                  // j contiguous: chunk = (k, j pair)
                 const int k = c >> 6, j = (c & 63) * 2;
                 const int gk = k0 + k, gj = j0 + j;
                 const double* src = p.B + (long long)gk * p.ldb + gj;
-                const bool kin = gk < p.K;
+                const bool kin = gk < kend;
                 rb[2 * q] = (kin && gj < nlim) ? src[0] : 0.0;
                 rb[2 * q + 1] = (kin && gj + 1 < nlim) ? src[1] : 0.0;
             }
@@ -150,12 +162,12 @@ void k_dgemm(DgemmArgs p)
         for (int c = 0; c < 4; ++c) acc[a][c] = d4{0.0, 0.0, 0.0, 0.0};
 
     const int kq = lane >> 4, kr = lane & 15;        // fragment lane -> (k within 4, row/col within 16)
-    const int nk = (p.K + kGK - 1) / kGK;
-    load_k(0);
+    const int nk = (kend - kbeg + kGK - 1) / kGK;
+    load_k(kbeg);
     store_k();
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) load_k((kt + 1) * kGK);
+        if (kt + 1 < nk) load_k(kbeg + (kt + 1) * kGK);
 #pragma unroll
         for (int ks = 0; ks < kGK / 4; ++ks) {
             double fa[4], fb[4];
@@ -179,6 +191,24 @@ void k_dgemm(DgemmArgs p)
 
     // accumulator register r of lane l holds row 4 r + l / 16 of the MFMA result, i.e.
     // C(ii = l % 16, jj = 4 r + l / 16) of its block (layout checked on gfx950)
+    if (p.kparts > 1) {
+        // split-K: the slice's partial tile, logical columns, dense M x N per slice
+        double* part = p.splitk + (size_t)ks * p.M * p.N;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int gi = i0 + wm * 64 + a * 16 + kr;
+            if (gi >= p.M) continue;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int jl = wn * 64 + c * 16 + 4 * r + kq;
+                    if (sCol[jl] < 0) continue;
+                    part[(size_t)(j0 + jl) * p.M + gi] = acc[a][c][r];
+                }
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int gi = i0 + wm * 64 + a * 16 + kr;
@@ -203,17 +233,59 @@ void k_dgemm(DgemmArgs p)
     }
 }
 
-hipError_t launch_dgemm(int ta, int tb, const DgemmArgs& a, hipStream_t s)
+// Split-K reduction: C = alpha * (sum of the slices in order) + beta * Cin
+__global__ __launch_bounds__(256)
+void k_dgemm_splitk_sum(DgemmArgs p)
 {
-    if (a.M <= 0 || a.N <= 0) return hipSuccess;
-    if (a.cols && tb != 0) return hipErrorInvalidValue;
+    const int nlim = p.ncols ? min(p.N, *p.ncols) : p.N;
+    const long long tot = (long long)p.M * nlim;
+    const size_t slice = (size_t)p.M * p.N;
+    for (long long k = blockIdx.x * 256LL + threadIdx.x; k < tot; k += (long long)gridDim.x * 256) {
+        const int i = (int)(k % p.M);
+        const int j = (int)(k / p.M);
+        double v = 0.0;
+        for (int s = 0; s < p.kparts; ++s) v += p.splitk[s * slice + (size_t)j * p.M + i];
+        const int pj = p.cols ? p.cols[j] : j;
+        double* dst = p.C + (long long)pj * p.ldc + i;
+        const double w = p.alpha * v;
+        if (p.beta != 0.0) {
+            const double cin = p.Cin ? p.Cin[(long long)pj * p.ldcin + i] : *dst;
+            *dst = fma(p.beta, cin, w);
+        } else {
+            *dst = w;
+        }
+    }
+}
+
+hipError_t launch_dgemm(int ta, int tb, const DgemmArgs& a0, hipStream_t s)
+{
+    if (a0.M <= 0 || a0.N <= 0) return hipSuccess;
+    if (a0.cols && tb != 0) return hipErrorInvalidValue;
+    DgemmArgs a = a0;
     const int tiles = ((a.M + kGM - 1) / kGM) * ((a.N + kGN - 1) / kGN);
-    const dim3 grid(tiles), block(256);
+    // Fewer tiles than the chip's 256 CUs: split K so that about 256
+    // workgroups run, each slice at least 4 K steps, the slices summed in a
+    // fixed order afterwards (deterministic).  tiles * parts <= 256 keeps the
+    // slices within the scratch.
+    a.kparts = 1;
+    a.kslice = a.K;
+    if (a.splitk && tiles < 128) {
+        const int maxp = std::max(1, 256 / tiles);
+        const int steps = (a.K + kGK - 1) / kGK;
+        const int parts = std::min(maxp, std::max(1, steps / 4));
+        if (parts > 1) {
+            const int per = (steps + parts - 1) / parts;
+            a.kslice = per * kGK;
+            a.kparts = (steps + per - 1) / per;
+        }
+    }
+    const dim3 grid(tiles, a.kparts), block(256);
     if (ta == 0 && tb == 0) k_dgemm<0, 0><<<grid, block, 0, s>>>(a);
     else if (ta == 1 && tb == 0) k_dgemm<1, 0><<<grid, block, 0, s>>>(a);
     else if (ta == 0 && tb == 1) k_dgemm<0, 1><<<grid, block, 0, s>>>(a);
     else if (ta == 1 && tb == 1) k_dgemm<1, 1><<<grid, block, 0, s>>>(a);
     else return hipErrorInvalidValue;
+    if (a.kparts > 1) k_dgemm_splitk_sum<<<1024, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
