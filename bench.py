@@ -180,6 +180,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companion", action="store_true")
     ap.add_argument("--no-unscreened", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16-storage leg of the C2 run")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="bound the oracle baseline to this many iterations (0: full solve)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "table2", "fig1", "sweep"],
@@ -190,6 +191,9 @@ def main():
     ap.add_argument("--c3-rhs", type=int, default=8192)
     ap.add_argument("--c3-iters", type=int, default=200)
     ap.add_argument("--c4-count", type=int, default=2048)
+    ap.add_argument("--c4-planted", action="store_true", help="C4-pl: the planted, non-degenerate companion")
+    ap.add_argument("--c4-oracle-budget", type=float, default=60.0,
+                    help="host seconds for the C4 oracle sample (smallest instances first)")
     ap.add_argument("--c5-iters", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling rocprofv3 byte counters) and exit")
@@ -297,6 +301,29 @@ def main():
         del devq
         torch.cuda.empty_cache()
 
+    if not args.no_bf16:
+        # precision tiering of the storage: the same instance with A rounded to
+        # bfloat16 (half the bytes per sweep; every element still promoted
+        # exactly to FP64, so the solve is exact for the stored problem)
+        log("[bench] C2 with bfloat16 storage of A")
+        Ab = dev[0].to(torch.bfloat16)
+        devb = (Ab, dev[1], dev[2], dev[3])
+        dtb, _, (xb, sb, ib) = time_solves(devb, args.steps, args.warmup, screening=True, eps_gap=1e-6,
+                                           screen_every=10)
+        _, infb, _ = time_solves(devb, 1, 0, screening=True, eps_gap=1e-6, screen_every=10, profile=True)
+        rb = sweep_roofline(infb, m, n, 2)
+        if rb:
+            rb["traffic"] = None
+            rb["kernel"] = rb["kernel"].replace("k_sweep<float,", "k_sweep<__bf16,").replace(",4,", ",8,", 1)
+        result["c2_bf16_storage"] = {
+            "value": round(args.steps / dtb, 3), "unit": "solves/s", "ms_per_step": round(1e3 * dtb / args.steps, 3),
+            "iters": ib["iters"], "gap": ib["gap"], "status": ib["status_name"],
+            "speedup_vs_fp32_storage": round((args.steps / dtb) / value, 3),
+            "max_abs_diff_x_vs_fp32_storage": float((xb - x).abs().max()),
+            "roofline": rb}
+        del Ab, devb
+        torch.cuda.empty_cache()
+
     if not args.no_cpu_baseline:
         log("[bench] FP64 oracle on the host (cpu baseline)")
         dtc, res, cores = cpu_baseline(P, args.cpu_iters or None)
@@ -310,6 +337,17 @@ def main():
                       f"{info['iters']}-iteration solve")
         result["cpu_baseline"] = {"value": round(val, 5), "unit": "solves/s", "cores": cores, "kind": "oracle",
                                   "sample": sample, "seconds": round(dtc, 2)}
+        # the same oracle on one thread, on a bounded sample (30 PG iterations,
+        # scaled to the solve's iteration count)
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                dt1, res1, _ = cpu_baseline(P, 30)
+            result["cpu_baseline"]["value_1_thread"] = round((res1.iters / dt1) / max(info["iters"], 1), 5)
+            result["cpu_baseline"]["sample_1_thread"] = (f"first {res1.iters} oracle PG iterations on one thread, "
+                                                         f"scaled to the {info['iters']}-iteration solve")
+        except ImportError:
+            pass
         # the oracle's own FP64 gap (eq. Dual_Gap) at the GPU's returned x
         from oracle import boxls as ob
         A64 = P.A64()

@@ -66,7 +66,11 @@ typedef enum {
  * tau = sigma = opts->step or 1 / (1.05 sqrt(L_est)); the screening test uses
  * the residual dual point of Sec. 4 like the other solvers) */
 typedef enum { BXS_PG = 0, BXS_CD = 1, BXS_CP = 2 } bxs_solver;
-typedef enum { BXS_F64 = 0, BXS_F32 = 1 } bxs_dtype;  /* storage type of A                               */
+/* Storage type of A.  Every element is promoted exactly to FP64 before it is
+ * used, so the problem solved is the one the stored values define; BXS_BF16
+ * (bfloat16: 8-bit significand) halves the bytes of FP32 storage for the
+ * single-problem and uneven-batch solvers (not the shared-matrix solver). */
+typedef enum { BXS_F64 = 0, BXS_F32 = 1, BXS_BF16 = 2 } bxs_dtype;
 /* Arithmetic of the primal iterations of the batched shared-matrix solver
  * (the certification pass is FP64 in both cases). */
 typedef enum { BXS_ITER_F64 = 0, BXS_ITER_BF16X3 = 1 } bxs_iter_precision;
@@ -174,6 +178,11 @@ typedef struct {
                            every timed launch); measured once per process and device    */
     long   t_column;    /* column whose negative is t (BXS_T_NEG_MOST/LEAST_CORRELATED),
                            else -1                                                      */
+    double dual;        /* primal - gap: the dual objective of the last pass (eq. Dual_obj),
+                           a certified lower bound of the optimal value                   */
+    double max_margin;  /* last pass: rounding margin of a correlation a_j^T theta per unit
+                           ||a_j|| (the band inside which no coordinate is screened)       */
+    long   n_free;      /* coordinates strictly inside the box at the returned x           */
 } bxs_info;
 
 /* Fill *opts with defaults: PG, screening on, K = 10, max_iter = 100000,

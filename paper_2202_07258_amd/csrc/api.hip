@@ -271,8 +271,8 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps, int
     P.sizes.resize(count);
     long total_items = 0;
     size_t inst_bytes = 0;
-    const size_t esz = dtype == BXS_F32 ? 4 : 8;
-    const int vecw = dtype == BXS_F32 ? 4 : 2;
+    const size_t esz = dtype == BXS_BF16 ? 2 : (dtype == BXS_F32 ? 4 : 8);
+    const int vecw = (int)(16 / esz);                   // elements per 16-byte load
     P.vec = 1;
     for (long i = 0; i < count; ++i) {
         const InstSpec& s = P.specs[i];
@@ -819,6 +819,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         slot = nxt;
     }
     if (!noalloc) BXS_HIP(hipEventRecord(ev2, stream));
+    BXS_HIP(launch_count_free(c, (int)count));
     BXS_HIP(hipMemcpyAsync(img, D.st, sbytes, hipMemcpyDeviceToHost, stream));
     std::vector<bxs_pass_record> hrec;
     long nrec = 0;
@@ -871,6 +872,9 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             f.sweep_launches = sweep_launches;
             f.event_overhead_ms = ev_over;
             f.t_column = P.tdir ? S.t_column : -1;
+            f.dual = S.primal - S.gap;
+            f.max_margin = S.margin;
+            f.n_free = S.n_free;
         }
     }
     if (history && count == 1) {
@@ -1017,7 +1021,8 @@ static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const 
     g_last_error.clear();
     bxs_status s = check_opts(opts);
     if (s != BXS_OK) return s;
-    if (a_dtype != BXS_F64 && a_dtype != BXS_F32) return fail(BXS_ERR_ARG, "unknown a_dtype %d", a_dtype);
+    if (a_dtype != BXS_F64 && a_dtype != BXS_F32 && a_dtype != BXS_BF16)
+        return fail(BXS_ERR_ARG, "unknown a_dtype %d", a_dtype);
     for (size_t i = 0; i < specs.size(); ++i) {
         s = check_spec(specs[i], (long)i);
         if (s != BXS_OK) return s;

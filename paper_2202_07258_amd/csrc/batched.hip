@@ -700,6 +700,20 @@ void k_b_compact_rhs(int B, const BState* __restrict__ st, int* __restrict__ act
     }
 }
 
+// coordinates with x_jb > 0 per right-hand side (BState::pad0), one workgroup each
+__global__ __launch_bounds__(256)
+void k_b_count_free(const double* __restrict__ X64, int n, BState* __restrict__ st)
+{
+    __shared__ int sh[4];
+    const long long b = blockIdx.x;
+    int c = 0;
+    for (int j = threadIdx.x; j < n; j += 256) c += X64[j + b * n] > 0.0 ? 1 : 0;
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) st[b].pad0 = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
 __global__ void k_b_iota(int* __restrict__ act, int B, int* __restrict__ nact)
 {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) act[b] = b;
@@ -1028,6 +1042,7 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
         }
     }
     k_b_output<<<grid, 256, 0, s>>>(X64, X, ldx, (int)n, (int)B);
+    k_b_count_free<<<(int)B, 256, 0, s>>>(X64, (int)n, st);
     BXS_HIPB(hipEventRecord(e2, s));
     std::vector<BState> hs(B);
     BXS_HIPB(hipMemcpyAsync(hs.data(), st, sizeof(BState) * B, hipMemcpyDeviceToHost, s));
@@ -1052,6 +1067,9 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
             f.sweep_ms = gemm_ms;
             f.sweep_launches = gemm_pairs;
             f.event_overhead_ms = ev_over;
+            f.t_column = -1;
+            f.dual = S.primal - S.gap;
+            f.n_free = S.pad0;       // coordinates strictly inside the box (x_jb > 0)
         }
     }
     return worst;

@@ -82,6 +82,8 @@ struct State {
     double ynorm;           // upper bound of ||y||_2
     double mass_screened;   // sum over screened j of |x_j| * cn_j
     int t_column;           // column picked for t by the library (bxs_translation), or -1
+    int n_free;             // coordinates strictly inside the box at exit
+    double margin;          // last pass: rounding margin of a correlation per unit column norm
 };
 
 // Per-item scalars written by the correlation sweep for the screening pass:
@@ -274,6 +276,7 @@ hipError_t launch_set_step(const LaunchCtx& c, int count, double step);
 hipError_t launch_lanczos(const LaunchCtx& c, int count, int k, int last, int cp = 0);
 // Chambolle-Pock start: v = sigma (A x0 - y') / (1 + sigma) = -sigma r / (1 + sigma) into r2
 hipError_t launch_cp_init(const LaunchCtx& c, int count);
+hipError_t launch_count_free(const LaunchCtx& c, int count);
 // host_done: pinned host word that receives the stop counter at the end of
 // the pass (nullptr: the caller copies it itself); host_gap: pinned host
 // double that receives the gap of instance 0 (single-instance calls), or

@@ -173,6 +173,7 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[CBI], int lane
 // for the update instead of keeping all converted values live in between.
 __device__ __forceinline__ float opaque(float v) { asm volatile("" : "+v"(v)); return v; }
 __device__ __forceinline__ double opaque(double v) { return v; }
+__device__ __forceinline__ __bf16 opaque(__bf16 v) { return v; }
 
 template <int CBI>
 __device__ __forceinline__ int col_of_lane(int lane) { return (lane >> (6 - Log2C<CBI>::v)) & (CBI - 1); }

@@ -636,7 +636,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
                 rc.iters = iters; rc.n_active = nA; rc.gap = G; rc.radius = rad;
                 rc.eps = eps; rc.primal = primal; rc.n_screened = 0;
             }
-            S.gap = G; S.radius = rad; S.eps = eps; S.primal = primal;
+            S.gap = G; S.radius = rad; S.eps = eps; S.primal = primal; S.margin = e_g + gw * eps * tnorm; S.margin = e_g + gw * eps * tnorm;
             S.t_valid = fallback ? 0 : 1;
             S.passes = passes + 1;
             S.n_fold = 0;
@@ -758,6 +758,28 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
             for (int i = tid; i < m; i += NT) I.r[i] = I.r2[i];
         }
     }
+}
+
+// Coordinates strictly inside the box at the returned iterate, one workgroup
+// per instance (reported with the solve).
+__global__ __launch_bounds__(256)
+void k_count_free(const Inst* __restrict__ insts, State* __restrict__ st)
+{
+    __shared__ double sh[4];
+    const Inst& I = insts[blockIdx.x];
+    double c = 0.0;
+    for (int j = threadIdx.x; j < I.n; j += 256) {
+        const double xj = I.x[j];
+        c += (xj > lo_of(I.l, j) && xj < up_of(I.u, j)) ? 1.0 : 0.0;
+    }
+    c = block_sum<256>(c, sh);
+    if (threadIdx.x == 0) st[blockIdx.x].n_free = (int)c;
+}
+
+hipError_t launch_count_free(const LaunchCtx& c, int count)
+{
+    k_count_free<<<dim3(count), dim3(256), 0, c.stream>>>(c.insts, c.st);
+    return hipGetLastError();
 }
 
 // One workgroup per instance.  With host_done set, the last workgroup to
@@ -914,12 +936,24 @@ BXS_SWEEP_PART_DECL(sweep_f64v_1)
 BXS_SWEEP_PART_DECL(sweep_f64v_2)
 BXS_SWEEP_PART_DECL(sweep_f32s)
 BXS_SWEEP_PART_DECL(sweep_f64s)
+BXS_SWEEP_PART_DECL(sweep_bf16v_0)
+BXS_SWEEP_PART_DECL(sweep_bf16v_1)
+BXS_SWEEP_PART_DECL(sweep_bf16v_2)
+BXS_SWEEP_PART_DECL(sweep_bf16s)
 #undef BXS_SWEEP_PART_DECL
 
 hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items, int first)
 {
     if (n_items <= 0) return hipSuccess;
     if (variant < 0 || variant >= kNumVariants) return hipErrorInvalidValue;
+    if (c.dtype == BXS_BF16) {
+        if (!c.vec) return sweep_bf16s(c, variant, mode, items, n_items, first);
+        switch (variant % kSweepParts) {
+        case 0: return sweep_bf16v_0(c, variant, mode, items, n_items, first);
+        case 1: return sweep_bf16v_1(c, variant, mode, items, n_items, first);
+        default: return sweep_bf16v_2(c, variant, mode, items, n_items, first);
+        }
+    }
     if (c.dtype == BXS_F32) {
         if (!c.vec) return sweep_f32s(c, variant, mode, items, n_items, first);
         switch (variant % kSweepParts) {
@@ -963,6 +997,9 @@ static hipError_t cd_dispatch_v(const LaunchCtx& c, int bucket, const int* list,
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps)
 {
     if (n_list <= 0) return hipSuccess;
+    if (c.dtype == BXS_BF16)
+        return c.vec ? cd_dispatch_v<__bf16, 8>(c, bucket, inst_list, n_list, sweeps)
+                     : cd_dispatch_v<__bf16, 1>(c, bucket, inst_list, n_list, sweeps);
     if (c.dtype == BXS_F32)
         return c.vec ? cd_dispatch_v<float, 4>(c, bucket, inst_list, n_list, sweeps)
                      : cd_dispatch_v<float, 1>(c, bucket, inst_list, n_list, sweeps);
@@ -996,7 +1033,10 @@ hipError_t launch_colstats(const LaunchCtx& c, int bucket, const Item* items, in
     (void)bucket;
     if (n_items <= 0) return hipSuccess;
     const dim3 g(n_items), b(256);
-    if (c.dtype == BXS_F32) {
+    if (c.dtype == BXS_BF16) {
+        if (c.vec) k_colstats<__bf16, 8><<<g, b, 0, c.stream>>>(c.insts, c.st, items);
+        else k_colstats<__bf16, 1><<<g, b, 0, c.stream>>>(c.insts, c.st, items);
+    } else if (c.dtype == BXS_F32) {
         if (c.vec) k_colstats<float, 4><<<g, b, 0, c.stream>>>(c.insts, c.st, items);
         else k_colstats<float, 1><<<g, b, 0, c.stream>>>(c.insts, c.st, items);
     } else {

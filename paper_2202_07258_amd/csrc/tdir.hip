@@ -149,14 +149,17 @@ hipError_t launch_tdir(const LaunchCtx& c, int choice, long m, long n, double* s
     double* s = partial + (size_t)m * chunks;
     double* score = s + m;
     const dim3 g1((unsigned)((m + 255) / 256), (unsigned)chunks);
-    if (c.dtype == BXS_F32) k_tdir_colsum<float><<<g1, 256, 0, c.stream>>>(c.insts, partial);
+    if (c.dtype == BXS_BF16) k_tdir_colsum<__bf16><<<g1, 256, 0, c.stream>>>(c.insts, partial);
+    else if (c.dtype == BXS_F32) k_tdir_colsum<float><<<g1, 256, 0, c.stream>>>(c.insts, partial);
     else k_tdir_colsum<double><<<g1, 256, 0, c.stream>>>(c.insts, partial);
     k_tdir_rowsum<<<(unsigned)((m + 255) / 256), 256, 0, c.stream>>>(c.insts, partial, chunks, s);
     if (choice != BXS_T_NEG_MEAN_COLUMN) {
-        if (c.dtype == BXS_F32) k_tdir_score<float><<<(unsigned)((n + 3) / 4), 256, 0, c.stream>>>(c.insts, s, score);
+        if (c.dtype == BXS_BF16) k_tdir_score<__bf16><<<(unsigned)((n + 3) / 4), 256, 0, c.stream>>>(c.insts, s, score);
+        else if (c.dtype == BXS_F32) k_tdir_score<float><<<(unsigned)((n + 3) / 4), 256, 0, c.stream>>>(c.insts, s, score);
         else k_tdir_score<double><<<(unsigned)((n + 3) / 4), 256, 0, c.stream>>>(c.insts, s, score);
     }
-    if (c.dtype == BXS_F32) k_tdir_pick<float><<<1, 1024, 0, c.stream>>>(c.insts, s, score, choice, t, picked);
+    if (c.dtype == BXS_BF16) k_tdir_pick<__bf16><<<1, 1024, 0, c.stream>>>(c.insts, s, score, choice, t, picked);
+    else if (c.dtype == BXS_F32) k_tdir_pick<float><<<1, 1024, 0, c.stream>>>(c.insts, s, score, choice, t, picked);
     else k_tdir_pick<double><<<1, 1024, 0, c.stream>>>(c.insts, s, score, choice, t, picked);
     return hipGetLastError();
 }

@@ -23,7 +23,7 @@ BXS_OK, BXS_ERR_ARG, BXS_ERR_SHAPE, BXS_ERR_NONFINITE, BXS_ERR_BOUNDS, BXS_ERR_D
 STATUS_NAMES = {0: "ok", 1: "err_arg", 2: "err_shape", 3: "err_nonfinite", 4: "err_bounds",
                 5: "err_device", 6: "err_nomem", 7: "maxiter", 8: "singular"}
 BXS_PG, BXS_CD, BXS_CP = 0, 1, 2
-BXS_F64, BXS_F32 = 0, 1
+BXS_F64, BXS_F32, BXS_BF16 = 0, 1, 2
 MAX_ROWS = 16384
 T_CHOICES = {"given": 0, "neg_mean_column": 1, "neg_most_correlated": 2, "neg_least_correlated": 3}
 
@@ -49,7 +49,8 @@ class Info(C.Structure):
                 ("gap", C.c_double), ("primal", C.c_double), ("radius", C.c_double), ("eps", C.c_double),
                 ("step", C.c_double), ("lipschitz", C.c_double), ("ms_setup", C.c_double),
                 ("ms_solve", C.c_double), ("col_iters", C.c_long), ("sweep_ms", C.c_double),
-                ("sweep_launches", C.c_long), ("event_overhead_ms", C.c_double), ("t_column", C.c_long)]
+                ("sweep_launches", C.c_long), ("event_overhead_ms", C.c_double), ("t_column", C.c_long),
+                ("dual", C.c_double), ("max_margin", C.c_double), ("n_free", C.c_long)]
 
 
 class Problem(C.Structure):
@@ -143,13 +144,14 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 def _check_matrix(A: torch.Tensor):
     if not (A.is_cuda and A.dim() == 2):
         raise ValueError("A must be a 2-D tensor on the GPU")
-    if A.dtype not in (torch.float32, torch.float64):
-        raise ValueError("A must be float32 or float64")
+    if A.dtype not in (torch.float32, torch.float64, torch.bfloat16):
+        raise ValueError("A must be float32, float64 or bfloat16")
     m, n = A.shape
     if A.stride(0) != 1 and m > 1:
         raise ValueError("A must be column-major (stride(0) == 1); use colmajor()")
     lda = A.stride(1) if n > 1 else max(m, 1)
-    return m, n, max(lda, m), (BXS_F32 if A.dtype == torch.float32 else BXS_F64)
+    dt = {torch.float32: BXS_F32, torch.float64: BXS_F64, torch.bfloat16: BXS_BF16}[A.dtype]
+    return m, n, max(lda, m), dt
 
 
 def _vec(v: torch.Tensor | None, length: int, name: str):

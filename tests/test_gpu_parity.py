@@ -324,6 +324,20 @@ def test_history_records():
         assert hg["gap"] == pytest.approx(ho["gap"], rel=1e-6, abs=1e-11)
 
 
+def test_info_dual_margin_and_free_count():
+    """info.dual is the dual objective of the last pass (primal - gap, a lower
+    bound of the optimum), info.n_free the count of coordinates strictly
+    inside the box, info.max_margin the correlation margin per unit norm."""
+    P = planted(9, 250, 700)
+    kw = dict(screen_every=10, eps_gap=1e-9, step=step_of(P))
+    xg, sg, info = run_gpu(P, "bvls", **kw)
+    assert info["dual"] == pytest.approx(info["primal"] - info["gap"], rel=1e-15, abs=1e-15)
+    p_star = ob.primal(P.A64(), P.y, P.x_true)
+    assert info["dual"] <= p_star * (1 + 1e-12) + 1e-15
+    assert info["n_free"] == int(np.count_nonzero((xg > P.l) & (xg < P.u)))
+    assert 0.0 < info["max_margin"] < 1e-10
+
+
 def test_device_side_validation():
     import paper_2202_07258_amd as bx
     P = planted(8, 30, 50)
