@@ -265,9 +265,6 @@ def main():
         result["unscreened"] = {"value": round(args.steps / dt0, 3), "unit": "solves/s",
                                 "ms_per_step": round(1e3 * dt0 / args.steps, 3), "iters": info0["iters"],
                                 "speedup_screened": round((args.steps / dt) / (args.steps / dt0), 3)}
-    del dev
-    torch.cuda.empty_cache()
-
     if not args.no_companion:
         log("[bench] planted companion C2-pl (same shape, non-degenerate)")
         Q = W.c2_planted(0)
@@ -322,7 +319,8 @@ def main():
             "max_abs_diff_x_vs_fp32_storage": float((xb - x).abs().max()),
             "roofline": rb}
         del Ab, devb
-        torch.cuda.empty_cache()
+    del dev
+    torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         log("[bench] FP64 oracle on the host (cpu baseline)")

@@ -259,7 +259,9 @@ bxs_status solve_bvls_varbatch(long count, int a_dtype, const bxs_problem* probs
  * smallest default variant that holds its m rows; bxs_set_sweep_variant
  * selects which variant later calls use for a class (v < 0 restores the
  * default).  These settings are process-wide and must not change while a
- * solve is running.  Used by the autotuner, which times the candidates. */
+ * solve is running; they apply to FP32 and FP64 storage (bfloat16 storage
+ * keeps the library's own table).  Used by the autotuner, which times the
+ * candidates. */
 int        bxs_num_sweep_variants(void);
 bxs_status bxs_sweep_variant_info(int v, int* tpc, int* ng, int* rows, int* cbi, int* pd, long* capacity);
 int        bxs_row_class(long m);            /* -1 if m > BXS_MAX_ROWS */

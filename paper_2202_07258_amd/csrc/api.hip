@@ -155,11 +155,17 @@ static int device_cus()
 // four times as many columns (up to 256 MB).
 static int g_variant_pref[kNumDefaultVariants] = {0, 1, 2, 3, 12, 12, 18, 31, 29};
 
-static int choose_variant(long m)
+// bfloat16 storage moves half the bytes per column, so the classes that are
+// latency-limited at 8 rows per thread keep twice the columns in flight
+// (measured on MI355X at 4000 x 16000: 38.9 us per sweep with 4 columns per
+// round against 46.3 us with 2).  Not changed by bxs_set_sweep_variant.
+static const int g_variant_pref_bf16[kNumDefaultVariants] = {0, 1, 2, 3, 12, 10, 10, 31, 29};
+
+static int choose_variant(long m, int dtype = BXS_F32)
 {
     const int cls = default_variant_for_rows(m);
     if (cls < 0) return -1;
-    const int v = g_variant_pref[cls];
+    const int v = (dtype == BXS_BF16) ? g_variant_pref_bf16[cls] : g_variant_pref[cls];
     return (v >= 0 && v < kNumVariants && variant_capacity(v) >= m) ? v : cls;
 }
 
@@ -263,7 +269,7 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps, int
     const long count = (long)P.specs.size();
     const int cus = device_cus();
     P.variant.resize(count);
-    for (long i = 0; i < count; ++i) P.variant[i] = choose_variant(P.specs[i].m);
+    for (long i = 0; i < count; ++i) P.variant[i] = choose_variant(P.specs[i].m, dtype);
     std::vector<int> g = group_targets(P.specs, P.variant, cus);
     P.rec_cap = rec_cap;
     P.lz_steps = lz_steps;
@@ -706,7 +712,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         }
         BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk, pg ? 1 : 0,
                               host_done, (host_done && count == 1) ? hgap + slot : nullptr,
-                              (host_done && poll) ? hseq : nullptr));
+                              (host_done && poll) ? hseq : nullptr, o->theta_star != nullptr));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));

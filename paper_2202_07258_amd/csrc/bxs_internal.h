@@ -281,10 +281,11 @@ hipError_t launch_count_free(const LaunchCtx& c, int count);
 // the pass (nullptr: the caller copies it itself); host_gap: pinned host
 // double that receives the gap of instance 0 (single-instance calls), or
 // nullptr; host_seq: pinned (coherent) host word that receives the number of
-// screening passes run, written last with a system-scope release, or nullptr.
+// screening passes run, written last with a system-scope release, or nullptr;
+// oracle_dual: the instances carry a given dual optimum (Inst::ts).
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening,
                          int final_pass, int K, int kk, int ahead, int* host_done, double* host_gap,
-                         int* host_seq);
+                         int* host_seq, int oracle_dual);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
 // translation direction computed from A (tdir.hip, one instance)
 size_t tdir_scratch_doubles(long m, long n);

@@ -157,6 +157,7 @@ void k_init(const Inst* __restrict__ insts, State* __restrict__ st)
         S.t_valid = 1;
         S.passes = 0;
         S.ahead = 0;
+        S.n_free = 0;
     }
 }
 
@@ -429,6 +430,9 @@ void k_lanczos(const Inst* __restrict__ insts, State* __restrict__ st, int k, in
 // e_j bounds |computed - exact| of a_j^T theta, delta_r bounds the residual
 // error, and each rounded sum, product and square root is pushed outward.
 // ---------------------------------------------------------------------------
+// OD selects the diagnostic mode with a given dual optimum (its own
+// instantiation, so the regular pass carries none of its registers).
+template <bool OD>
 __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, State* __restrict__ st,
                                             int* __restrict__ done_counter, double eps_gap, int screening,
                                             int final_pass, int K, int kk, int ahead)
@@ -457,7 +461,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
     // point the dual update starts from (correlations gs_j = a_j^T ts from
     // the setup), so the item partials of the sweep do not apply
     const double* __restrict__ ts = I.ts;
-    const bool oracle_dual = ts != nullptr;
+    constexpr bool oracle_dual = OD;
 
     // ||r||^2 and the per-item quantities written by the correlation sweep
     // (mass, interior flag of t, largest translation ratio, presence of
@@ -556,19 +560,16 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
     // dot products (depth m/64 + 8, like w)
     const double e_ts = oracle_dual ? gw * S.tsnorm : 0.0;
     if (oracle_dual && has_inf) {
-        // interior check of t and translation coefficient from gs
+        // interior check of t and translation coefficient from gs (a plain
+        // loop: this diagnostic path keeps no batch of columns in registers)
         double tvl = 1.0, eml = 0.0;
-        for (int base = 0; base < nA; base += CH) {
-            Col c[E];
-            bool valid[E];
-            gather(base, c, valid);
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                if (!valid[e] || !isinf(c[e].u)) continue;
-                const double ewj = gw * c[e].cn * tnorm;
-                if (!(c[e].w + ewj < 0.0)) tvl = 0.0;
-                else eml = fmax(eml, fmax(c[e].g + c[e].cn * e_ts + 4.0 * u1 * fabs(c[e].g), 0.0) / (-c[e].w - ewj));
-            }
+        for (int p = tid; p < nA; p += NT) {
+            const int j = I.idx[p];
+            if (!isinf(up_of(I.u, j))) continue;
+            const double cnj = I.cn[j], wj = I.w[j], gj = I.gs[j];
+            const double ewj = gw * cnj * tnorm;
+            if (!(wj + ewj < 0.0)) tvl = 0.0;
+            else eml = fmax(eml, fmax(gj + cnj * e_ts + 4.0 * u1 * fabs(gj), 0.0) / (-wj - ewj));
         }
         tv = block_min<NT>(tvl, sh);
         emax = block_max<NT>(eml, sh);
@@ -636,7 +637,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
                 rc.iters = iters; rc.n_active = nA; rc.gap = G; rc.radius = rad;
                 rc.eps = eps; rc.primal = primal; rc.n_screened = 0;
             }
-            S.gap = G; S.radius = rad; S.eps = eps; S.primal = primal; S.margin = e_g + gw * eps * tnorm; S.margin = e_g + gw * eps * tnorm;
+            S.gap = G; S.radius = rad; S.eps = eps; S.primal = primal; S.margin = e_g + gw * eps * tnorm;
             S.t_valid = fallback ? 0 : 1;
             S.passes = passes + 1;
             S.n_fold = 0;
@@ -734,7 +735,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
             rc.iters = iters; rc.n_active = nA; rc.gap = G; rc.radius = rad;
             rc.eps = eps; rc.primal = primal; rc.n_screened = fout;
         }
-        S.gap = G; S.radius = rad; S.eps = eps; S.primal = primal;
+        S.gap = G; S.radius = rad; S.eps = eps; S.primal = primal; S.margin = e_g + gw * eps * tnorm;
         S.t_valid = 1;
         S.passes = passes + 1;
         S.n_active = out;
@@ -760,25 +761,26 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
     }
 }
 
-// Coordinates strictly inside the box at the returned iterate, one workgroup
-// per instance (reported with the solve).
+// Coordinates strictly inside the box at the returned iterate (reported with
+// the solve); grid (blocks, count), each block adds its count to n_free,
+// which the setup cleared.
 __global__ __launch_bounds__(256)
 void k_count_free(const Inst* __restrict__ insts, State* __restrict__ st)
 {
     __shared__ double sh[4];
-    const Inst& I = insts[blockIdx.x];
+    const Inst& I = insts[blockIdx.y];
     double c = 0.0;
-    for (int j = threadIdx.x; j < I.n; j += 256) {
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < I.n; j += gridDim.x * 256) {
         const double xj = I.x[j];
         c += (xj > lo_of(I.l, j) && xj < up_of(I.u, j)) ? 1.0 : 0.0;
     }
     c = block_sum<256>(c, sh);
-    if (threadIdx.x == 0) st[blockIdx.x].n_free = (int)c;
+    if (threadIdx.x == 0 && c > 0.0) atomicAdd(&st[blockIdx.y].n_free, (int)c);
 }
 
 hipError_t launch_count_free(const LaunchCtx& c, int count)
 {
-    k_count_free<<<dim3(count), dim3(256), 0, c.stream>>>(c.insts, c.st);
+    k_count_free<<<dim3(16, count), dim3(256), 0, c.stream>>>(c.insts, c.st);
     return hipGetLastError();
 }
 
@@ -790,12 +792,13 @@ hipError_t launch_count_free(const LaunchCtx& c, int count)
 // it then stores the number of screening passes run so far (a counter after
 // the ticket) with a system-scope release, so the host can wait for the pass
 // by reading that word instead of a completion event.
+template <bool OD>
 __global__ __launch_bounds__(1024)
 void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
               double eps_gap, int screening, int final_pass, int K, int kk, int ahead, int* host_done,
               double* host_gap, int* host_seq)
 {
-    screen_pass(insts, st, done_counter, eps_gap, screening, final_pass, K, kk, ahead);
+    screen_pass<OD>(insts, st, done_counter, eps_gap, screening, final_pass, K, kk, ahead);
     if (host_done == nullptr) return;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1093,10 +1096,17 @@ hipError_t launch_cp_init(const LaunchCtx& c, int count)
 }
 
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening, int final_pass,
-                         int K, int kk, int ahead, int* host_done, double* host_gap, int* host_seq)
+                         int K, int kk, int ahead, int* host_done, double* host_gap, int* host_seq,
+                         int oracle_dual)
 {
-    k_screen<<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                        final_pass, K, kk, ahead, host_done, host_gap, host_seq);
+    if (oracle_dual)
+        k_screen<true><<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
+                                                                  final_pass, K, kk, ahead, host_done, host_gap,
+                                                                  host_seq);
+    else
+        k_screen<false><<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
+                                                                   final_pass, K, kk, ahead, host_done, host_gap,
+                                                                   host_seq);
     return hipGetLastError();
 }
 
