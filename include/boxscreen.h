@@ -66,6 +66,11 @@ typedef enum {
  * tau = sigma = opts->step or 1 / (1.05 sqrt(L_est)); the screening test uses
  * the residual dual point of Sec. 4 like the other solvers) */
 typedef enum { BXS_PG = 0, BXS_CD = 1, BXS_CP = 2 } bxs_solver;
+/* Data-fidelity term f of eq. LR.  Only the least-squares fidelity
+ * f(z) = 1/2 ||z - y||^2 (alpha = 1 in eq. GAP_Safe_sph) is built; the
+ * values after it are reserved for the other fidelities that Sec. 3.3 leaves
+ * to local strong-concavity bounds, and are rejected with BXS_ERR_ARG. */
+typedef enum { BXS_FID_LS = 0 } bxs_fidelity;
 /* Storage type of A.  Every element is promoted exactly to FP64 before it is
  * used, so the problem solved is the one the stored values define; BXS_BF16
  * (bfloat16: 8-bit significand) halves the bytes of FP32 storage for the
@@ -148,6 +153,10 @@ typedef struct {
                                 problem of a batch.                                           */
     int     t_choice;        /* bxs_translation; with BXS_T_GIVEN opts->t applies, otherwise
                                 opts->t must be NULL                                           */
+    int     fidelity;        /* bxs_fidelity (BXS_FID_LS)                                      */
+    int     deterministic;   /* 0 or 1.  Every reduction of the library sums in a fixed order
+                                and no kernel uses floating-point atomics, so results repeat
+                                bit for bit on the same device, inputs and options either way */
 } bxs_opts;
 
 typedef struct {

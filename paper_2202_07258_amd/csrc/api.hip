@@ -226,6 +226,9 @@ static bxs_status check_opts(const bxs_opts* o)
     if (o->t_choice < BXS_T_GIVEN || o->t_choice > BXS_T_NEG_LEAST_CORRELATED)
         return fail(BXS_ERR_ARG, "unknown t_choice %d", o->t_choice);
     if (o->t_choice != BXS_T_GIVEN && o->t) return fail(BXS_ERR_ARG, "t_choice computes t: opts->t must be NULL");
+    if (o->fidelity != BXS_FID_LS)
+        return fail(BXS_ERR_ARG, "fidelity %d: only the least-squares fidelity (BXS_FID_LS) is built", o->fidelity);
+    if (o->deterministic != 0 && o->deterministic != 1) return fail(BXS_ERR_ARG, "deterministic must be 0 or 1");
     return BXS_OK;
 }
 

@@ -40,7 +40,7 @@ class Opts(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("history", C.POINTER(PassRecord)), ("history_cap", C.c_long), ("profile", C.c_int),
                 ("iter_precision", C.c_int), ("graph", C.c_int), ("theta_star", C.c_void_p),
-                ("t_choice", C.c_int)]
+                ("t_choice", C.c_int), ("fidelity", C.c_int), ("deterministic", C.c_int)]
 
 
 class Info(C.Structure):
@@ -173,7 +173,8 @@ def colmajor(A: Any, device="cuda", dtype=None) -> torch.Tensor:
 def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, eps_gap=1e-6, step=0.0,
               power_iters=0, t: torch.Tensor | None = None, history=0, stream=None,
               profile=False, iter_precision="f64", graph=False,
-              theta_star: torch.Tensor | None = None, t_choice="given") -> tuple[Opts, Any]:
+              theta_star: torch.Tensor | None = None, t_choice="given", fidelity="ls",
+              deterministic=True) -> tuple[Opts, Any]:
     lib = load()
     o = Opts()
     lib.bxs_default_opts(C.byref(o))
@@ -191,6 +192,8 @@ def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, 
     o.graph = 1 if graph else 0
     o.theta_star = _ptr(theta_star)
     o.t_choice = T_CHOICES[t_choice] if isinstance(t_choice, str) else int(t_choice)
+    o.fidelity = {"ls": 0}[fidelity] if isinstance(fidelity, str) else int(fidelity)
+    o.deterministic = 1 if deterministic else 0
     hist = None
     if history:
         hist = (PassRecord * int(history))()

@@ -47,6 +47,7 @@ def test_default_opts(lib):
     assert (o.solver, o.screening, o.screen_every, o.max_iter, o.eps_gap, o.step, o.power_iters) == \
         (0, 1, 10, 100000, 1e-6, 0.0, 0)
     assert not o.t and not o.workspace and not o.stream
+    assert o.fidelity == 0 and o.deterministic in (0, 1)      # least squares; reductions always fixed-order
 
 
 def _opts(lib, **kw):
@@ -73,7 +74,7 @@ def test_shape_errors(lib, m, n, lda, code):
 
 @pytest.mark.parametrize("field,value", [("solver", 7), ("screening", 2), ("screen_every", 0),
                                          ("max_iter", 0), ("eps_gap", -1.0), ("eps_gap", float("inf")),
-                                         ("step", float("nan"))])
+                                         ("step", float("nan")), ("fidelity", 1), ("deterministic", 2)])
 def test_option_errors(lib, field, value):
     o = _opts(lib, **{field: value})
     st = lib.solve_nnls(8, 8, 0, FAKE, 8, FAKE, FAKE, FAKE, C.byref(o), None)
