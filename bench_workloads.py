@@ -96,8 +96,9 @@ def bench_c1(args, device):
             comp[f"{solver}_{'screened' if screening else 'unscreened'}"] = {
                 "ms_per_solve": round(1e3 * (time.perf_counter() - t0) / args.steps, 3), "iters": ic["iters"],
                 "n_screened": ic["n_lower"], "status": ic["status_name"], "gap": ic["gap"]}
-    # many instances of the same law in one batch call
-    count = 1024
+    # many instances of the same law in one batch call (C1 x N: 4096 seeds,
+    # 3.3 GB of A, HBM-bound where the single instance is latency-bound)
+    count = 4096
     probs = []
     for i in range(count):
         Q = W.c1_nnls(1000 + i)
@@ -117,7 +118,10 @@ def bench_c1(args, device):
                          "sweeps": info_cd["iters"], "status": info_cd["status_name"]},
            "companion_nonneg_A": comp,
            "batch": {"instances": count, "solves_per_s": round(count / dtb, 1), "seconds": round(dtb, 3),
-                     "status": status, "max_iters": max(i["iters"] for i in infos)}}
+                     "status": status, "max_iters": max(i["iters"] for i in infos),
+                     # algorithmic bytes of the primal sweeps: every preserved column of
+                     # every iteration once in FP64 (plus x/l/u/index) and the residual
+                     "roofline": _batch_roofline(infos, P.m, 8, dtb)}}
     if not args.no_cpu_baseline:
         from oracle import boxls as ob
         A64 = P.A64()
@@ -127,6 +131,17 @@ def bench_c1(args, device):
         out["cpu_baseline"] = {"value": round(1 / dtc, 3), "unit": "solves/s", "cores": _cores(), "kind": "oracle",
                                "sample": f"one full oracle solve ({res.iters} iterations)"}
     return out
+
+
+def _batch_roofline(infos, m, elem_bytes, seconds):
+    """Whole-call HBM rate of a batch: the primal sweeps' algorithmic bytes
+    (sum over instances of col_iters x (m s_A + 36) + iters x 8 m) over the
+    call's wall time, against 8 TB/s."""
+    byts = sum(i["col_iters"] * (m * elem_bytes + 36) + i["iters"] * 8 * m for i in infos)
+    ach = byts / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK, 4), "traffic": None, "algorithmic_bytes": int(byts),
+            "note": "whole call (setup, screening passes and launch gaps included)"}
 
 
 # --------------------------------------------------------------------------

@@ -136,8 +136,18 @@ def translation_direction(A, choice: str):
                                b_+ (b_-) maximises (minimises) the summed correlation
                                with the other columns, sum_{k != j} b_j^T b_k
                                (Prop. 2, case 4, when that column of A^T A is positive);
-    ties go to the smallest index.  Returns (t, j) with j = -1 for the mean."""
+      "normal_equations":      Prop. 2, case 1 (rank(A) = n <= m): the solution of
+                               A^T t = -1 in the range of A, t = A (A^T A)^{-1} (-1)
+                               (unnormalised columns), so that A^T t = -1 exactly;
+    ties go to the smallest index.  Returns (t, j) with j = -1 for the mean and
+    the normal-equations direction."""
     A = np.asarray(A, dtype=np.float64)
+    if choice == "normal_equations":
+        m, n = A.shape
+        if n > m:
+            raise ValueError("Prop. 2, case 1 needs rank(A) = n <= m")
+        v = np.linalg.solve(A.T @ A, -np.ones(n))
+        return A @ v, -1
     nrm = np.sqrt(np.sum(A * A, axis=0))
     B = A / np.where(nrm > 0, nrm, 1.0)
     if choice == "neg_mean_column":

@@ -166,3 +166,20 @@ def test_prop2_case3_every_choice_interior_for_nonnegative_A():
     for choice in ("neg_mean_column", "neg_most_correlated", "neg_least_correlated"):
         t, _ = ob.translation_direction(A, choice)
         assert np.all(A.T @ t < 0), choice
+
+
+def test_prop2_case1_normal_equations_direction():
+    """Prop. 2, case 1 as the oracle computes it: A^T t = -1 for a tall
+    full-rank signed matrix (checked against an independent least-squares
+    solve of the transposed system, whose minimum-norm solution is the same
+    vector: it lies in the range of A), and t is interior."""
+    rng = np.random.default_rng(45)
+    A = rng.standard_normal((40, 17))
+    t, j = ob.translation_direction(A, "normal_equations")
+    assert j == -1
+    np.testing.assert_allclose(A.T @ t, -np.ones(17), atol=1e-12)
+    t_ls, *_ = np.linalg.lstsq(A.T, -np.ones(17), rcond=None)
+    np.testing.assert_allclose(t, t_ls, atol=1e-12)
+    assert ob.interior_direction_ok(A, np.full(17, np.inf), t)
+    with pytest.raises(ValueError):
+        ob.translation_direction(rng.standard_normal((5, 9)), "normal_equations")
