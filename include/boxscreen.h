@@ -89,11 +89,15 @@ typedef enum { BXS_ITER_F64 = 0, BXS_ITER_BF16X3 = 1 } bxs_iter_precision;
  *                               sum_{k != j} a_j^T a_k / (||a_j|| ||a_k||) with the others is
  *                               largest (case 4 when that column of A^T A is positive)
  *   BXS_T_NEG_LEAST_CORRELATED  t = -a_- / ||a_-||, the smallest summed correlation
+ *   BXS_T_NORMAL_EQUATIONS      t = A v with A^T A v = -1, so A^T t = -1 (case 1, rank(A) = n <= m;
+ *                               BXS_ERR_ARG when n > m); v by FP64 conjugate gradients to a
+ *                               residual norm of 1e-11 sqrt(n) or 2000 iterations, with a host
+ *                               synchronisation every 16 iterations (setup only)
  * Ties go to the smallest column index.  The computed t goes through the
  * same interior check as a given one (info.t_valid).  solve_bvls / solve_nnls
  * / solve_bvls_noalloc only (one problem per call). */
 typedef enum { BXS_T_GIVEN = 0, BXS_T_NEG_MEAN_COLUMN = 1, BXS_T_NEG_MOST_CORRELATED = 2,
-               BXS_T_NEG_LEAST_CORRELATED = 3 } bxs_translation;
+               BXS_T_NEG_LEAST_CORRELATED = 3, BXS_T_NORMAL_EQUATIONS = 4 } bxs_translation;
 
 /* Largest number of rows a single instance may have. */
 #define BXS_MAX_ROWS 16384

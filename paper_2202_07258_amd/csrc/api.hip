@@ -223,7 +223,7 @@ static bxs_status check_opts(const bxs_opts* o)
     if (o->iter_precision != BXS_ITER_F64 && o->iter_precision != BXS_ITER_BF16X3)
         return fail(BXS_ERR_ARG, "unknown iter_precision %d", o->iter_precision);
     if (o->power_iters > kLanczosMax) return fail(BXS_ERR_ARG, "power_iters must be <= %d", kLanczosMax);
-    if (o->t_choice < BXS_T_GIVEN || o->t_choice > BXS_T_NEG_LEAST_CORRELATED)
+    if (o->t_choice < BXS_T_GIVEN || o->t_choice > BXS_T_NORMAL_EQUATIONS)
         return fail(BXS_ERR_ARG, "unknown t_choice %d", o->t_choice);
     if (o->t_choice != BXS_T_GIVEN && o->t) return fail(BXS_ERR_ARG, "t_choice computes t: opts->t must be NULL");
     if (o->fidelity != BXS_FID_LS)
@@ -1038,6 +1038,9 @@ static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const 
     }
     if (opts->t_choice != BXS_T_GIVEN && specs.size() != 1)
         return fail(BXS_ERR_ARG, "t_choice is available for single problems only");
+    if (opts->t_choice == BXS_T_NORMAL_EQUATIONS && specs[0].n > specs[0].m)
+        return fail(BXS_ERR_ARG, "the normal-equations direction (Prop. 2, case 1) needs n <= m, got n=%ld m=%ld",
+                    specs[0].n, specs[0].m);
     Plan P;
     P.specs = specs;
     const long rc = (specs.size() == 1 && opts->history) ? opts->history_cap : 0;

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "ok", 1: "err_arg", 2: "err_shape", 3: "err_nonfinite", 4: "e
 BXS_PG, BXS_CD, BXS_CP = 0, 1, 2
 BXS_F64, BXS_F32, BXS_BF16 = 0, 1, 2
 MAX_ROWS = 16384
-T_CHOICES = {"given": 0, "neg_mean_column": 1, "neg_most_correlated": 2, "neg_least_correlated": 3}
+T_CHOICES = {"given": 0, "neg_mean_column": 1, "neg_most_correlated": 2, "neg_least_correlated": 3,
+             "normal_equations": 4}
 
 
 class PassRecord(C.Structure):

@@ -81,6 +81,12 @@ def test_option_errors(lib, field, value):
     assert st == N.BXS_ERR_ARG
 
 
+def test_normal_equations_direction_needs_tall_matrix(lib):
+    o = _opts(lib, t_choice=N.T_CHOICES["normal_equations"])
+    assert lib.solve_nnls(8, 16, 0, FAKE, 8, FAKE, FAKE, FAKE, C.byref(o), None) == N.BXS_ERR_ARG
+    assert "n <= m" in lib.bxs_last_error().decode()
+
+
 def test_null_arguments(lib):
     o = _opts(lib)
     assert lib.solve_bvls(8, 8, 0, None, 8, FAKE, FAKE, FAKE, FAKE, FAKE, C.byref(o), None) == N.BXS_ERR_ARG

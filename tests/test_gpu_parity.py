@@ -218,6 +218,26 @@ def test_library_translation_direction_prop2_cases_2_and_4():
     parity_vs_oracle(P, xg, sg, info, t=t_ora, **kw)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_library_translation_direction_prop2_case_1(dtype):
+    """Prop. 2 case 1 computed by the library: t = A v with A^T A v = -1 by
+    conjugate gradients on a tall signed matrix of full column rank (where
+    t = -1 is not interior); the trajectory and screened sets of the oracle
+    run with its exact solve of the same system."""
+    rng = W.rng_for(92, 2)
+    m, n = 600, 250
+    A = np.asfortranarray(W.unit_columns(rng.standard_normal((m, n))).astype(dtype))
+    xs = np.abs(rng.standard_normal(n)) * (rng.random(n) < 0.3)
+    y = A.astype(np.float64) @ xs + 0.1 * rng.standard_normal(m)
+    P = W.Problem(A, y, np.zeros(n), np.full(n, np.inf))
+    t_ora, _ = ob.translation_direction(P.A64(), "normal_equations")
+    assert not ob.interior_direction_ok(P.A64(), P.u, -np.ones(m))
+    kw = dict(screen_every=10, eps_gap=1e-9, max_iter=4000, step=step_of(P))
+    xg, sg, info = run_gpu(P, "nnls", t_choice="normal_equations", **kw)
+    assert info["t_valid"] == 1 and info["t_column"] == -1 and np.count_nonzero(sg) > 0
+    parity_vs_oracle(P, xg, sg, info, t=t_ora, **kw)
+
+
 def test_cd_nnls_parity():
     P = W.c1_companion(2, 150, 400)
     kw = dict(solver="cd", screen_every=1, eps_gap=1e-9, max_iter=3000)
