@@ -20,6 +20,31 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+// Low-latency wave sum through DPP lane moves (a few cycles each, against a
+// round trip through the LDS crossbar for a shuffle): pairs within quads,
+// then half rows and rows (mirrors), then the four rows through the row
+// broadcasts, which leave the total in lane 63; v_readlane hands it to every
+// lane.  The order is fixed, so the result repeats bit for bit.  Used where a
+// reduction sits on a sequential critical path (coordinate descent).
+template <int CTRL, int ROWM>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWM, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWM, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_move<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+    v += dpp_move<0x141, 0xF>(v);    // row_half_mirror: quads 0-1 / 2-3 of each row
+    v += dpp_move<0x140, 0xF>(v);    // row_mirror: the two halves of each row
+    v += dpp_move<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));

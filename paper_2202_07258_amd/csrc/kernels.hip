@@ -822,15 +822,21 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
 // ---------------------------------------------------------------------------
 // Cyclic coordinate descent, one workgroup per instance: for j in P in
 // ascending order, x_j <- Pi(x_j + a_j^T r / ||a_j||^2), r -= delta a_j.
-// r lives in registers across the whole sweep; the next column is loaded
-// while the current dot product is reduced.
+// r lives in registers across the whole sweep.  The columns are sequential
+// but their loads are not: a ring of PF column buffers keeps the loads of
+// the next PF - 1 columns in flight while the current one is reduced and
+// applied.  The preserved-set indices are staged in LDS by chunks of 1024
+// positions (two buffers, the next chunk loaded when a chunk begins), so a
+// column load waits only on an LDS read of its index.  Ring slots are
+// compile-time (the step loop is unrolled by PF).
 // ---------------------------------------------------------------------------
-template <typename TA, int TPC, int R, int V>
+template <typename TA, int TPC, int R, int V, int PF>
 __global__ __launch_bounds__(TPC)
 void k_cd(const Inst* __restrict__ insts, State* __restrict__ st, const int* __restrict__ inst_list, int sweeps)
 {
     constexpr int RO = R / V;
     constexpr int NW = TPC / 64;
+    static_assert(PF >= 2, "at least one column in flight");
     const int ii = inst_list[blockIdx.x];
     const Inst& I = insts[ii];
     const State& S = st[ii];
@@ -840,6 +846,16 @@ void k_cd(const Inst* __restrict__ insts, State* __restrict__ st, const int* __r
     const long long lda = I.lda;
     const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
     const int nA = S.n_active;
+    // every per-column array through a global address-space pointer held in
+    // registers: a flat load also counts against the scalar-load counter, and
+    // the wait for a descriptor field would then drain the prefetched columns
+    const int* __restrict__ idx = I.idx;
+    const double* __restrict__ cn2p = I.cn2;
+    double* __restrict__ xp = I.x;
+    const double* __restrict__ lp = I.l;
+    const double* __restrict__ up = I.u;
+    const double* __restrict__ lq = lp ? lp : cn2p;   // always a valid address
+    const double* __restrict__ uq = up ? up : cn2p;
     double rl[R];
 #pragma unroll
     for (int k = 0; k < RO; ++k)
@@ -856,8 +872,19 @@ void k_cd(const Inst* __restrict__ insts, State* __restrict__ st, const int* __r
     __shared__ double red[2][NW];
     int buf = 0;
     // column j and its scalars; rows >= m are masked where the column is used
-    struct Next { int j; double c2, x, l, u; };
-    auto load_col = [&](int j, TA (&dst)[R], Next& nx) {
+    struct Col { int j; double c2, x, l, u; };
+    TA ab[PF][R];
+    Col cs[PF];
+    constexpr int CH = 1024;
+    __shared__ int s_idx[2][CH];
+    auto stage = [&](int c) {                  // chunk c of positions into buffer c & 1
+        for (int k = L; k < CH; k += TPC) {
+            const int pos = c * CH + k;
+            s_idx[c & 1][k] = (pos < nA) ? gload(idx + pos) : 0;
+        }
+    };
+    auto idx_at = [&](int pos) { return s_idx[(pos / CH) & 1][pos % CH]; };
+    auto load_col = [&](int j, TA (&dst)[R], Col& nx) {
         const TA* col = A + (long long)j * lda;
 #pragma unroll
         for (int k = 0; k < RO; ++k) {
@@ -867,53 +894,64 @@ void k_cd(const Inst* __restrict__ insts, State* __restrict__ st, const int* __r
             for (int e = 0; e < V; ++e) dst[k * V + e] = tmp[e];
         }
         nx.j = j;
-        nx.c2 = I.cn2[j];
-        nx.x = I.x[j];
-        nx.l = lo_of(I.l, j);
-        nx.u = up_of(I.u, j);
+        nx.c2 = gload(cn2p + j);
+        nx.x = gload(xp + j);
+        // raw bound values: the defaults for absent bounds are selected where
+        // the column is used, so nothing here waits for these loads
+        nx.l = gload(lq + j);
+        nx.u = gload(uq + j);
     };
     for (int s = 0; s < sweeps; ++s) {
         if (nA == 0) break;
-        TA av[R];
-        Next cur, nxt{};
-        load_col(I.idx[0], av, cur);
-        int jnn = (nA > 1) ? I.idx[1] : 0;     // index of the next column, one step ahead of its load
-        for (int p = 0; p < nA; ++p) {
-            TA an[R];
-            if (p + 1 < nA) {
-                load_col(jnn, an, nxt);
-                jnn = (p + 2 < nA) ? I.idx[p + 2] : 0;
-            }
-            double d = 0.0;
+        stage(0);
+        stage(1);
+        __syncthreads();
+        // prologue: columns of positions 0 .. PF-2 in slots 0 .. PF-2
 #pragma unroll
-            for (int k = 0; k < R; ++k) d = fma(rowok[k] ? (double)av[k] : 0.0, rl[k], d);
-            d = wave_sum(d);
-            if constexpr (NW > 1) {
-                if ((L & 63) == 0) red[buf][L >> 6] = d;
-                __syncthreads();
-                double t2 = 0.0;
+        for (int q = 0; q < PF - 1; ++q)
+            if (q < nA) load_col(idx_at(q), ab[q], cs[q]);
+        for (int p0 = 0; p0 < nA; p0 += PF) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) t2 += red[buf][w];
-                d = t2;
-                buf ^= 1;
-            }
-            if (cur.c2 > 0.0) {
-                const double xn = fmin(fmax(cur.x + d / cur.c2, cur.l), cur.u);
-                const double delta = xn - cur.x;
-                if (delta != 0.0) {
-#pragma unroll
-                    for (int k = 0; k < R; ++k) rl[k] = fma(-delta, rowok[k] ? (double)av[k] : 0.0, rl[k]);
-                    if (L == 0) gstore(I.x + cur.j, xn);
+            for (int q = 0; q < PF; ++q) {
+                const int p = p0 + q;
+                if (p >= nA) break;
+                // a chunk begins: the buffer of the one before it is free (the
+                // lookahead only runs forward) and takes the chunk after it
+                if (p % CH == 0 && p > 0) {
+                    stage(p / CH + 1);
+                    __syncthreads();
                 }
-            }
-            if (p + 1 < nA) {
-                cur = nxt;
+                // issue position p + PF - 1 into the slot freed by step p - 1
+                const int s1 = (q + PF - 1) % PF;
+                if (p + PF - 1 < nA) load_col(idx_at(p + PF - 1), ab[s1], cs[s1]);
+                // independent of the dot product: overlaps its reduction
+                const double ic2 = (cs[q].c2 > 0.0) ? 1.0 / cs[q].c2 : 0.0;
+                double d = 0.0;
 #pragma unroll
-                for (int k = 0; k < R; ++k) av[k] = an[k];
+                for (int k = 0; k < R; ++k) d = fma(rowok[k] ? (double)ab[q][k] : 0.0, rl[k], d);
+                d = wave_sum_dpp(d);
+                if constexpr (NW > 1) {
+                    if ((L & 63) == 0) red[buf][L >> 6] = d;
+                    __syncthreads();
+                    double t2 = 0.0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) t2 += red[buf][w];
+                    d = t2;
+                    buf ^= 1;
+                }
+                // branch-free update (a zero column, ic2 = 0, leaves x_j and r as
+                // they are); only the store of x_j is conditional
+                const Col& cur = cs[q];
+                const double lo = lp ? cur.l : 0.0, hi = up ? cur.u : __builtin_inf();
+                const double xn = fmin(fmax(cur.x + d * ic2, lo), hi);
+                const double delta = (cur.c2 > 0.0) ? xn - cur.x : 0.0;
+#pragma unroll
+                for (int k = 0; k < R; ++k) rl[k] = fma(-delta, rowok[k] ? (double)ab[q][k] : 0.0, rl[k]);
+                if (L == 0 && delta != 0.0) gstore(xp + cur.j, xn);
             }
         }
         // the next sweep reads x_j written by lane 0 in this one
-        if constexpr (NW > 1) __syncthreads();
+        __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < RO; ++k)
@@ -976,22 +1014,24 @@ hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* i
 template <typename TA, int V>
 static hipError_t cd_dispatch_v(const LaunchCtx& c, int bucket, const int* list, int n_list, int sweeps)
 {
-#define BXS_CD(TPC, R)                                                                              \
-    {                                                                                               \
-        constexpr int VV = (V < R) ? V : R;                                                         \
-        k_cd<TA, TPC, R, VV><<<dim3(n_list), dim3(TPC), 0, c.stream>>>(c.insts, c.st, list, sweeps); \
-        return hipGetLastError();                                                                   \
+// PF: columns in flight, sized to the registers each bucket's workgroup
+// leaves a thread (64 and 256 threads: 512 VGPRs, 512: 256, 1024: 128)
+#define BXS_CD(TPC, R, PF)                                                                              \
+    {                                                                                                   \
+        constexpr int VV = (V < R) ? V : R;                                                             \
+        k_cd<TA, TPC, R, VV, PF><<<dim3(n_list), dim3(TPC), 0, c.stream>>>(c.insts, c.st, list, sweeps); \
+        return hipGetLastError();                                                                       \
     }
     switch (bucket) {
-    case 0: BXS_CD(64, 1)
-    case 1: BXS_CD(64, 2)
-    case 2: BXS_CD(64, 4)
-    case 3: BXS_CD(64, 8)
-    case 4: BXS_CD(256, 4)
-    case 5: BXS_CD(256, 8)
-    case 6: BXS_CD(256, 16)
-    case 7: BXS_CD(512, 16)
-    case 8: BXS_CD(1024, 16)
+    case 0: BXS_CD(64, 1, 8)
+    case 1: BXS_CD(64, 2, 8)
+    case 2: BXS_CD(64, 4, 8)
+    case 3: BXS_CD(64, 8, 8)
+    case 4: BXS_CD(256, 4, 8)
+    case 5: BXS_CD(256, 8, 8)
+    case 6: BXS_CD(256, 16, 6)
+    case 7: BXS_CD(512, 16, (sizeof(TA) == 8 && V == 1) ? 2 : 3)
+    case 8: BXS_CD(1024, 16, 2)
     default: return hipErrorInvalidValue;
     }
 #undef BXS_CD
