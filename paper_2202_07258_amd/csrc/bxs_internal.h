@@ -200,12 +200,10 @@ constexpr int dot_depth(int tpc, int rows) { return rows + 6 + tpc / 64; }
     X(29, 1024, 1, 16, 1, 2)     \
     X(30, 512, 1, 16, 1, 1)      \
     X(31, 512, 1, 16, 2, 1)      \
-    X(32, 512, 1, 16, 1, 2)     \
-    X(33, 512, 1, 8, 8, 1)      \
-    X(34, 512, 1, 8, 4, 2)
+    X(32, 512, 1, 16, 1, 2)
 
 struct VariantSpec { int tpc, ng, rows, cbi, pd; };
-constexpr int kNumVariants = 35;
+constexpr int kNumVariants = 33;
 constexpr int kNumDefaultVariants = 9;
 constexpr VariantSpec kVariants[kNumVariants] = {
 #define BXS_VS(ID, TPC, NG, R, CBI, PD) {TPC, NG, R, CBI, PD},
