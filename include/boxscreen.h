@@ -338,6 +338,23 @@ bxs_status nnls_adjoint(long m, long n, long B, int a_dtype, const void* A, long
                         const double* Y, long ldy, const double* X, long ldx,
                         const double* dX, long ldg, double* dY, long lddy, double* dA, long ldda,
                         double* dl, long lddl, const bxs_opts* opts, long* cg_iters);
+
+/* The same adjoint for box constraints shared by the right-hand sides
+ * (Sec. 3.2, eq. optimality2 with the free set F_b = {j : l_j < X_jb < u_j};
+ * the coordinates on a bound stay there under small perturbations when
+ * complementarity is strict):
+ *     v_b = (A_F^T A_F)^{-1} (dL/dx_b)_F,  dL/dY = A V,
+ *     dL/dA = (Y - A X) V^T - (dL/dY) X^T,
+ *     dL/dl_jb = (dL/dx_b - A^T dL/dy_b)_j where X_jb <= l_j, else 0,
+ *     dL/du_jb = the same where X_jb >= u_j, else 0.
+ *   l, u: device n-vectors or NULL (NULL l: l = 0; NULL u: u = +inf, so
+ *   l = u = NULL is nnls_adjoint).  du [lddu*B] out or NULL.  Every other
+ *   argument, the CG and the return codes as for nnls_adjoint. */
+bxs_status bvls_adjoint(long m, long n, long B, int a_dtype, const void* A, long lda,
+                        const double* Y, long ldy, const double* X, long ldx,
+                        const double* l, const double* u, const double* dX, long ldg,
+                        double* dY, long lddy, double* dA, long ldda, double* dl, long lddl,
+                        double* du, long lddu, const bxs_opts* opts, long* cg_iters);
 bxs_status bxs_workspace_size_adjoint(long m, long n, long B, size_t* bytes);
 
 /* Thread-local description of the last error (empty string if none). */

@@ -8,7 +8,7 @@ and raises if it is missing (there is no CPU fallback).
 from .native import (  # noqa: F401
     BoxscreenError, colmajor, load, solve_bvls, solve_bvls_noalloc, solve_bvls_varbatch, solve_nnls,
     solve_nnls_batched_shared,
-    nnls_adjoint, version, LIBRARY_PATH, EXPORTED, MAX_ROWS,
+    nnls_adjoint, bvls_adjoint, version, LIBRARY_PATH, EXPORTED, MAX_ROWS,
 )
 from .layer import nnls_layer  # noqa: F401
 from . import autotune  # noqa: F401

@@ -45,8 +45,9 @@ bxs_status set_error(bxs_status s, const char* msg) { return fail(s, "%s", msg);
 size_t batched_workspace_bytes(long m, long n, long B, int iter_precision);
 size_t adjoint_workspace_bytes(long m, long n, long B);
 bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
-                       const double* X, long ldx, const double* dX, long ldg, double* dY, long lddy, double* dA,
-                       long ldda, double* dl, long lddl, const bxs_opts* o, long* cg_iters);
+                       const double* X, long ldx, const double* l, const double* u, const double* dX, long ldg,
+                       double* dY, long lddy, double* dA, long ldda, double* dl, long lddl, double* du, long lddu,
+                       const bxs_opts* o, long* cg_iters);
 bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
                             double* X, long ldx, signed char* sat, long ldsat, const bxs_opts* o, bxs_info* infos);
 
@@ -1128,9 +1129,10 @@ bxs_status bxs_workspace_size_adjoint(long m, long n, long B, size_t* bytes)
     return BXS_OK;
 }
 
-bxs_status nnls_adjoint(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
-                        const double* X, long ldx, const double* dX, long ldg, double* dY, long lddy, double* dA,
-                        long ldda, double* dl, long lddl, const bxs_opts* opts, long* cg_iters)
+static bxs_status adjoint_common(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y,
+                                 long ldy, const double* X, long ldx, const double* l, const double* u,
+                                 const double* dX, long ldg, double* dY, long lddy, double* dA, long ldda, double* dl,
+                                 long lddl, double* du, long lddu, const bxs_opts* opts, long* cg_iters)
 {
     g_last_error.clear();
     if (!opts) return fail(BXS_ERR_ARG, "opts is NULL");
@@ -1138,13 +1140,31 @@ bxs_status nnls_adjoint(long m, long n, long B, int a_dtype, const void* A, long
     if (!(opts->eps_gap >= 0.0) || isinf(opts->eps_gap)) return fail(BXS_ERR_ARG, "eps_gap must be finite and >= 0");
     if (a_dtype != BXS_F64 && a_dtype != BXS_F32) return fail(BXS_ERR_ARG, "unknown a_dtype %d", a_dtype);
     if (m < 1 || n < 1 || B < 1) return fail(BXS_ERR_SHAPE, "m=%ld n=%ld B=%ld must be >= 1", m, n, B);
-    if (lda < m || ldy < m || ldx < n || ldg < n || lddy < m || (dA && ldda < m) || (dl && lddl < n))
+    if (lda < m || ldy < m || ldx < n || ldg < n || lddy < m || (dA && ldda < m) || (dl && lddl < n) ||
+        (du && lddu < n))
         return fail(BXS_ERR_SHAPE, "a leading dimension is too small");
     if ((double)m * (double)B > 2e9 || (double)n * (double)B > 2e9 || (double)m * (double)n > 2e9)
         return fail(BXS_ERR_SHAPE, "adjoint problem too large for 32-bit GEMM sizes");
     if (!A || !Y || !X || !dX || !dY) return fail(BXS_ERR_ARG, "NULL array argument");
-    return adjoint_run(m, n, B, a_dtype, A, lda, Y, ldy, X, ldx, dX, ldg, dY, lddy, dA, ldda, dl, lddl, opts,
-                       cg_iters);
+    return adjoint_run(m, n, B, a_dtype, A, lda, Y, ldy, X, ldx, l, u, dX, ldg, dY, lddy, dA, ldda, dl, lddl, du,
+                       lddu, opts, cg_iters);
+}
+
+bxs_status nnls_adjoint(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
+                        const double* X, long ldx, const double* dX, long ldg, double* dY, long lddy, double* dA,
+                        long ldda, double* dl, long lddl, const bxs_opts* opts, long* cg_iters)
+{
+    return adjoint_common(m, n, B, a_dtype, A, lda, Y, ldy, X, ldx, nullptr, nullptr, dX, ldg, dY, lddy, dA, ldda,
+                          dl, lddl, nullptr, 0, opts, cg_iters);
+}
+
+bxs_status bvls_adjoint(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
+                        const double* X, long ldx, const double* l, const double* u, const double* dX, long ldg,
+                        double* dY, long lddy, double* dA, long ldda, double* dl, long lddl, double* du, long lddu,
+                        const bxs_opts* opts, long* cg_iters)
+{
+    return adjoint_common(m, n, B, a_dtype, A, lda, Y, ldy, X, ldx, l, u, dX, ldg, dY, lddy, dA, ldda, dl, lddl,
+                          du, lddu, opts, cg_iters);
 }
 
 bxs_status solve_bvls_varbatch(long count, int a_dtype, const bxs_problem* probs, const bxs_opts* opts,

@@ -1078,17 +1078,20 @@ bxs_status batched_nnls_run(long m, long n, long B, int a_dtype, const void* A, 
 }  // namespace bxs
 
 // ---------------------------------------------------------------------------
-// Adjoint of the batched NNLS solution map (implicit differentiation).
-// At an optimum with free set F_b = {j : x_jb > 0} the optimality conditions
-// (Sec. 3.2, eq. optimality2: a_j^T (y_b - A x_b) = 0 on F_b) give
-// x_F = (A_F^T A_F)^{-1} A_F^T y_b, hence for dL/dX:
+// Adjoint of the batched box-constrained solution map (implicit
+// differentiation), with bounds l, u shared by the right-hand sides (NNLS:
+// l = 0, u = +inf).  At an optimum with free set F_b = {j : l_j < x_jb < u_j}
+// the optimality conditions (Sec. 3.2, eq. optimality2: a_j^T (y_b - A x_b)
+// = 0 on F_b) give x_F = (A_F^T A_F)^{-1} A_F^T (y_b - A_S x_S), hence for dL/dX:
 //     v_b      = (A_F^T A_F)^{-1} (dL/dx_b)_F      (batched masked CG, FP64)
 //     dL/dy_b  = A v_b  (v_b = 0 off F_b)
 //     dL/dA    = R V^T - (dL/dY) X^T,   R = Y - A X
+//     dL/dl_jb = (dL/dx_b - A^T dL/dy_b)_j at a lower bound, dL/du likewise at an upper one
 // ---------------------------------------------------------------------------
 namespace bxs {
 
 __global__ void k_adj_init(const double* __restrict__ X, long long ldx, const double* __restrict__ dX, long long ldg,
+                           const double* __restrict__ l, const double* __restrict__ u,
                            int n, int B, double* __restrict__ V, double* __restrict__ Rc, double* __restrict__ P,
                            signed char* __restrict__ F)
 {
@@ -1096,7 +1099,8 @@ __global__ void k_adj_init(const double* __restrict__ X, long long ldx, const do
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(k % n);
         const long long b = k / n;
-        const bool free_ = X[j + b * ldx] > 0.0;
+        const double xj = X[j + b * ldx];
+        const bool free_ = xj > (l ? l[j] : 0.0) && xj < (u ? u[j] : __builtin_inf());
         const double d = free_ ? dX[j + b * ldg] : 0.0;
         F[k] = free_ ? 1 : 0;
         V[k] = 0.0;
@@ -1264,22 +1268,28 @@ size_t adjoint_workspace_bytes(long m, long n, long B)
     return b + 1024;
 }
 
-// dL/dl = dL/dx - A^T dL/dy on the coordinates at their bound 0, 0 on the free set
+// dL/dl = dL/dx - A^T dL/dy on the coordinates at their lower bound, dL/du
+// the same at the upper bound, 0 elsewhere (either output may be NULL)
 __global__ void k_adj_bound_grad(const double* __restrict__ dX, long long ldg, const double* __restrict__ AtdY,
-                                 const signed char* __restrict__ F, int n, int B, double* __restrict__ dl,
-                                 long long lddl)
+                                 const signed char* __restrict__ F, const double* __restrict__ X, long long ldx,
+                                 const double* __restrict__ l, const double* __restrict__ u, int n, int B,
+                                 double* __restrict__ dl, long long lddl, double* __restrict__ du, long long lddu)
 {
     const long long tot = (long long)n * B;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(k % n);
         const long long b = k / n;
-        dl[j + b * lddl] = F[k] ? 0.0 : dX[j + b * ldg] - AtdY[k];
+        const double c = F[k] ? 0.0 : dX[j + b * ldg] - AtdY[k];
+        const double xj = X[j + b * ldx];
+        if (dl) dl[j + b * lddl] = (xj <= (l ? l[j] : 0.0)) ? c : 0.0;
+        if (du) du[j + b * lddu] = (xj >= (u ? u[j] : __builtin_inf())) ? c : 0.0;
     }
 }
 
 bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long lda, const double* Y, long ldy,
-                       const double* X, long ldx, const double* dX, long ldg, double* dY, long lddy, double* dA,
-                       long ldda, double* dl, long lddl, const bxs_opts* o, long* cg_iters)
+                       const double* X, long ldx, const double* l, const double* u, const double* dX, long ldg,
+                       double* dY, long lddy, double* dA, long ldda, double* dl, long lddl, double* du, long lddu,
+                       const bxs_opts* o, long* cg_iters)
 {
     hipStream_t s = (hipStream_t)o->stream;
     const size_t need = adjoint_workspace_bytes(m, n, B);
@@ -1319,7 +1329,7 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
     else
         k_b_convert_a<double><<<grid, 256, 0, s>>>((const double*)A, lda, (int)m, (int)n, A64, nullptr);
     k_adj_copy2<<<grid, 256, 0, s>>>(X, ldx, Xc, n, (int)n, (int)B);
-    k_adj_init<<<grid, 256, 0, s>>>(X, ldx, dX, ldg, (int)n, (int)B, V, Rc, P, F);
+    k_adj_init<<<grid, 256, 0, s>>>(X, ldx, dX, ldg, l, u, (int)n, (int)B, V, Rc, P, F);
     k_adj_dot<<<(int)B, 256, 0, s>>>(Rc, Rc, (int)n, rs);
     k_b_copy<<<64, 256, 0, s>>>(rs, rs0, B);
     k_adj_frob<<<1, 1024, 0, s>>>(A64, (long long)m * n, frob);
@@ -1362,10 +1372,10 @@ bxs_status adjoint_run(long m, long n, long B, int a_dtype, const void* A, long 
         BXS_HIPB(launch_dgemm(0, 1, gemm_args(skw, R, m, V, n, dA, ldda, m, n, B, 1.0, 0.0), s));
         BXS_HIPB(launch_dgemm(0, 1, gemm_args(skw, dY, lddy, Xc, n, dA, ldda, m, n, B, -1.0, 1.0), s));
     }
-    if (dl) {
+    if (dl || du) {
         // S = A^T dL/dY (S is free once the CG is done)
         BXS_HIPB(launch_dgemm(1, 0, gemm_args(skw, A64, m, dY, lddy, S, n, n, B, m, 1.0, 0.0), s));
-        k_adj_bound_grad<<<grid, 256, 0, s>>>(dX, ldg, S, F, (int)n, (int)B, dl, lddl);
+        k_adj_bound_grad<<<grid, 256, 0, s>>>(dX, ldg, S, F, Xc, n, l, u, (int)n, (int)B, dl, lddl, du, lddu);
         BXS_HIPB(hipGetLastError());
     }
     BXS_HIPB(hipStreamSynchronize(s));

@@ -66,7 +66,7 @@ EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch"
             "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
             "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant",
             "bxs_sweep_variant_for_rows", "bxs_set_group_scale", "bxs_group_scale",
-            "solve_nnls_batched_shared", "bxs_workspace_size_batched", "nnls_adjoint",
+            "solve_nnls_batched_shared", "bxs_workspace_size_batched", "nnls_adjoint", "bvls_adjoint",
             "bxs_workspace_size_adjoint"]
 
 _lib = None
@@ -126,6 +126,11 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
                                  C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p,
                                  C.c_long, C.c_void_p, C.c_long, C.POINTER(Opts), C.POINTER(C.c_long)]
     lib.nnls_adjoint.restype = C.c_int
+    lib.bvls_adjoint.argtypes = [C.c_long, C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long, C.c_void_p, C.c_long,
+                                 C.c_void_p, C.c_long, C.c_void_p, C.c_void_p, C.c_void_p, C.c_long, C.c_void_p,
+                                 C.c_long, C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p, C.c_long,
+                                 C.POINTER(Opts), C.POINTER(C.c_long)]
+    lib.bvls_adjoint.restype = C.c_int
     lib.bxs_workspace_size_adjoint.argtypes = [C.c_long, C.c_long, C.c_long, C.POINTER(C.c_size_t)]
     lib.bxs_workspace_size_adjoint.restype = C.c_int
     _lib = lib
@@ -437,3 +442,38 @@ def nnls_adjoint(A, Y, X, dX, *, max_iter=10000, tol=1e-12, need_dA=True, need_d
     if need_dl:
         return dY, dA, int(it.value), STATUS_NAMES[st], dl
     return dY, dA, int(it.value), STATUS_NAMES[st]
+
+
+def bvls_adjoint(A, Y, X, dX, l=None, u=None, *, max_iter=10000, tol=1e-12, need_dA=True, stream=None):
+    """Implicit-differentiation adjoint of the batched box-constrained map
+    with bounds shared by the right-hand sides (C ABI bvls_adjoint).  l, u:
+    (n,) float64 GPU tensors or None (0 and +inf).  Returns (dY, dA or None,
+    dl, du, cg_iterations, status), every gradient float64."""
+    lib = load()
+    m, n, lda, dt = _check_matrix(A)
+    Y64 = _colmajor64(Y, m, "Y")
+    B = Y64.shape[1]
+    X64 = _colmajor64(X, n, "X")
+    G64 = _colmajor64(dX, n, "dX")
+    lv = _vec(l, n, "l") if l is not None else None
+    uv = _vec(u, n, "u") if u is not None else None
+    dY = torch.empty((B, m), dtype=torch.float64, device=A.device).t()
+    dA = torch.empty((n, m), dtype=torch.float64, device=A.device).t() if need_dA else None
+    dl = torch.empty((B, n), dtype=torch.float64, device=A.device).t()
+    du = torch.empty((B, n), dtype=torch.float64, device=A.device).t()
+    o, _ = make_opts(max_iter=max_iter, eps_gap=tol, stream=stream)
+    b = C.c_size_t(0)
+    st = lib.bxs_workspace_size_adjoint(m, n, B, C.byref(b))
+    if st != BXS_OK:
+        _raise(lib, st)
+    wst = torch.empty(int(b.value), dtype=torch.uint8, device=A.device)
+    o.workspace = wst.data_ptr()
+    o.workspace_bytes = int(b.value)
+    it = C.c_long(0)
+    st = lib.bvls_adjoint(m, n, B, dt, A.data_ptr(), lda, Y64.data_ptr(), m, X64.data_ptr(), n,
+                          _ptr(lv), _ptr(uv), G64.data_ptr(), n, dY.data_ptr(), m,
+                          dA.data_ptr() if dA is not None else None, m, dl.data_ptr(), n, du.data_ptr(), n,
+                          C.byref(o), C.byref(it))
+    if st not in (BXS_OK, BXS_MAXITER, BXS_SINGULAR):
+        _raise(lib, st)
+    return dY, dA, dl, du, int(it.value), STATUS_NAMES[st]

@@ -107,3 +107,53 @@ def test_layer_warns_when_the_forward_did_not_converge():
     X = bx.nnls_layer(At, Yt, eps_gap=1e-12, max_iter=5, screen_every=5, on_inexact="raise")
     with pytest.raises(bx.BoxscreenError, match="not exact"):
         X.sum().backward()
+
+
+def test_bvls_adjoint_matches_oracle_formula():
+    """Box constraints shared by the right-hand sides (bvls_adjoint): dL/dY,
+    dL/dA, dL/dl and dL/du against the oracle's analytic adjoint at exact
+    BVLS solutions (SciPy's bounded-variable least squares), with
+    coordinates on both bounds; and l = u = NULL reproduces nnls_adjoint."""
+    import paper_2202_07258_amd as bx
+    from scipy.optimize import lsq_linear
+    rng = W.rng_for(98, 0)
+    m, n, B = 60, 45, 5
+    A = rng.standard_normal((m, n))
+    l = -0.2 - 0.3 * rng.random(n)
+    u = 0.2 + 0.3 * rng.random(n)
+    Y = A @ (rng.standard_normal((n, B))) + 0.1 * rng.standard_normal((m, B))
+    X = np.stack([lsq_linear(A, Y[:, b], bounds=(l, u), method="bvls", tol=1e-14).x for b in range(B)], axis=1)
+    # snap to the bounds the solver reached, so that the free sets are exact
+    X = np.where(np.abs(X - l[:, None]) < 1e-12, l[:, None], X)
+    X = np.where(np.abs(X - u[:, None]) < 1e-12, u[:, None], X)
+    ex = [oa.exact_solution(A, Y[:, b], l, u, X[:, b]) for b in range(B)]
+    assert all(ok for _, ok in ex)
+    X = np.stack([x for x, _ in ex], axis=1)
+    G = rng.standard_normal((n, B))
+    dA = torch.tensor(A.T.copy(), device="cuda").t()
+    dY, dAg, dl, du, iters, status = bx.bvls_adjoint(dA, torch.tensor(Y, device="cuda"), torch.tensor(X, device="cuda"),
+                                                     torch.tensor(G, device="cuda"), torch.tensor(l, device="cuda"),
+                                                     torch.tensor(u, device="cuda"))
+    assert status == "ok"
+    dY, dAg, dl, du = (t.cpu().numpy() for t in (dY, dAg, dl, du))
+    dA_ref = np.zeros_like(A)
+    n_lo = n_hi = 0
+    for b in range(B):
+        gy, gA, gl, gu = oa.solution_grad(A, Y[:, b], l, u, X[:, b], G[:, b])
+        tol = lambda g: dict(rtol=1e-8, atol=1e-9 * (1 + np.abs(g).max()))
+        np.testing.assert_allclose(dY[:, b], gy, **tol(gy))
+        np.testing.assert_allclose(dl[:, b], gl, **tol(gl))
+        np.testing.assert_allclose(du[:, b], gu, **tol(gu))
+        n_lo += np.count_nonzero(gl)
+        n_hi += np.count_nonzero(gu)
+        dA_ref += gA
+    assert n_lo > 0 and n_hi > 0
+    np.testing.assert_allclose(dAg, dA_ref, rtol=1e-8, atol=1e-9 * (1 + np.abs(dA_ref).max()))
+    # NNLS as the special case l = u = NULL
+    Xn = np.stack([_exact(A, Y[:, b]) for b in range(B)], axis=1)
+    args = (dA, torch.tensor(Y, device="cuda"), torch.tensor(Xn, device="cuda"), torch.tensor(G, device="cuda"))
+    dY1, dA1, _, st1, dl1 = bx.nnls_adjoint(*args, need_dl=True)
+    dY2, dA2, dl2, du2, _, st2 = bx.bvls_adjoint(*args)
+    assert st1 == st2
+    assert torch.equal(dY1, dY2) and torch.equal(dA1, dA2) and torch.equal(dl1, dl2)
+    assert float(du2.abs().max()) == 0.0
