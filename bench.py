@@ -298,6 +298,30 @@ def main():
         del devq
         torch.cuda.empty_cache()
 
+    if not args.no_companion:
+        # where screening pays at C2's shape: the saturation-ratio law of
+        # Sec. 5.1, Fig. 1 (a_ij, y_i ~ N(0,1), box b [-1, 1]) with b = 0.0005,
+        # 97% of the coordinates saturated at the optimum
+        log("[bench] Fig. 1 law at C2's shape, b = 0.0005 (screening pays)")
+        Q = W.fig1_bvls(0, m, n, 0.0005, dtype=np.float32)
+        devq = upload(Q, device)
+        dts, _, (xq, sq, iq) = time_solves(devq, args.steps, args.warmup, screening=True, eps_gap=1e-6,
+                                           screen_every=10)
+        leg = {"workload": f"Fig. 1 law: BVLS {m}x{n} N(0,1) entries (columns not normalised) stored FP32, "
+                           "y ~ N(0,1), box 0.0005 [-1, 1], PG K=10, gap 1e-6",
+               "screened": {"value": round(args.steps / dts, 3), "ms_per_step": round(1e3 * dts / args.steps, 3),
+                            "iters": iq["iters"], "n_screened": iq["n_lower"] + iq["n_upper"], "gap": iq["gap"],
+                            "mean_preserved_fraction": round(iq["col_iters"] / max(iq["iters"], 1) / n, 4)}}
+        if not args.no_unscreened:
+            dtu, _, (_, _, iu) = time_solves(devq, args.steps, args.warmup, screening=False, eps_gap=1e-6,
+                                             screen_every=10)
+            leg["unscreened"] = {"value": round(args.steps / dtu, 3), "ms_per_step": round(1e3 * dtu / args.steps, 3),
+                                 "iters": iu["iters"]}
+            leg["speedup_screened"] = round(dtu / dts, 3)
+        result["screening_pays"] = leg
+        del devq
+        torch.cuda.empty_cache()
+
     if not args.no_bf16:
         # precision tiering of the storage: the same instance with A rounded to
         # bfloat16 (half the bytes per sweep; every element still promoted
