@@ -256,7 +256,8 @@ struct Plan {
     std::vector<PlanSizes> sizes;
     std::vector<Inst> insts;                 // host copy of the device descriptors
     std::vector<Item> items[kNumVariants];
-    std::vector<RItem> ritems;
+    std::vector<RItem> ritems;      // wide reduction (kRedRows rows per block)
+    std::vector<RItem> nritems;     // narrow reduction (kRedRowsN rows per block)
     std::vector<int> cd_list[kNumCdBuckets];
     std::vector<int> variant;                // sweep variant per instance
     long rec_cap = 0;
@@ -318,6 +319,7 @@ static void layout(Plan& P, char* base)
     for (int b = 0; b < kNumVariants; ++b) P.items[b].clear();
     for (int b = 0; b < kNumCdBuckets; ++b) P.cd_list[b].clear();
     P.ritems.clear();
+    P.nritems.clear();
     for (long i = 0; i < count; ++i) {
         const InstSpec& s = P.specs[i];
         const PlanSizes& z = P.sizes[i];
@@ -351,7 +353,11 @@ static void layout(Plan& P, char* base)
         I.item_base = (int)P.items[b].size();
         for (int t = 0; t < z.items_cap; ++t) P.items[b].push_back(Item{(int)i, t});
         P.cd_list[cd_bucket_for_rows(s.m)].push_back((int)i);
-        for (int rb = 0; rb < (int)((s.m + kRedRows - 1) / kRedRows); ++rb) P.ritems.push_back(RItem{(int)i, rb});
+        // an instance never has more work items in use than items_cap
+        if (z.items_cap <= kRedNarrowMax)
+            for (int rb = 0; rb < (int)((s.m + kRedRowsN - 1) / kRedRowsN); ++rb) P.nritems.push_back(RItem{(int)i, rb});
+        else
+            for (int rb = 0; rb < (int)((s.m + kRedRows - 1) / kRedRows); ++rb) P.ritems.push_back(RItem{(int)i, rb});
         P.insts[i] = I;
     }
 }
@@ -363,6 +369,8 @@ struct DevTables {
     int n_items[kNumVariants];
     RItem* ritems;
     int n_ritems;
+    RItem* nritems;     // after the wide ones in the same table
+    int n_nritems;
     int* lists[kNumCdBuckets];
     int n_list[kNumCdBuckets];
     int* done_counter;
@@ -495,10 +503,12 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     D.insts = (Inst*)cur; cur += align_up(sizeof(Inst) * count, 256);
     D.st = (State*)cur; cur += align_up(sizeof(State) * count, 256);
     Item* items_base = (Item*)cur; cur += align_up(sizeof(Item) * total_items, 256);
-    D.ritems = (RItem*)cur; cur += align_up(sizeof(RItem) * P.ritems.size(), 256);
+    D.ritems = (RItem*)cur; cur += align_up(sizeof(RItem) * (P.ritems.size() + P.nritems.size()), 256);
     int* ints = (int*)cur;
     D.done_counter = ints + count;
     D.n_ritems = (int)P.ritems.size();
+    D.nritems = D.ritems + P.ritems.size();
+    D.n_nritems = (int)P.nritems.size();
     // Host image of the tables (descriptors, zeroed states, work items,
     // reduction items, CD lists, zeroed stop counter and ticket), uploaded
     // with one copy from pinned memory.
@@ -526,6 +536,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         off += D.n_items[b];
     }
     if (!P.ritems.empty()) memcpy(at(D.ritems), P.ritems.data(), sizeof(RItem) * P.ritems.size());
+    if (!P.nritems.empty()) memcpy(at(D.nritems), P.nritems.data(), sizeof(RItem) * P.nritems.size());
     for (int b = 0; b < kNumCdBuckets; ++b) {
         D.lists[b] = ints + loff;
         D.n_list[b] = (int)P.cd_list[b].size();
@@ -605,14 +616,14 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         const int np = P.lz_steps;
         for (int k = 0; k < np; ++k) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pow(b));
-            BXS_HIP(launch_reduce(c, kRedPow, D.ritems, D.n_ritems));
+            BXS_HIP(launch_reduce(c, kRedPow, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
             BXS_HIP(launch_lanczos(c, (int)count, k, k == np - 1, o->solver == BXS_CP));
         }
     } else {
         BXS_HIP(launch_set_step(c, (int)count, o->step));
     }
     for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
-    BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+    BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
     if (o->solver == BXS_CP) BXS_HIP(launch_cp_init(c, (int)count));
     if (!noalloc) BXS_HIP(hipEventRecord(ev1, stream));
 
@@ -694,23 +705,23 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             }
             if (o->profile) BXS_HIP(hipEventRecord(pev[(size_t)slot * 2 * K + 2 * k + 1], stream));
             if (pg) {
-                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, first));
+                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, first, D.nritems, D.n_nritems));
             } else if (cp) {
-                BXS_HIP(launch_reduce(c, kRedCP, D.ritems, D.n_ritems));
+                BXS_HIP(launch_reduce(c, kRedCP, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
             } else {
                 // fresh residual from the updated iterate
                 for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
-                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
             }
         }
         if (pg) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pgs(b));
-            BXS_HIP(launch_reduce(c, kRedAhead, D.ritems, D.n_ritems));
+            BXS_HIP(launch_reduce(c, kRedAhead, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
         } else {
             if (cp) {
                 // the screening test needs the residual at x (the iteration carries A x-bar)
                 for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
-                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems));
+                BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
             }
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeCorr, D.items[b], D.n_items[b]));
         }
@@ -719,7 +730,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
                               (host_done && poll) ? hseq : nullptr, o->theta_star != nullptr));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
-            BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems));
+            BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
         }
         return BXS_OK;
     };

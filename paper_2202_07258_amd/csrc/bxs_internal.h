@@ -102,6 +102,8 @@ struct Item {               // one workgroup of a column sweep
 };
 
 constexpr int kRedRows = 16;   // rows per workgroup of the partial reduction
+constexpr int kRedRowsN = 256; // rows per workgroup of the narrow reduction (one thread per row)
+constexpr int kRedNarrowMax = 16;   // instances with at most this many work items use it
 
 struct RItem {              // one workgroup of a partial reduction
     int inst;
@@ -267,7 +269,10 @@ hipError_t launch_colstats(const LaunchCtx& c, int variant, const Item* items, i
 // the kModePGS sweep of the previous pass.
 hipError_t launch_sweep(const LaunchCtx& c, int variant, int mode, const Item* items, int n_items,
                         int first = 0);
-hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems, int first = 0);
+// ritems: row blocks of kRedRows rows (instances with many work items);
+// nritems: row blocks of kRedRowsN rows (instances with at most kRedNarrowMax)
+hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems, int first = 0,
+                         const RItem* nritems = nullptr, int n_nritems = 0);
 hipError_t launch_validate(const LaunchCtx& c, int count);
 hipError_t launch_publish(const LaunchCtx& c, int* host_dst);
 hipError_t launch_pow_init(const LaunchCtx& c, int count);

@@ -24,6 +24,30 @@ namespace bxs {
 // masked in the sum) before adding them in order; the 64 group sums of a row
 // are then added by wave shuffles (4 groups per wave) and 16 per-wave sums.
 // ---------------------------------------------------------------------------
+// The reduced row's update, by mode: r = y' - sum (residual), r2 = y' - sum
+// (step taken ahead), y' -= sum and r -= sum2 (fold), r = sum (product with
+// A A^T), the Chambolle-Pock dual step v <- (v + sigma (sum - y')) / (1 + sigma)
+// with v in r2.
+template <int MODE>
+__device__ __forceinline__ void reduce_apply(const Inst& I, const State& S, int row, double ypv, double tot,
+                                             double tot2)
+{
+    if constexpr (MODE == kRedResidual) {
+        I.r[row] = ypv - tot;
+    } else if constexpr (MODE == kRedAhead) {
+        I.r2[row] = ypv - tot;
+    } else if constexpr (MODE == kRedFold) {
+        I.yp[row] = ypv - tot;
+        I.r[row] -= tot2;
+    } else if constexpr (MODE == kRedCP) {
+        // dual step of Chambolle-Pock: prox of sigma F*, F*(v) = 1/2 ||v||^2 + v^T y'
+        const double sg = S.step;
+        I.r2[row] = (I.r2[row] + sg * (tot - ypv)) / (1.0 + sg);
+    } else {
+        I.r[row] = tot;
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(1024)
 void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems, int first,
@@ -100,21 +124,37 @@ void k_reduce(const Inst* __restrict__ insts, State* __restrict__ st, const RIte
             tot += sh[w][rowl];
             if (MODE == kRedFold) tot2 += sh2[w][rowl];
         }
-        if constexpr (MODE == kRedResidual) {
-            I.r[row] = ypv - tot;
-        } else if constexpr (MODE == kRedAhead) {
-            I.r2[row] = ypv - tot;
-        } else if constexpr (MODE == kRedFold) {
-            I.yp[row] = ypv - tot;
-            I.r[row] -= tot2;
-        } else if constexpr (MODE == kRedCP) {
-            // dual step of Chambolle-Pock: prox of sigma F*, F*(v) = 1/2 ||v||^2 + v^T y'
-            const double sg = S.step;
-            I.r2[row] = (I.r2[row] + sg * (tot - ypv)) / (1.0 + sg);
-        } else {
-            I.r[row] = tot;
-        }
+        reduce_apply<MODE>(I, S, row, ypv, tot, tot2);
     }
+}
+
+// Partial reduction for instances with at most kRedNarrowMax work items (the
+// host puts every row block of such an instance in the narrow list): one
+// thread per row, kRedRowsN rows per workgroup, the partials of the row summed
+// in item order.  The wide kernel above would spend a 1024-thread workgroup
+// on every 16 rows whatever the number of items.
+template <int MODE>
+__global__ __launch_bounds__(kRedRowsN)
+void k_reduce_n(const Inst* __restrict__ insts, State* __restrict__ st, const RItem* __restrict__ ritems, int first)
+{
+    const RItem ri = ritems[blockIdx.x];
+    const Inst& I = insts[ri.inst];
+    const State& S = st[ri.inst];
+    if (S.done) return;
+    if (MODE == kRedResidual && first && S.ahead) return;
+    const int m = I.m;
+    const int row = ri.rb * kRedRowsN + threadIdx.x;
+    if (row >= m) return;
+    const int nlist = (MODE == kRedFold) ? S.n_fold : S.n_active;
+    const int cb = (MODE == kRedFold) ? S.cb_fold : S.cb;
+    const int T = (nlist + cb - 1) / cb;
+    const double ypv = (MODE == kRedPow) ? 0.0 : gload(I.yp + row);
+    double s = 0.0, s2 = 0.0;
+    for (int t = 0; t < T; ++t) {
+        s += gload(I.part + (size_t)t * m + row);
+        if (MODE == kRedFold) s2 += gload(I.part2 + (size_t)t * m + row);
+    }
+    reduce_apply<MODE>(I, S, row, ypv, s, s2);
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,8 +1090,22 @@ hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n
                  : cd_dispatch_v<double, 1>(c, bucket, inst_list, n_list, sweeps);
 }
 
-hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems, int first)
+hipError_t launch_reduce(const LaunchCtx& c, int mode, const RItem* ritems, int n_ritems, int first,
+                         const RItem* nritems, int n_nritems)
 {
+    if (n_nritems > 0) {
+        const dim3 g(n_nritems), b(kRedRowsN);
+        switch (mode) {
+        case kRedResidual: k_reduce_n<kRedResidual><<<g, b, 0, c.stream>>>(c.insts, c.st, nritems, first); break;
+        case kRedFold: k_reduce_n<kRedFold><<<g, b, 0, c.stream>>>(c.insts, c.st, nritems, first); break;
+        case kRedPow: k_reduce_n<kRedPow><<<g, b, 0, c.stream>>>(c.insts, c.st, nritems, first); break;
+        case kRedAhead: k_reduce_n<kRedAhead><<<g, b, 0, c.stream>>>(c.insts, c.st, nritems, first); break;
+        case kRedCP: k_reduce_n<kRedCP><<<g, b, 0, c.stream>>>(c.insts, c.st, nritems, first); break;
+        default: return hipErrorInvalidValue;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (n_ritems <= 0) return hipSuccess;
     dim3 grid(n_ritems), block(1024);
     switch (mode) {
