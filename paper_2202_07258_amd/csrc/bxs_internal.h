@@ -103,7 +103,7 @@ struct Item {               // one workgroup of a column sweep
 
 constexpr int kRedRows = 16;   // rows per workgroup of the partial reduction
 constexpr int kRedRowsN = 256; // rows per workgroup of the narrow reduction (one thread per row)
-constexpr int kRedNarrowMax = 16;   // instances with at most this many work items use it
+constexpr int kRedNarrowMax = 64;   // instances with at most this many work items use it
 
 struct RItem {              // one workgroup of a partial reduction
     int inst;
