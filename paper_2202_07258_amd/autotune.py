@@ -74,7 +74,7 @@ def _time_iteration(inst, iters: int, reps: int, copies: int = 1) -> float:
     return best
 
 
-SCALES = (1.0, 0.5, 0.25, 0.125)
+SCALES = (1.0, 0.5, 0.25, 0.125, 0.0625)
 
 
 def tune(device: str = "cuda:0", classes=None, iters: int = 40, reps: int = 2, cols_per_row: int = 4,

@@ -78,7 +78,7 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2202_07258_amd.build "
                            "(hipcc --offload-arch=gfx950); the solvers have no CPU fallback")
     lib = C.CDLL(path)
     lib.bxs_default_opts.argtypes = [C.POINTER(Opts)]

@@ -24,7 +24,7 @@ def _declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(N.LIBRARY_PATH):
-        pytest.fail("libboxscreen.so not built: run __graft_entry__.build()")
+        pytest.fail("libboxscreen.so not built: run python -m paper_2202_07258_amd.build")
     return N.load()
 
 
