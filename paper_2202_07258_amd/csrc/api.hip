@@ -786,6 +786,49 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         return g_new * (g_new / g_old) < o->eps_gap;
     };
 
+    // Batches: each time the unfinished instances fall to half of those still
+    // running at the last rebuild, the work-item, reduction and CD tables are
+    // rebuilt over the unfinished ones (the stream is drained first, since
+    // the pass in flight reads the tables), so the launches of the tail carry
+    // no workgroups of finished instances.  Not under graph replay (the
+    // captured pass holds the tables' sizes) nor without allocation.
+    const bool compact_ok = !want_graph && !noalloc && count > 1;
+    long live_prev = count;
+    auto rebuild_tables = [&]() -> bxs_status {
+        BXS_HIP(hipStreamSynchronize(stream));
+        std::vector<State> hs(count);
+        BXS_HIP(hipMemcpy(hs.data(), D.st, sbytes, hipMemcpyDeviceToHost));
+        auto live = [&](int inst) { return hs[inst].done == 0; };
+        long nlive = 0;
+        for (long i = 0; i < count; ++i) nlive += live((int)i) ? 1 : 0;
+        for (int b = 0; b < kNumVariants; ++b) {
+            std::vector<Item>& v = P.items[b];
+            v.erase(std::remove_if(v.begin(), v.end(), [&](const Item& it) { return !live(it.inst); }), v.end());
+            if (!v.empty()) BXS_HIP(hipMemcpy(D.items[b], v.data(), sizeof(Item) * v.size(), hipMemcpyHostToDevice));
+            D.n_items[b] = (int)v.size();
+        }
+        auto filt = [&](std::vector<RItem>& v) {
+            v.erase(std::remove_if(v.begin(), v.end(), [&](const RItem& r) { return !live(r.inst); }), v.end());
+        };
+        filt(P.ritems);
+        filt(P.nritems);
+        // the narrow list keeps its place after the wide one's original end
+        if (!P.ritems.empty())
+            BXS_HIP(hipMemcpy(D.ritems, P.ritems.data(), sizeof(RItem) * P.ritems.size(), hipMemcpyHostToDevice));
+        if (!P.nritems.empty())
+            BXS_HIP(hipMemcpy(D.nritems, P.nritems.data(), sizeof(RItem) * P.nritems.size(), hipMemcpyHostToDevice));
+        D.n_ritems = (int)P.ritems.size();
+        D.n_nritems = (int)P.nritems.size();
+        for (int b = 0; b < kNumCdBuckets; ++b) {
+            std::vector<int>& v = P.cd_list[b];
+            v.erase(std::remove_if(v.begin(), v.end(), [&](int i) { return !live(i); }), v.end());
+            if (!v.empty()) BXS_HIP(hipMemcpy(D.lists[b], v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
+            D.n_list[b] = (int)v.size();
+        }
+        live_prev = nlive;
+        return BXS_OK;
+    };
+
     int slot = 0;
     {
         bxs_status s = enqueue_pass(slot);
@@ -833,6 +876,13 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             }
         }
         if (hdone[slot] >= count || slot_final[slot]) break;
+        if (compact_ok) {
+            const long live_now = count - hdone[slot];
+            if (2 * live_now <= live_prev && live_prev - live_now >= 16) {
+                const bxs_status rs = rebuild_tables();
+                if (rs != BXS_OK) return rs;
+            }
+        }
         if (!queued_next) {
             bxs_status s = enqueue_pass(nxt);
             if (s != BXS_OK) return s;
