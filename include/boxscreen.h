@@ -290,6 +290,16 @@ bxs_status bxs_set_sweep_variant(int row_class, int v);
 bxs_status bxs_set_group_scale(int row_class, double scale);
 double bxs_group_scale(int row_class);   /* current scale, 0 for a bad class */
 
+/* Coordinate descent of a single problem (solve_bvls / solve_nnls with
+ * BXS_CD) runs block-sequentially by default: blocks of 128 preserved
+ * coordinates, their correlations A_J^T r over many workgroups, the
+ * coordinate updates of the block in order from the Gram block A_J^T A_J
+ * (c_p = a_p^T r - sum_{q < p in J} a_p^T a_q delta_q, the same iterates as one
+ * coordinate at a time up to rounding), then r -= A_J delta_J.  enable = 0
+ * runs every sweep in one workgroup instead (as for batches).  BXS_ERR_ARG for
+ * enable outside {0, 1}. */
+bxs_status bxs_set_cd_block(int enable);
+
 /* Batched non-negative LS with one shared matrix (Alg. 2 for every column
  * y_b of Y):  min 1/2 ||A x_b - y_b||^2  s.t. x_b >= 0,  b = 0..B-1.
  * Projected gradient for all right-hand sides at once, the matrix products

@@ -114,7 +114,7 @@ struct PlanSizes {
 };
 
 // Per-instance device bytes.
-static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap, int lz_steps, int tdir)
+static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap, int lz_steps, int tdir, int cdb)
 {
     PlanSizes p;
     p.g_target = g_target;
@@ -130,6 +130,7 @@ static PlanSizes instance_sizes(long m, long n, int g_target, long rec_cap, int 
     b += align_up(sizeof(bxs_pass_record) * std::max<long>(rec_cap, 0), 256);
     if (lz_steps > 0) b += align_up(sizeof(double) * (2 * (size_t)lz_steps + 2 * m), 256);  // Lanczos
     if (tdir) b += align_up(sizeof(double) * ((size_t)m + tdir_scratch_doubles(m, n)), 256);  // t and its scratch
+    if (cdb) b += align_up(sizeof(double) * (cdb_gram_doubles(n) + cdb_pg_doubles(m) + 2 * kCdbB), 256);  // block CD
     p.bytes = b;
     return p;
 }
@@ -265,11 +266,23 @@ struct Plan {
     int tdir = 0;                            // bxs_translation computed by the library (one instance)
     double* tbuf = nullptr;                  // its t (device) and scratch
     double* tscratch = nullptr;
+    int cdb = 0;                             // block-sequential CD (one instance)
+    double* cdb_gram = nullptr;              // its Gram blocks, chunk partials and block update
+    double* cdb_pg = nullptr;
+    double* cdb_delta = nullptr;
     int vec = 1;
     size_t bytes = 0;
 };
 
-static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps, int tdir = 0)
+// Block-sequential CD for single-instance CD solves (on unless switched off
+// by bxs_set_cd_block; batches keep one workgroup per instance).
+static int g_cd_block = 1;
+static int cd_block_on(const bxs_opts* o, long count)
+{
+    return (g_cd_block && count == 1 && o->solver == BXS_CD) ? 1 : 0;
+}
+
+static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps, int tdir = 0, int cdb = 0)
 {
     const long count = (long)P.specs.size();
     const int cus = device_cus();
@@ -279,6 +292,7 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps, int
     P.rec_cap = rec_cap;
     P.lz_steps = lz_steps;
     P.tdir = (count == 1) ? tdir : 0;
+    P.cdb = (count == 1) ? cdb : 0;
     P.sizes.resize(count);
     long total_items = 0;
     size_t inst_bytes = 0;
@@ -287,7 +301,7 @@ static bxs_status build_plan(Plan& P, int dtype, long rec_cap, int lz_steps, int
     P.vec = 1;
     for (long i = 0; i < count; ++i) {
         const InstSpec& s = P.specs[i];
-        P.sizes[i] = instance_sizes(s.m, s.n, g[i], (i == 0 && count == 1) ? rec_cap : 0, lz_steps, P.tdir);
+        P.sizes[i] = instance_sizes(s.m, s.n, g[i], (i == 0 && count == 1) ? rec_cap : 0, lz_steps, P.tdir, P.cdb);
         total_items += P.sizes[i].items_cap;
         inst_bytes += P.sizes[i].bytes;
         if ((s.lda % vecw) != 0 || ((uintptr_t)s.A % 16) != 0) P.vec = 0;
@@ -348,6 +362,11 @@ static void layout(Plan& P, char* base)
         if (P.tdir) {
             P.tbuf = (double*)take(sizeof(double) * ((size_t)s.m + tdir_scratch_doubles(s.m, s.n)));
             P.tscratch = P.tbuf + s.m;
+        }
+        if (P.cdb) {
+            P.cdb_gram = (double*)take(sizeof(double) * (cdb_gram_doubles(s.n) + cdb_pg_doubles(s.m) + 2 * kCdbB));
+            P.cdb_pg = P.cdb_gram + cdb_gram_doubles(s.n);
+            P.cdb_delta = P.cdb_pg + cdb_pg_doubles(s.m);
         }
         const int b = P.variant[i];
         I.item_base = (int)P.items[b].size();
@@ -700,6 +719,12 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
                 for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_pg(b, first));
             } else if (cp) {
                 for (int b = 0; b < kNumVariants; ++b) BXS_HIP(sweep_cp(b));
+            } else if (P.cdb) {
+                // Gram blocks of the preserved list, which changes only at a screening
+                // pass (the kernel returns at once when the list is unchanged); the
+                // host's n bounds the device's block count
+                if (k == 0) BXS_HIP(launch_cdb_gram(c, P.specs[0].n, P.cdb_gram));
+                BXS_HIP(launch_cdb_sweep(c, P.specs[0].m, P.specs[0].n, P.cdb_pg, P.cdb_gram, P.cdb_delta));
             } else {
                 for (int b = 0; b < kNumCdBuckets; ++b) BXS_HIP(launch_cd(c, b, D.lists[b], D.n_list[b], 1));
             }
@@ -1055,6 +1080,13 @@ bxs_status bxs_set_group_scale(int row_class, double scale)
     return BXS_OK;
 }
 
+bxs_status bxs_set_cd_block(int enable)
+{
+    if (enable != 0 && enable != 1) return fail(BXS_ERR_ARG, "enable must be 0 or 1");
+    g_cd_block = enable;
+    return BXS_OK;
+}
+
 double bxs_group_scale(int row_class)
 {
     return (row_class >= 0 && row_class < kNumDefaultVariants) ? g_group_scale[row_class] : 0.0;
@@ -1076,7 +1108,7 @@ bxs_status bxs_workspace_size_batch(long count, const long* m, const long* n, co
         if (sp.m < 1 || sp.n < 1 || sp.m > BXS_MAX_ROWS) return fail(BXS_ERR_SHAPE, "problem %ld: bad shape", i);
     }
     build_plan(P, BXS_F64, (count == 1 && opts->history) ? opts->history_cap : 0, lanczos_steps(opts),
-               opts->t_choice);
+               opts->t_choice, cd_block_on(opts, count));
     *bytes = P.bytes;
     return BXS_OK;
 }
@@ -1106,7 +1138,9 @@ static bxs_status solve_common(std::vector<InstSpec>& specs, int a_dtype, const 
     Plan P;
     P.specs = specs;
     const long rc = (specs.size() == 1 && opts->history) ? opts->history_cap : 0;
-    s = build_plan(P, a_dtype, rc, lanczos_steps(opts), opts->t_choice);
+    // the allocation-free entry keeps its fixed scratch bound: one workgroup per instance
+    const int cdb = fixed ? 0 : cd_block_on(opts, (long)specs.size());
+    s = build_plan(P, a_dtype, rc, lanczos_steps(opts), opts->t_choice, cdb);
     if (s != BXS_OK) return s;
     return run(P, a_dtype, opts, opts->t, infos, opts->history, opts->history_cap, fixed);
 }

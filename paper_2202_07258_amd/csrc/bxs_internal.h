@@ -84,6 +84,7 @@ struct State {
     int t_column;           // column picked for t by the library (bxs_translation), or -1
     int n_free;             // coordinates strictly inside the box at exit
     double margin;          // last pass: rounding margin of a correlation per unit column norm
+    int cdb_n;              // block CD: preserved-list length + 1 its Gram blocks were formed for
 };
 
 // Per-item scalars written by the correlation sweep for the screening pass:
@@ -295,6 +296,16 @@ hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n
 // translation direction computed from A (tdir.hip, one instance)
 size_t tdir_scratch_doubles(long m, long n);
 hipError_t launch_tdir(const LaunchCtx& c, int choice, long m, long n, double* scratch, double* t, int* picked);
+
+// Block-sequential CD of one instance (cdblock.hip): blocks of kCdbB
+// preserved positions, kCdbRows rows per workgroup of the block products.
+constexpr int kCdbB = 128;
+constexpr int kCdbRows = 64;
+size_t cdb_gram_doubles(long n);        // Gram and cross-Gram blocks of up to n preserved columns
+size_t cdb_pg_doubles(long m);          // chunk partials of two blocks' correlations
+hipError_t launch_cdb_gram(const LaunchCtx& c, long n, double* gram);
+// one sweep over at most nb blocks (an upper bound of the device's count)
+hipError_t launch_cdb_sweep(const LaunchCtx& c, long m, long n, double* pg, const double* gram, double* delta);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t s);
 
 }  // namespace bxs

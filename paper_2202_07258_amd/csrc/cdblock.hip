@@ -1,0 +1,373 @@
+// Block-sequential cyclic coordinate descent for one large instance (the
+// exact form of the cyclic sweep that spreads over the chip).  The preserved
+// list is cut into blocks J_0, J_1, ... of kCdbB consecutive positions and the
+// blocks are taken in order.  With r^(k) the residual after blocks 0..k-1:
+//   g_k = A_{J_k}^T r^(k),
+//   for p in J_k ascending: c_p = g_p - sum_{q < p in J_k} (a_p^T a_q) delta_q,
+//                           x_p <- Pi(x_p + c_p / ||a_p||^2), delta_p = change,
+//   r^(k+1) = r^(k) - A_{J_k} delta_k.
+// Since a_p^T (r - sum_{q<p} delta_q a_q) = g_p - sum_{q<p} delta_q a_p^T a_q,
+// the iterates are those of the one-coordinate-at-a-time sweep (Alg. 1 with
+// the CD solver of Sec. 5) up to rounding.
+//
+// Launch k of a sweep does two independent things at once:
+//   * the row workgroups apply r^(k-1) = r^(k-2) - A_{J_{k-2}} delta_{k-2} and
+//     form their rows' share of A_{J_k}^T r^(k-1);
+//   * one more workgroup runs the sequential update of block k-1 from
+//     g_{k-1} = A_{J_{k-1}}^T r^(k-2) - (A_{J_{k-1}}^T A_{J_{k-2}}) delta_{k-2}:
+//     the cross-Gram block accounts for the previous block's update, which the
+//     row workgroups apply to r only in this same launch.
+// A sweep of nb blocks is nb + 2 launches.  The Gram blocks A_J^T A_J and the
+// cross blocks A_{J_k}^T A_{J_{k-1}} of the preserved list are formed when the
+// list has changed (a screening pass that removed columns, or a new solve).
+// Every sum runs in a fixed order.
+#include "dev_common.h"
+
+#include <algorithm>
+
+namespace bxs {
+
+namespace {
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+struct double4v {
+    double x, y, z, w;
+};
+__device__ __forceinline__ double4v ld4(const double* s, int p)
+{
+    return double4v{s[4 * p], s[4 * p + 1], s[4 * p + 2], s[4 * p + 3]};
+}
+
+// The Gram blocks are valid for the preserved list of this many columns (+1,
+// so that 0 means none yet): the list only shrinks, keeping its order, so its
+// length names it.
+__device__ __forceinline__ int gram_tag(int n_active) { return n_active + 1; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Gram blocks.  blockIdx.z = 0: gram[k] = A_{J_k}^T A_{J_k}; z = 1 (k >= 1):
+// gram[nbh + k] = A_{J_k}^T A_{J_{k-1}}; both column-major B x B, element
+// (a, b) at b * B + a with rows a from J_k, zero outside the blocks' sizes.
+// Grid (nbh, 4, 2): a 64 x 64 tile per workgroup, rows of A staged through
+// LDS 32 at a time, a 4 x 4 register tile per thread.
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(256)
+void k_cdb_gram(const Inst* __restrict__ insts, const State* __restrict__ st, double* __restrict__ gram, int nbh)
+{
+    constexpr int B = kCdbB, RT = 32;
+    const Inst& I = insts[0];
+    const State& S = st[0];
+    if (S.done || S.cdb_n == gram_tag(S.n_active)) return;
+    const int nA = S.n_active;
+    const int k = blockIdx.x, cross = blockIdx.z;
+    const int p0 = k * B;
+    if (p0 >= nA || (cross && k == 0)) return;
+    const int bs = min(B, nA - p0);
+    const int pb = cross ? p0 - B : p0, bsb = cross ? B : bs;
+    const int ta = blockIdx.y >> 1, tb = blockIdx.y & 1;
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const int m = I.m;
+    const long long lda = I.lda;
+    const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
+    __shared__ double sa[RT][65], sb[RT][65];
+    __shared__ int ja[64], jb[64];
+    if (tid < 64) {
+        const int qa = ta * 64 + tid, qb = tb * 64 + tid;
+        ja[tid] = (qa < bs) ? I.idx[p0 + qa] : -1;
+        jb[tid] = (qb < bsb) ? I.idx[pb + qb] : -1;
+    }
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int r0 = 0; r0 < m; r0 += RT) {
+#pragma unroll
+        for (int t = 0; t < (RT * 64) / 256; ++t) {
+            const int e = tid + 256 * t;
+            const int row = e % RT, col = e / RT;
+            const int i = r0 + row;
+            const int ca = ja[col], cb = jb[col];
+            sa[row][col] = (ca >= 0 && i < m) ? (double)A[(long long)ca * lda + i] : 0.0;
+            sb[row][col] = (cb >= 0 && i < m) ? (double)A[(long long)cb * lda + i] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int rr = 0; rr < RT; ++rr) {
+            double va[4], vb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) va[a] = sa[rr][ty * 4 + a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) vb[b] = sb[rr][tx * 4 + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fma(va[a], vb[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+    double* __restrict__ G = gram + ((size_t)cross * nbh + k) * B * B;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int ga = ta * 64 + ty * 4 + a, gb = tb * 64 + tx * 4 + b;
+            G[(size_t)gb * B + ga] = (ga < bs && gb < bsb) ? acc[a][b] : 0.0;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Launch k of a sweep (k = 0 .. nb + 1), 512 threads per workgroup.
+//
+// Workgroups 0 .. nchunks-1, kCdbRows rows each (64 rows x 8 groups):
+//   k >= 2:  r -= A_{J_{k-2}} delta_{k-2} over the workgroup's rows;
+//   k < nb:  pg[k & 1][chunk][q] = sum over the rows of a_{J_k[q]} r, one
+//            column per 8 lanes (lane `part` takes rows part, part + 8, ...),
+//            then a 3-step butterfly over the 8 lanes.
+// Workgroup nchunks, for block b = k - 1 (1 <= k <= nb): stages the Gram
+// block in LDS (128 KB), forms g_b from the chunk partials minus the cross
+// block times delta_{b-1}, then one wave runs the in-block sequential update.
+// Lane l holds c for positions l and l + 64; at step p every lane reads c_p
+// with v_readlane and takes the same step, so delta_p is uniform and each lane
+// updates its c values with column p of the Gram block.  delta_b goes to
+// delta[b & 1] and the new x of the block's columns to x.
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(512)
+void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, int nchunks, int nbh,
+                double* __restrict__ pg, const double* __restrict__ gram, double* __restrict__ delta)
+{
+    constexpr int B = kCdbB, RW = kCdbRows;
+    static_assert(B == 128 && RW == 64, "two positions per lane, 64 rows per workgroup");
+    const Inst& I = insts[0];
+    State& S = st[0];
+    if (S.done) return;
+    const int nA = S.n_active;
+    const int nb = (nA + B - 1) / B;
+    const int tid = threadIdx.x;
+    __shared__ double smem[B * B + 12 * B];
+    __shared__ int sj[2 * B];
+
+    if (blockIdx.x == nchunks) {
+        // ---- sequential update of block b ----
+        const int b = k - 1;
+        if (b < 0 || b >= nb) {
+            if (k == nb + 1 && tid == 0) S.cdb_n = gram_tag(nA);  // this sweep's blocks are the current list's
+            return;
+        }
+        double* G = smem;
+        double* sg = smem + B * B;          // [4][B] chunk-group sums of g
+        double* sc = sg + 4 * B;            // [4][B] cross-term partials
+        double* sq = sc + 4 * B;            // [B][4] x, l, u, 1 / ||a||^2
+        const int p0 = b * B, bs = min(B, nA - p0);
+        const double* __restrict__ Gb = gram + (size_t)b * B * B;
+#pragma unroll 8
+        for (int e = tid; e < B * B; e += 512) G[e] = Gb[e];
+        {
+            const int q = tid & (B - 1), cg = tid >> 7;
+            const double* __restrict__ pgb = pg + (size_t)(b & 1) * nchunks * B;
+            double s = 0.0;
+            if (q < bs)
+                for (int ch = cg; ch < nchunks; ch += 4) s += pgb[(size_t)ch * B + q];
+            sg[cg * B + q] = s;
+            double t = 0.0;
+            if (b >= 1 && q < bs) {
+                // the previous block is full; its delta is in delta[(b - 1) & 1]
+                const double* __restrict__ Cb = gram + ((size_t)nbh + b) * B * B;
+                const double* __restrict__ dp = delta + (size_t)((b - 1) & 1) * B;
+#pragma unroll 8
+                for (int p = cg; p < B; p += 4) t = fma(Cb[(size_t)p * B + q], dp[p], t);
+            }
+            sc[cg * B + q] = t;
+            if (tid < B) {
+                const bool v = tid < bs;
+                const int j = v ? I.idx[p0 + tid] : 0;
+                const double c2 = v ? I.cn2[j] : 0.0;
+                sj[tid] = j;
+                sq[4 * tid + 0] = v ? I.x[j] : 0.0;
+                sq[4 * tid + 1] = v ? lo_of(I.l, j) : 0.0;
+                sq[4 * tid + 2] = v ? up_of(I.u, j) : 0.0;
+                sq[4 * tid + 3] = (c2 > 0.0) ? 1.0 / c2 : 0.0;
+            }
+        }
+        __syncthreads();
+        if (tid >= 64) return;
+        const int lane = tid, q0 = lane, q1 = lane + 64;
+        double c0 = ((sg[q0] + sg[B + q0]) + (sg[2 * B + q0] + sg[3 * B + q0])) -
+                    ((sc[q0] + sc[B + q0]) + (sc[2 * B + q0] + sc[3 * B + q0]));
+        double c1 = ((sg[q1] + sg[B + q1]) + (sg[2 * B + q1] + sg[3 * B + q1])) -
+                    ((sc[q1] + sc[B + q1]) + (sc[2 * B + q1] + sc[3 * B + q1]));
+        double d0 = 0.0, d1 = 0.0, xo0 = 0.0, xo1 = 0.0;
+        // Column p of the Gram block and position p's scalars are read two
+        // steps ahead into two alternating register sets (the loop is unrolled
+        // by two, so no set is copied), which keeps the LDS latency off the
+        // step-to-step chain: readlane c_p, the projected step, the c update.
+        // A zero column has 1 / ||a||^2 = 0 and c_p = 0, so its step x + 0 is
+        // x (x stays inside the box): delta = 0.
+        struct Buf {
+            double g0, g1;
+            double4v s;
+        };
+        auto fetch = [&](Buf& f, int p) {
+            const int pc = min(p, B - 1);
+            f.g0 = G[pc * B + q0];
+            f.g1 = G[pc * B + q1];
+            f.s = ld4(sq, pc);
+            // keep the reads here, ahead of the next step, not at their use
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        // step p of the block: its c is in c_lo (positions < 64) or c1
+        auto step = [&](const Buf& f, int p, bool lo_half) {
+            const double cp = readlane_d(lo_half ? c0 : c1, p & 63);
+            const double xn = fmin(fmax(f.s.x + cp * f.s.w, f.s.y), f.s.z);
+            const double d = xn - f.s.x;
+            const bool me = lane == (p & 63);
+            if (lo_half) {
+                d0 = me ? d : d0;
+                xo0 = me ? xn : xo0;
+                c0 = fma(-f.g0, d, c0);
+            } else {
+                d1 = me ? d : d1;
+                xo1 = me ? xn : xo1;
+            }
+            c1 = fma(-f.g1, d, c1);
+        };
+        Buf fa, fb;
+        fetch(fa, 0);
+        fetch(fb, 1);
+        const int n0 = min(bs, 64);
+        int p = 0;
+        for (; p + 1 < n0; p += 2) {
+            step(fa, p, true);
+            fetch(fa, p + 2);
+            step(fb, p + 1, true);
+            fetch(fb, p + 3);
+        }
+        if (p < n0) {              // odd count: bs < 64, the block ends here
+            step(fa, p, true);
+            ++p;
+        }
+        for (; p + 1 < bs; p += 2) {
+            step(fa, p, false);
+            fetch(fa, p + 2);
+            step(fb, p + 1, false);
+            fetch(fb, p + 3);
+        }
+        if (p < bs) step(fa, p, false);
+        double* __restrict__ db = delta + (size_t)(b & 1) * B;
+        if (q0 < bs) {
+            db[q0] = d0;
+            if (d0 != 0.0) I.x[sj[q0]] = xo0;
+        }
+        if (q1 < bs) {
+            db[q1] = d1;
+            if (d1 != 0.0) I.x[sj[q1]] = xo1;
+        }
+        return;
+    }
+
+    // ---- row workgroup: apply block k-2's update, form block k's partials ----
+    const bool upd = k >= 2 && k - 2 < nb;
+    const bool dot = k < nb;
+    if (!upd && !dot) return;
+    const int m = I.m;
+    const long long lda = I.lda;
+    const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
+    double* sdl = smem;                 // [B] delta_{k-2}
+    double* sr = sdl + B;               // [RW] updated residual rows
+    double* sp = sr + RW;               // [8][RW] update partials
+    int* sip = sj;                      // [B] columns of block k-2
+    int* sic = sj + B;                  // [B] columns of block k
+    const int qs = upd ? min(B, nA - (k - 2) * B) : 0;
+    const int bs = dot ? min(B, nA - k * B) : 0;
+    if (tid < B) {
+        sip[tid] = (tid < qs) ? I.idx[(k - 2) * B + tid] : 0;
+        sdl[tid] = (tid < qs) ? delta[(size_t)(k & 1) * B + tid] : 0.0;
+    } else if (tid < 2 * B) {
+        const int t = tid - B;
+        sic[t] = (t < bs) ? I.idx[k * B + t] : 0;
+    }
+    const int r0 = blockIdx.x * RW;
+    const int row = tid & (RW - 1), grp = tid >> 6;
+    const int i = r0 + row;
+    const bool rok = i < m;
+    const int ic = rok ? i : 0;
+    __syncthreads();
+    double rv = rok ? I.r[i] : 0.0;
+    if (upd) {
+        double s = 0.0;
+#pragma unroll 4
+        for (int q = grp; q < qs; q += 8) s = fma((double)A[(long long)sip[q] * lda + ic], sdl[q], s);
+        sp[grp * RW + row] = s;
+        __syncthreads();
+        if (grp == 0) {
+            const double* t = sp + row;
+            rv -= ((t[0] + t[RW]) + (t[2 * RW] + t[3 * RW])) + ((t[4 * RW] + t[5 * RW]) + (t[6 * RW] + t[7 * RW]));
+            if (rok) I.r[i] = rv;
+        }
+    }
+    if (!dot) return;
+    if (grp == 0) sr[row] = rok ? rv : 0.0;
+    __syncthreads();
+    const int part = tid & 7, slot = tid >> 3;
+    double* __restrict__ pgk = pg + (size_t)(k & 1) * nchunks * B + (size_t)blockIdx.x * B;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = slot + 64 * h;
+        const long long base = (long long)sic[min(q, bs - 1)] * lda;
+        double v = 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int rr = part + 8 * e;
+            const int ii = min(r0 + rr, m - 1);
+            v = fma((double)A[base + ii], sr[rr], v);
+        }
+        v += dpp_move<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+        v += dpp_move<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+        v += dpp_move<0x141, 0xF>(v);    // row_half_mirror: the two quads of 8 lanes
+        if (part == 0 && q < bs) pgk[q] = v;
+    }
+}
+
+size_t cdb_gram_doubles(long n) { return (size_t)2 * ((n + kCdbB - 1) / kCdbB) * kCdbB * kCdbB; }
+size_t cdb_pg_doubles(long m) { return (size_t)2 * ((m + kCdbRows - 1) / kCdbRows) * kCdbB; }
+
+hipError_t launch_cdb_gram(const LaunchCtx& c, long n, double* gram)
+{
+    const int nbh = (int)((n + kCdbB - 1) / kCdbB);
+    const dim3 g((unsigned)nbh, 4, 2), b(256);
+    if (c.dtype == BXS_BF16) k_cdb_gram<__bf16><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+    else if (c.dtype == BXS_F32) k_cdb_gram<float><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+    else k_cdb_gram<double><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+    return hipGetLastError();
+}
+
+// One sweep over up to n preserved columns: launches 0 .. nbh + 1, nbh from
+// the host's n (an upper bound of the device's block count; launches past
+// the device's count return at once).
+hipError_t launch_cdb_sweep(const LaunchCtx& c, long m, long n, double* pg, const double* gram, double* delta)
+{
+    const int nbh = (int)((n + kCdbB - 1) / kCdbB);
+    const int chunks = (int)((m + kCdbRows - 1) / kCdbRows);
+    for (int k = 0; k <= nbh + 1; ++k) {
+        if (c.dtype == BXS_BF16)
+            k_cdb_step<__bf16><<<chunks + 1, 512, 0, c.stream>>>(c.insts, c.st, k, chunks, nbh, pg, gram, delta);
+        else if (c.dtype == BXS_F32)
+            k_cdb_step<float><<<chunks + 1, 512, 0, c.stream>>>(c.insts, c.st, k, chunks, nbh, pg, gram, delta);
+        else
+            k_cdb_step<double><<<chunks + 1, 512, 0, c.stream>>>(c.insts, c.st, k, chunks, nbh, pg, gram, delta);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bxs

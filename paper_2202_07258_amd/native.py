@@ -65,7 +65,7 @@ NOALLOC_SCRATCH_BYTES = 32 << 20   # BXS_NOALLOC_SCRATCH_BYTES of include/boxscr
 EXPORTED = ["bxs_default_opts", "bxs_workspace_size", "bxs_workspace_size_batch", "solve_bvls", "solve_bvls_noalloc",
             "solve_nnls", "solve_bvls_varbatch", "bxs_last_error", "bxs_version",
             "bxs_num_sweep_variants", "bxs_sweep_variant_info", "bxs_row_class", "bxs_set_sweep_variant",
-            "bxs_sweep_variant_for_rows", "bxs_set_group_scale", "bxs_group_scale",
+            "bxs_sweep_variant_for_rows", "bxs_set_group_scale", "bxs_group_scale", "bxs_set_cd_block",
             "solve_nnls_batched_shared", "bxs_workspace_size_batched", "nnls_adjoint", "bvls_adjoint",
             "bxs_workspace_size_adjoint"]
 
@@ -116,6 +116,8 @@ def load(path: str = LIBRARY_PATH) -> C.CDLL:
     lib.bxs_set_group_scale.restype = C.c_int
     lib.bxs_group_scale.argtypes = [C.c_int]
     lib.bxs_group_scale.restype = C.c_double
+    lib.bxs_set_cd_block.argtypes = [C.c_int]
+    lib.bxs_set_cd_block.restype = C.c_int
     lib.solve_nnls_batched_shared.argtypes = [C.c_long, C.c_long, C.c_long, C.c_int, C.c_void_p, C.c_long,
                                               C.c_void_p, C.c_long, C.c_void_p, C.c_long, C.c_void_p, C.c_long,
                                               C.POINTER(Opts), C.POINTER(Info)]
@@ -370,6 +372,15 @@ def set_group_scale(row_class_: int, scale: float) -> None:
 
 def group_scale(row_class_: int) -> float:
     return float(load().bxs_group_scale(int(row_class_)))
+
+
+def set_cd_block(enable: bool) -> None:
+    """Block-sequential coordinate descent for single problems (default on);
+    off runs each sweep in one workgroup."""
+    lib = load()
+    st = lib.bxs_set_cd_block(1 if enable else 0)
+    if st != BXS_OK:
+        _raise(lib, st)
 
 
 def solve_nnls_batched_shared(A, Y, X0=None, **kw):

@@ -136,16 +136,48 @@ def test_cd_parity(m, n):
     xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, **kw)
 
 
+@pytest.fixture(params=[1, 0], ids=["block", "one_wg"])
+def cd_block(request):
+    """Single-problem CD as the block-sequential sweep (Gram blocks, one
+    launch per block of 128 positions) and as the one-workgroup sweep."""
+    from paper_2202_07258_amd import native as N
+    N.set_cd_block(request.param)
+    yield request.param
+    N.set_cd_block(1)
+
+
 @pytest.mark.parametrize("m,n", [(700, 1500), (2000, 1300), (4000, 900), (6000, 800), (9000, 700)])
-def test_cd_parity_multiwave(m, n):
-    """CD buckets whose workgroup spans several waves (m > 512: 256, 512 and
-    1024 threads), where each dot product adds the per-wave sums through LDS.
-    Tall shapes keep |F| = 0.4 min(m, n) free coordinates."""
-    print(f"\n[cd bvls multi-wave] m={m} n={n}", flush=True)
+def test_cd_parity_multiwave(m, n, cd_block):
+    """Large single problems: the block-sequential sweep (several blocks, a
+    ragged last block, m not a multiple of the 64-row chunks) and the
+    one-workgroup sweep whose workgroup spans several waves (m > 512: 256,
+    512 and 1024 threads).  Tall shapes keep |F| = 0.4 min(m, n) free
+    coordinates."""
+    print(f"\n[cd bvls multi-wave] m={m} n={n} block={cd_block}", flush=True)
     P = planted(23, m, n, nf_frac=0.4 * min(m, n) / m)
     kw = dict(solver="cd", screen_every=1, eps_gap=1e-10, max_iter=2000)
     xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, **kw)
     assert res.status == "ok" and np.count_nonzero(res.sat) > 0
+
+
+@pytest.mark.parametrize("screening", [True, False])
+def test_cd_block_sweeps_match_oracle(screening, cd_block):
+    """Fixed budget of 60 CD sweeps (Sec. 5 CD solver), screening every 5, on
+    a BVLS problem of 5 blocks of 128 with a ragged last one (n = 601) and
+    m = 1001 rows: the gap and preserved-set size after every pass match the
+    oracle's.  With screening the list shrinks over several passes to 400
+    (4 blocks), so the Gram blocks are re-formed after those passes and
+    reused after the others."""
+    print(f"\n[cd bvls sweeps] screening={screening} block={cd_block}", flush=True)
+    P = planted(31, 1001, 601)
+    kw = dict(solver="cd", screening=screening, screen_every=5, eps_gap=0.0, max_iter=60)
+    xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, history=64, **kw)
+    assert info["iters"] == res.iters == 60
+    if screening:
+        assert res.history[0]["n_active"] == 601 and res.history[-1]["n_active"] <= 450
+    for hg, ho in zip(info["history"], res.history):
+        assert hg["n_active"] == ho["n_active"]
+        assert hg["gap"] == pytest.approx(ho["gap"], rel=1e-6, abs=1e-11)
 
 
 @pytest.mark.parametrize("solver,dtype", [("pg", np.float32), ("pg", np.float64), ("cd", np.float64)])
