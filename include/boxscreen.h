@@ -295,9 +295,11 @@ double bxs_group_scale(int row_class);   /* current scale, 0 for a bad class */
  * coordinates, their correlations A_J^T r over many workgroups, the
  * coordinate updates of the block in order from the Gram block A_J^T A_J
  * (c_p = a_p^T r - sum_{q < p in J} a_p^T a_q delta_q, the same iterates as one
- * coordinate at a time up to rounding), then r -= A_J delta_J.  enable = 0
- * runs every sweep in one workgroup instead (as for batches).  BXS_ERR_ARG for
- * enable outside {0, 1}. */
+ * coordinate at a time up to rounding), then r -= A_J delta_J.  Its
+ * workspace (bxs_workspace_size counts it) adds 2 * 128 doubles per column
+ * (the Gram blocks and the cross blocks A_Jk^T A_J(k-1)).  enable = 0 runs
+ * every sweep in one workgroup instead, as batches and solve_bvls_noalloc
+ * always do.  Process-wide; BXS_ERR_ARG for enable outside {0, 1}. */
 bxs_status bxs_set_cd_block(int enable);
 
 /* Batched non-negative LS with one shared matrix (Alg. 2 for every column

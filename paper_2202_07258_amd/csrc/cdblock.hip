@@ -155,7 +155,7 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
     const int nA = S.n_active;
     const int nb = (nA + B - 1) / B;
     const int tid = threadIdx.x;
-    __shared__ double smem[B * B + 12 * B];
+    __shared__ __align__(16) double smem[B * B + 20 * B];
     __shared__ int sj[2 * B];
 
     if (blockIdx.x == nchunks) {
@@ -166,29 +166,65 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
             return;
         }
         double* G = smem;
-        double* sg = smem + B * B;          // [4][B] chunk-group sums of g
-        double* sc = sg + 4 * B;            // [4][B] cross-term partials
-        double* sq = sc + 4 * B;            // [B][4] x, l, u, 1 / ||a||^2
+        double* sg = smem + B * B;          // [8][B] chunk-group sums of g
+        double* sc = sg + 8 * B;            // [8][B] cross-term partials
+        double* sq = sc + 8 * B;            // [B][4] x, l, u, 1 / ||a||^2
         const int p0 = b * B, bs = min(B, nA - p0);
-        const double* __restrict__ Gb = gram + (size_t)b * B * B;
-#pragma unroll 8
-        for (int e = tid; e < B * B; e += 512) G[e] = Gb[e];
         {
-            const int q = tid & (B - 1), cg = tid >> 7;
-            const double* __restrict__ pgb = pg + (size_t)(b & 1) * nchunks * B;
-            double s = 0.0;
-            if (q < bs)
-                for (int ch = cg; ch < nchunks; ch += 4) s += pgb[(size_t)ch * B + q];
-            sg[cg * B + q] = s;
-            double t = 0.0;
-            if (b >= 1 && q < bs) {
+            // Every global read of the prologue is issued before its results
+            // are used: the Gram block and the cross block as 16-byte loads,
+            // the chunk partials in batches of independent loads.  Thread
+            // (pair q2, group cg) covers positions 2 q2 and 2 q2 + 1; each
+            // group's sums run in a fixed order.
+            const int q2 = tid & 63, cg = tid >> 6, q = 2 * q2;
+            const double2* __restrict__ Gb2 = reinterpret_cast<const double2*>(gram + (size_t)b * B * B);
+            double2 gv[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) gv[i] = Gb2[tid + 512 * i];
+            double2 t2 = make_double2(0.0, 0.0);
+            if (b >= 1) {
                 // the previous block is full; its delta is in delta[(b - 1) & 1]
-                const double* __restrict__ Cb = gram + ((size_t)nbh + b) * B * B;
+                const double2* __restrict__ Cb2 = reinterpret_cast<const double2*>(gram + ((size_t)nbh + b) * B * B);
                 const double* __restrict__ dp = delta + (size_t)((b - 1) & 1) * B;
-#pragma unroll 8
-                for (int p = cg; p < B; p += 4) t = fma(Cb[(size_t)p * B + q], dp[p], t);
+                double2 cv[16];
+                double dv[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    cv[i] = Cb2[(cg + 8 * i) * (B / 2) + q2];
+                    dv[i] = dp[cg + 8 * i];
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    t2.x = fma(cv[i].x, dv[i], t2.x);
+                    t2.y = fma(cv[i].y, dv[i], t2.y);
+                }
             }
-            sc[cg * B + q] = t;
+            const double2* __restrict__ pg2 =
+                reinterpret_cast<const double2*>(pg + (size_t)(b & 1) * nchunks * B) + q2;
+            double2 s2 = make_double2(0.0, 0.0);
+            int ch = cg;
+            for (; ch + 8 * 7 < nchunks; ch += 8 * 8) {
+                double2 v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = pg2[(size_t)(ch + 8 * i) * (B / 2)];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    s2.x += v[i].x;
+                    s2.y += v[i].y;
+                }
+            }
+            for (; ch < nchunks; ch += 8) {
+                const double2 v = pg2[(size_t)ch * (B / 2)];
+                s2.x += v.x;
+                s2.y += v.y;
+            }
+            sg[cg * B + q] = s2.x;
+            sg[cg * B + q + 1] = s2.y;
+            sc[cg * B + q] = t2.x;
+            sc[cg * B + q + 1] = t2.y;
+            double2* G2 = reinterpret_cast<double2*>(G);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) G2[tid + 512 * i] = gv[i];
             if (tid < B) {
                 const bool v = tid < bs;
                 const int j = v ? I.idx[p0 + tid] : 0;
@@ -203,67 +239,98 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
         __syncthreads();
         if (tid >= 64) return;
         const int lane = tid, q0 = lane, q1 = lane + 64;
-        double c0 = ((sg[q0] + sg[B + q0]) + (sg[2 * B + q0] + sg[3 * B + q0])) -
-                    ((sc[q0] + sc[B + q0]) + (sc[2 * B + q0] + sc[3 * B + q0]));
-        double c1 = ((sg[q1] + sg[B + q1]) + (sg[2 * B + q1] + sg[3 * B + q1])) -
-                    ((sc[q1] + sc[B + q1]) + (sc[2 * B + q1] + sc[3 * B + q1]));
-        double d0 = 0.0, d1 = 0.0, xo0 = 0.0, xo1 = 0.0;
-        // Column p of the Gram block and position p's scalars are read two
-        // steps ahead into two alternating register sets (the loop is unrolled
-        // by two, so no set is copied), which keeps the LDS latency off the
-        // step-to-step chain: readlane c_p, the projected step, the c update.
-        // A zero column has 1 / ||a||^2 = 0 and c_p = 0, so its step x + 0 is
-        // x (x stays inside the box): delta = 0.
+        auto sum8 = [&](const double* a, int qq) {
+            return ((a[qq] + a[B + qq]) + (a[2 * B + qq] + a[3 * B + qq])) +
+                   ((a[4 * B + qq] + a[5 * B + qq]) + (a[6 * B + qq] + a[7 * B + qq]));
+        };
+        double c0 = sum8(sg, q0) - sum8(sc, q0);
+        double c1 = sum8(sg, q1) - sum8(sc, q1);
+        // The step-to-step chain is kept to five dependent operations: c_p is
+        // finished as a uniform value, c_p = c'_p - G[p-1][p] delta_{p-1},
+        // where c'_p (every update up to delta_{p-2}) was read from its lane
+        // one step earlier, before that lane's own update with delta_{p-1};
+        // then the projected step and delta_p = x_new - x.  The lanes'
+        // updates c_q -= G[p][q] delta_p and the reads run beside the chain.
+        // G[p-1][p] delta_{p-1} is the same fma that lane p does, so c_p is
+        // the value it would hold.  Column p of the Gram block and position
+        // p's scalars are read four steps ahead into a ring of four register
+        // sets (the loop is unrolled by four, so no set is copied).  A zero
+        // column has 1 / ||a||^2 = 0 and c_p = 0: its step x + 0 is x (x stays
+        // inside the box), delta = 0.
+        const double x0 = sq[4 * q0], x1 = sq[4 * q1];
+        double xo0 = x0, xo1 = x1;
         struct Buf {
-            double g0, g1;
+            double g0, g1, gu;
             double4v s;
         };
         auto fetch = [&](Buf& f, int p) {
             const int pc = min(p, B - 1);
             f.g0 = G[pc * B + q0];
             f.g1 = G[pc * B + q1];
+            f.gu = G[max(pc - 1, 0) * B + pc];
             f.s = ld4(sq, pc);
-            // keep the reads here, ahead of the next step, not at their use
+            // keep the reads here, ahead of the steps that use them
             __builtin_amdgcn_sched_barrier(0);
         };
-        // step p of the block: its c is in c_lo (positions < 64) or c1
+        double cpo = readlane_d(c0, 0), dprev = 0.0;
         auto step = [&](const Buf& f, int p, bool lo_half) {
-            const double cp = readlane_d(lo_half ? c0 : c1, p & 63);
+            const double cp = fma(-f.gu, dprev, cpo);
             const double xn = fmin(fmax(f.s.x + cp * f.s.w, f.s.y), f.s.z);
             const double d = xn - f.s.x;
+            cpo = readlane_d(lo_half ? c0 : c1, (p + 1) & 63);
             const bool me = lane == (p & 63);
             if (lo_half) {
-                d0 = me ? d : d0;
                 xo0 = me ? xn : xo0;
                 c0 = fma(-f.g0, d, c0);
             } else {
-                d1 = me ? d : d1;
                 xo1 = me ? xn : xo1;
             }
             c1 = fma(-f.g1, d, c1);
+            dprev = d;
         };
-        Buf fa, fb;
-        fetch(fa, 0);
-        fetch(fb, 1);
+        Buf f0, f1, f2, f3;
+        fetch(f0, 0);
+        fetch(f1, 1);
+        fetch(f2, 2);
+        fetch(f3, 3);
         const int n0 = min(bs, 64);
         int p = 0;
-        for (; p + 1 < n0; p += 2) {
-            step(fa, p, true);
-            fetch(fa, p + 2);
-            step(fb, p + 1, true);
-            fetch(fb, p + 3);
+        for (; p + 3 < n0; p += 4) {
+            step(f0, p, true);
+            fetch(f0, p + 4);
+            step(f1, p + 1, true);
+            fetch(f1, p + 5);
+            step(f2, p + 2, true);
+            fetch(f2, p + 6);
+            step(f3, p + 3, true);
+            fetch(f3, p + 7);
         }
-        if (p < n0) {              // odd count: bs < 64, the block ends here
-            step(fa, p, true);
-            ++p;
+        if (p < n0) {              // bs < 64: the block ends within this ring turn
+            step(f0, p, true);
+            if (p + 1 < n0) step(f1, p + 1, true);
+            if (p + 2 < n0) step(f2, p + 2, true);
+        } else if (bs > 64) {
+            // position 64 is lane 0 of c1, already updated with delta_63
+            cpo = readlane_d(c1, 0);
+            dprev = 0.0;
+            for (; p + 3 < bs; p += 4) {
+                step(f0, p, false);
+                fetch(f0, p + 4);
+                step(f1, p + 1, false);
+                fetch(f1, p + 5);
+                step(f2, p + 2, false);
+                fetch(f2, p + 6);
+                step(f3, p + 3, false);
+                fetch(f3, p + 7);
+            }
+            if (p < bs) {
+                step(f0, p, false);
+                if (p + 1 < bs) step(f1, p + 1, false);
+                if (p + 2 < bs) step(f2, p + 2, false);
+            }
         }
-        for (; p + 1 < bs; p += 2) {
-            step(fa, p, false);
-            fetch(fa, p + 2);
-            step(fb, p + 1, false);
-            fetch(fb, p + 3);
-        }
-        if (p < bs) step(fa, p, false);
+        // delta = x_new - x, the same subtraction as in the step
+        const double d0 = xo0 - x0, d1 = xo1 - x1;
         double* __restrict__ db = delta + (size_t)(b & 1) * B;
         if (q0 < bs) {
             db[q0] = d0;
@@ -304,10 +371,32 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
     const int ic = rok ? i : 0;
     __syncthreads();
     double rv = rok ? I.r[i] : 0.0;
+    // Both phases' reads of A are issued before either is used (the dot
+    // phase reads A_{J_k}, which does not depend on the residual update).
+    const int part = tid & 7, slot = tid >> 3;
+    double av[B / 8];                   // update: row i, columns grp + 8 t of block k-2
+    double bv[2][8];                    // dot: column slot + 64 h, rows part + 8 e
+    if (upd && qs == B) {               // every block but the last
+#pragma unroll
+        for (int t = 0; t < B / 8; ++t) av[t] = (double)A[(long long)sip[grp + 8 * t] * lda + ic];
+    }
+    if (dot) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long base = (long long)sic[min(slot + 64 * h, bs - 1)] * lda;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bv[h][e] = (double)A[base + min(r0 + part + 8 * e, m - 1)];
+        }
+    }
     if (upd) {
         double s = 0.0;
+        if (qs == B) {
+#pragma unroll
+            for (int t = 0; t < B / 8; ++t) s = fma(av[t], sdl[grp + 8 * t], s);
+        } else {
 #pragma unroll 4
-        for (int q = grp; q < qs; q += 8) s = fma((double)A[(long long)sip[q] * lda + ic], sdl[q], s);
+            for (int q = grp; q < qs; q += 8) s = fma((double)A[(long long)sip[q] * lda + ic], sdl[q], s);
+        }
         sp[grp * RW + row] = s;
         __syncthreads();
         if (grp == 0) {
@@ -319,19 +408,13 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
     if (!dot) return;
     if (grp == 0) sr[row] = rok ? rv : 0.0;
     __syncthreads();
-    const int part = tid & 7, slot = tid >> 3;
     double* __restrict__ pgk = pg + (size_t)(k & 1) * nchunks * B + (size_t)blockIdx.x * B;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int q = slot + 64 * h;
-        const long long base = (long long)sic[min(q, bs - 1)] * lda;
         double v = 0.0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int rr = part + 8 * e;
-            const int ii = min(r0 + rr, m - 1);
-            v = fma((double)A[base + ii], sr[rr], v);
-        }
+        for (int e = 0; e < 8; ++e) v = fma(bv[h][e], sr[part + 8 * e], v);
         v += dpp_move<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
         v += dpp_move<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
         v += dpp_move<0x141, 0xF>(v);    // row_half_mirror: the two quads of 8 lanes
