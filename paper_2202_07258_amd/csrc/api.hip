@@ -733,8 +733,11 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
                 BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, first, D.nritems, D.n_nritems));
             } else if (cp) {
                 BXS_HIP(launch_reduce(c, kRedCP, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
-            } else {
-                // fresh residual from the updated iterate
+            } else if (!P.cdb || k == kk - 1) {
+                // fresh residual from the updated iterate.  The block sweep keeps r
+                // current itself (r -= A_J delta_J per block), so it needs this only
+                // before a screening pass, whose rounding bounds take r = y' - A x
+                // formed afresh.
                 for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeAx, D.items[b], D.n_items[b]));
                 BXS_HIP(launch_reduce(c, kRedResidual, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
             }
