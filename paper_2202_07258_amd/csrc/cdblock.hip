@@ -24,6 +24,7 @@
 #include "dev_common.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace bxs {
 
@@ -155,7 +156,7 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
     const int nA = S.n_active;
     const int nb = (nA + B - 1) / B;
     const int tid = threadIdx.x;
-    __shared__ __align__(16) double smem[B * B + 20 * B];
+    __shared__ __align__(16) double smem[B * B + 21 * B];
     __shared__ int sj[2 * B];
 
     if (blockIdx.x == nchunks) {
@@ -165,11 +166,15 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
             if (k == nb + 1 && tid == 0) S.cdb_n = gram_tag(nA);  // this sweep's blocks are the current list's
             return;
         }
-        double* G = smem;
-        double* sg = smem + B * B;          // [8][B] chunk-group sums of g
+        // the per-step scalars first, at LDS addresses a read's immediate
+        // offset reaches; the Gram block last
+        double* sq = smem;                  // [B][4] x, l, u, 1 / ||a||^2
+        double* sxn = sq + 4 * B;           // [B] new x of each position
+        double* sg = sxn + B;               // [8][B] chunk-group sums of g
         double* sc = sg + 8 * B;            // [8][B] cross-term partials
-        double* sq = sc + 8 * B;            // [B][4] x, l, u, 1 / ||a||^2
+        double* G = sc + 8 * B;             // [B][B] Gram block
         const int p0 = b * B, bs = min(B, nA - p0);
+        int nn_form = 1;
         {
             // Every global read of the prologue is issued before its results
             // are used: the Gram block and the cross block as 16-byte loads,
@@ -229,14 +234,18 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
                 const bool v = tid < bs;
                 const int j = v ? I.idx[p0 + tid] : 0;
                 const double c2 = v ? I.cn2[j] : 0.0;
+                const double lj = v ? lo_of(I.l, j) : 0.0, uj = v ? up_of(I.u, j) : HUGE_VAL;
                 sj[tid] = j;
                 sq[4 * tid + 0] = v ? I.x[j] : 0.0;
-                sq[4 * tid + 1] = v ? lo_of(I.l, j) : 0.0;
-                sq[4 * tid + 2] = v ? up_of(I.u, j) : 0.0;
+                sq[4 * tid + 1] = lj;
+                sq[4 * tid + 2] = uj;
                 sq[4 * tid + 3] = (c2 > 0.0) ? 1.0 / c2 : 0.0;
+                nn_form = (lj == 0.0 && uj == HUGE_VAL) ? 1 : 0;
             }
         }
-        __syncthreads();
+        // every position of the block has l = 0 and u = +inf (the NNLS form):
+        // the projection is then max(t, 0), one operation on the step chain
+        const int all_nn = __syncthreads_and(nn_form);
         if (tid >= 64) return;
         const int lane = tid, q0 = lane, q1 = lane + 64;
         auto sum8 = [&](const double* a, int qq) {
@@ -245,7 +254,8 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
         };
         double c0 = sum8(sg, q0) - sum8(sc, q0);
         double c1 = sum8(sg, q1) - sum8(sc, q1);
-        // The step-to-step chain is kept to five dependent operations: c_p is
+        // The step-to-step chain is kept to five dependent operations (four
+        // for a block in the NNLS form, whose projection is max(t, 0)): c_p is
         // finished as a uniform value, c_p = c'_p - G[p-1][p] delta_{p-1},
         // where c'_p (every update up to delta_{p-2}) was read from its lane
         // one step earlier, before that lane's own update with delta_{p-1};
@@ -254,81 +264,87 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
         // G[p-1][p] delta_{p-1} is the same fma that lane p does, so c_p is
         // the value it would hold.  Column p of the Gram block and position
         // p's scalars are read four steps ahead into a ring of four register
-        // sets (the loop is unrolled by four, so no set is copied).  A zero
+        // sets (the loop is unrolled by four, so no set is copied); lane 0
+        // records the four new x values of a turn in LDS.  A zero
         // column has 1 / ||a||^2 = 0 and c_p = 0: its step x + 0 is x (x stays
         // inside the box), delta = 0.
         const double x0 = sq[4 * q0], x1 = sq[4 * q1];
-        double xo0 = x0, xo1 = x1;
-        struct Buf {
-            double g0, g1, gu;
-            double4v s;
-        };
-        auto fetch = [&](Buf& f, int p) {
-            const int pc = min(p, B - 1);
-            f.g0 = G[pc * B + q0];
-            f.g1 = G[pc * B + q1];
-            f.gu = G[max(pc - 1, 0) * B + pc];
-            f.s = ld4(sq, pc);
-            // keep the reads here, ahead of the steps that use them
-            __builtin_amdgcn_sched_barrier(0);
-        };
-        double cpo = readlane_d(c0, 0), dprev = 0.0;
-        auto step = [&](const Buf& f, int p, bool lo_half) {
-            const double cp = fma(-f.gu, dprev, cpo);
-            const double xn = fmin(fmax(f.s.x + cp * f.s.w, f.s.y), f.s.z);
-            const double d = xn - f.s.x;
-            cpo = readlane_d(lo_half ? c0 : c1, (p + 1) & 63);
-            const bool me = lane == (p & 63);
-            if (lo_half) {
-                xo0 = me ? xn : xo0;
-                c0 = fma(-f.g0, d, c0);
-            } else {
-                xo1 = me ? xn : xo1;
+        auto run = [&](auto nn) {
+            struct Buf {
+                double g0, g1, gu;
+                double4v s;
+            };
+            auto fetch = [&](Buf& f, int p) {
+                const int pc = min(p, B - 1);
+                f.g0 = G[pc * B + q0];
+                f.g1 = G[pc * B + q1];
+                f.gu = G[max(pc - 1, 0) * B + pc];
+                f.s = ld4(sq, pc);
+                // keep the reads here, ahead of the steps that use them
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            double cpo = readlane_d(c0, 0), dprev = 0.0;
+            // one step: returns the new x of position p (uniform)
+            auto step = [&](const Buf& f, int p, bool lo_half) {
+                const double cp = fma(-f.gu, dprev, cpo);
+                double xn;
+                if constexpr (decltype(nn)::value) xn = fmax(f.s.x + cp * f.s.w, 0.0);
+                else xn = fmin(fmax(f.s.x + cp * f.s.w, f.s.y), f.s.z);
+                const double d = xn - f.s.x;
+                cpo = readlane_d(lo_half ? c0 : c1, (p + 1) & 63);
+                if (lo_half) c0 = fma(-f.g0, d, c0);
+                c1 = fma(-f.g1, d, c1);
+                dprev = d;
+                return xn;
+            };
+            // four steps of the ring, their new x recorded by lane 0 afterwards
+            auto turn = [&](Buf& fa, Buf& fb, Buf& fc, Buf& fd, int p, bool lo_half) {
+                const double xa = step(fa, p, lo_half);
+                fetch(fa, p + 4);
+                const double xb = step(fb, p + 1, lo_half);
+                fetch(fb, p + 5);
+                const double xc = step(fc, p + 2, lo_half);
+                fetch(fc, p + 6);
+                const double xd = step(fd, p + 3, lo_half);
+                fetch(fd, p + 7);
+                if (lane == 0) {
+                    sxn[p] = xa;
+                    sxn[p + 1] = xb;
+                    sxn[p + 2] = xc;
+                    sxn[p + 3] = xd;
+                }
+            };
+            auto tail = [&](Buf& fa, Buf& fb, Buf& fc, int p, int end, bool lo_half) {
+                const double xa = step(fa, p, lo_half);
+                const double xb = (p + 1 < end) ? step(fb, p + 1, lo_half) : 0.0;
+                const double xc = (p + 2 < end) ? step(fc, p + 2, lo_half) : 0.0;
+                if (lane == 0) {
+                    sxn[p] = xa;
+                    if (p + 1 < end) sxn[p + 1] = xb;
+                    if (p + 2 < end) sxn[p + 2] = xc;
+                }
+            };
+            Buf f0, f1, f2, f3;
+            fetch(f0, 0);
+            fetch(f1, 1);
+            fetch(f2, 2);
+            fetch(f3, 3);
+            const int n0 = min(bs, 64);
+            int p = 0;
+            for (; p + 3 < n0; p += 4) turn(f0, f1, f2, f3, p, true);
+            if (p < n0) {              // bs < 64: the block ends within this ring turn
+                tail(f0, f1, f2, p, n0, true);
+            } else if (bs > 64) {
+                // position 64 is lane 0 of c1, already updated with delta_63
+                cpo = readlane_d(c1, 0);
+                dprev = 0.0;
+                for (; p + 3 < bs; p += 4) turn(f0, f1, f2, f3, p, false);
+                if (p < bs) tail(f0, f1, f2, p, bs, false);
             }
-            c1 = fma(-f.g1, d, c1);
-            dprev = d;
         };
-        Buf f0, f1, f2, f3;
-        fetch(f0, 0);
-        fetch(f1, 1);
-        fetch(f2, 2);
-        fetch(f3, 3);
-        const int n0 = min(bs, 64);
-        int p = 0;
-        for (; p + 3 < n0; p += 4) {
-            step(f0, p, true);
-            fetch(f0, p + 4);
-            step(f1, p + 1, true);
-            fetch(f1, p + 5);
-            step(f2, p + 2, true);
-            fetch(f2, p + 6);
-            step(f3, p + 3, true);
-            fetch(f3, p + 7);
-        }
-        if (p < n0) {              // bs < 64: the block ends within this ring turn
-            step(f0, p, true);
-            if (p + 1 < n0) step(f1, p + 1, true);
-            if (p + 2 < n0) step(f2, p + 2, true);
-        } else if (bs > 64) {
-            // position 64 is lane 0 of c1, already updated with delta_63
-            cpo = readlane_d(c1, 0);
-            dprev = 0.0;
-            for (; p + 3 < bs; p += 4) {
-                step(f0, p, false);
-                fetch(f0, p + 4);
-                step(f1, p + 1, false);
-                fetch(f1, p + 5);
-                step(f2, p + 2, false);
-                fetch(f2, p + 6);
-                step(f3, p + 3, false);
-                fetch(f3, p + 7);
-            }
-            if (p < bs) {
-                step(f0, p, false);
-                if (p + 1 < bs) step(f1, p + 1, false);
-                if (p + 2 < bs) step(f2, p + 2, false);
-            }
-        }
+        if (all_nn) run(std::true_type{});
+        else run(std::false_type{});
+        const double xo0 = (q0 < bs) ? sxn[q0] : x0, xo1 = (q1 < bs) ? sxn[q1] : x1;
         // delta = x_new - x, the same subtraction as in the step
         const double d0 = xo0 - x0, d1 = xo1 - x1;
         double* __restrict__ db = delta + (size_t)(b & 1) * B;
