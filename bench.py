@@ -195,6 +195,10 @@ def main():
     ap.add_argument("--c4-oracle-budget", type=float, default=60.0,
                     help="host seconds for the C4 oracle sample (smallest instances first)")
     ap.add_argument("--c5-iters", type=int, default=20000)
+    ap.add_argument("--table1-n", type=int, nargs="+", default=[1000, 2000, 4000, 6000],
+                    help="Tab. 1 column counts to run (m = 2000)")
+    ap.add_argument("--table1-budget", type=int, default=0,
+                    help="sweep budget per Tab. 1 solve (0: 100000 for n <= 2000, else 20000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling rocprofv3 byte counters) and exit")
     args = ap.parse_args()

@@ -595,12 +595,12 @@ def bench_table1(args, device):
     out = {"workload": "Paper Table 1 setup: NNLS m=2000, |N(0,1)| entries, x-bar 5% |N(0,1)|, noise N(0,1); "
                        "CD, screening every 10 sweeps, gap 1e-6",
            "rows": []}
-    for n in (1000, 2000, 4000, 6000):
+    for n in args.table1_n:
         P = W.table1_nnls(0, 2000, n)
         A, y, _, _ = _upload(P, device)
-        row = {"n": n, "paper_baseline_s": paper[n][0], "paper_screened_s": paper[n][1]}
+        row = {"n": n, "paper_baseline_s": paper.get(n, (None, None))[0], "paper_screened_s": paper.get(n, (None, None))[1]}
         # n >= 4000: a budget of 20000 sweeps (the gap reached is reported)
-        budget = 100000 if n <= 2000 else 20000
+        budget = args.table1_budget or (100000 if n <= 2000 else 20000)
         for screening in (True, False):
             kw = dict(solver="cd", screening=screening, screen_every=10, eps_gap=1e-6, max_iter=budget)
             bx.solve_nnls(A, y, **dict(kw, max_iter=20))
