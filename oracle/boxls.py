@@ -8,6 +8,13 @@ Problem (Sec. 2, eq. LR, with the least-squares fidelity of Sec. 5):
     subject to l <= x <= u,   l finite, u_j in R or +inf.
 Non-negative LS is l = 0, u = +inf; bounded-variable LS has every u_j finite.
 
+A second fidelity with a Lipschitz gradient, the case of eq. GAP_Safe_sph
+with alpha = 1 / L (Sec. 3.3): the Huber function of the residual,
+    f(z; y) = h_delta(y - z),  h_delta(s) = s^2 / 2 for |s| <= delta,
+                                          delta |s| - delta^2 / 2 otherwise,
+whose derivative psi_delta(s) = clip(s, -delta, delta) is 1-Lipschitz, so
+alpha = 1 as for LS.  The keyword ``delta`` selects it; delta = +inf is LS.
+
 Conventions: A is an (m, n) array (any memory order), vectors are 1-D FP64
 arrays, J_inf = {j : u_j = +inf}.  For the negative and positive parts we use
 [z]^- = min(0, z) and [z]^+ = max(0, z) (Sec. 1, Notations).
@@ -25,27 +32,58 @@ INF = math.inf
 # ---------------------------------------------------------------------------
 # Objectives (Sec. 2 eq. LR; Sec. 3.1 eqs. Dual_obj and Dual_set; Sec. 5)
 # ---------------------------------------------------------------------------
-def primal(A, y, x) -> float:
-    """P(x) = 1/2 ||Ax - y||^2 (eq. LR with the LS fidelity of Sec. 5)."""
-    r = np.asarray(A, dtype=np.float64) @ x - y
-    return 0.5 * float(r @ r)
+def huber(s, delta=INF):
+    """h_delta(s) entrywise: s^2 / 2 for |s| <= delta, delta |s| - delta^2 / 2
+    beyond (delta = +inf: s^2 / 2)."""
+    s = np.asarray(s, dtype=np.float64)
+    a = np.abs(s)
+    out = 0.5 * s * s
+    big = a > delta
+    if np.any(big):
+        out = np.where(big, 0.0, out)
+        out[big] = delta * a[big] - 0.5 * delta * delta
+    return out
 
 
-def fconj(v, y):
-    """Fenchel conjugate of f(.; y) = 1/2 (. - y)^2 (Sec. 5):
-    f*(v; y) = 1/2 ((y + v)^2 - y^2), applied entrywise."""
-    return 0.5 * ((y + v) ** 2 - y ** 2)
+def huber_grad(s, delta=INF):
+    """psi_delta(s) = h_delta'(s) = clip(s, -delta, delta)."""
+    return np.clip(np.asarray(s, dtype=np.float64), -delta, delta)
 
 
-def dual(A, y, l, u, theta) -> float:
+def huber_conj(v, delta=INF):
+    """h_delta*(v) = v^2 / 2 for |v| <= delta, +inf otherwise (entrywise)."""
+    v = np.asarray(v, dtype=np.float64)
+    return np.where(np.abs(v) <= delta, 0.5 * v * v, INF)
+
+
+def primal(A, y, x, delta=INF) -> float:
+    """P(x) = sum_i f([Ax]_i; y_i): 1/2 ||Ax - y||^2 for LS (eq. LR with the
+    LS fidelity of Sec. 5), sum_i h_delta(y_i - [Ax]_i) for the Huber one."""
+    r = y - np.asarray(A, dtype=np.float64) @ x
+    if not math.isfinite(delta):
+        return 0.5 * float(r @ r)
+    return float(np.sum(huber(r, delta)))
+
+
+def fconj(v, y, delta=INF):
+    """Fenchel conjugate of f(.; y) = h_delta(y - .), entrywise:
+    f*(v; y) = sup_z v z - h_delta(y - z) = v y + h_delta*(-v); for LS
+    (delta = +inf) this is 1/2 ((y + v)^2 - y^2) (Sec. 5)."""
+    if not math.isfinite(delta):
+        return 0.5 * ((y + v) ** 2 - y ** 2)
+    return v * y + huber_conj(-v, delta)
+
+
+def dual(A, y, l, u, theta, delta=INF) -> float:
     """Dual objective, eq. Dual_obj (Sec. 3.1):
     D(theta) = - sum_i f*(-theta_i; y_i) - sum_j l_j [A^T theta]^-_j
                - sum_{j not in J_inf} u_j [A^T theta]^+_j.
-    Evaluated as written; feasibility (eq. Dual_set) is a separate check."""
+    Evaluated as written; feasibility (eq. Dual_set, and |theta_i| <= delta
+    for the Huber fidelity, where f* is finite) is a separate check."""
     A = np.asarray(A, dtype=np.float64)
     c = A.T @ theta
     fin = np.isfinite(u)
-    val = -float(np.sum(fconj(-theta, y)))
+    val = -float(np.sum(fconj(-theta, y, delta)))
     val -= float(np.sum(l * np.minimum(c, 0.0)))
     val -= float(np.sum(u[fin] * np.maximum(c[fin], 0.0)))
     return val
@@ -60,12 +98,12 @@ def dual_feasible(A, u, theta, tol: float = 0.0) -> bool:
     return bool(np.all(A[:, J].T @ theta <= tol))
 
 
-def duality_gap(A, y, l, u, x, theta) -> float:
+def duality_gap(A, y, l, u, x, theta, delta=INF) -> float:
     """Gap(x, theta) = P(x) - D(theta), eq. Dual_Gap (Sec. 3.3)."""
-    return primal(A, y, x) - dual(A, y, l, u, theta)
+    return primal(A, y, x, delta) - dual(A, y, l, u, theta, delta)
 
 
-def gap_per_coordinate(A, y, l, u, x, theta) -> float:
+def gap_per_coordinate(A, y, l, u, x, theta, delta=INF) -> float:
     """Gap(x, theta) = P(x) - D(theta) (eq. Dual_Gap) rewritten as a sum of
     per-coordinate terms, the form the screening loop evaluates.
 
@@ -80,7 +118,14 @@ def gap_per_coordinate(A, y, l, u, x, theta) -> float:
     No two large numbers are subtracted, so rounding cannot drive the value
     toward zero while a coordinate inside the box still has a correlation of
     its own (its term keeps the radius sqrt(2 Gap) above that correlation),
-    unlike P - D, whose two sides are each of the size of 1/2 ||y||^2."""
+    unlike P - D, whose two sides are each of the size of 1/2 ||y||^2.
+
+    Huber fidelity: the same derivation with f*(v; y) = v y + h*(-v) gives
+    the row terms h(rho_i) + h*(theta_i) - theta_i rho_i (>= 0, the
+    Fenchel-Young gap) in place of 1/2 (rho_i - theta_i)^2.  For |rho_i| <=
+    delta they are 1/2 (rho_i - theta_i)^2 again; beyond, with s = sign(rho_i),
+    1/2 (theta_i - s delta)^2 + (|rho_i| - delta)(delta - s theta_i), two
+    non-negative parts for |theta_i| <= delta (no cancellation either)."""
     A = np.asarray(A, dtype=np.float64)
     rho = y - A @ x
     c = A.T @ theta
@@ -90,16 +135,26 @@ def gap_per_coordinate(A, y, l, u, x, theta) -> float:
     terms[fin] += (u[fin] - x[fin]) * pos[fin]
     terms[~fin] -= x[~fin] * pos[~fin]
     d = rho - theta
-    return float(np.sum(terms)) + 0.5 * float(d @ d)
+    if not math.isfinite(delta):
+        return float(np.sum(terms)) + 0.5 * float(d @ d)
+    if np.any(np.abs(theta) > delta):
+        return INF                                  # theta outside dom h*
+    rows = 0.5 * d * d
+    out = np.abs(rho) > delta
+    if np.any(out):
+        sg, th, ar = np.sign(rho[out]), theta[out], np.abs(rho[out])
+        rows[out] = 0.5 * (th - sg * delta) ** 2 + (ar - delta) * (delta - sg * th)
+    return float(np.sum(terms)) + float(np.sum(rows))
 
 
 # ---------------------------------------------------------------------------
 # Dual points (Sec. 4)
 # ---------------------------------------------------------------------------
-def residual_dual_point(A, y, x):
-    """Theta(x) = -grad F(Ax; y) = y - Ax for the LS fidelity
-    (eq. BVLR_dual_up, Sec. 4.1)."""
-    return y - np.asarray(A, dtype=np.float64) @ x
+def residual_dual_point(A, y, x, delta=INF):
+    """Theta(x) = -grad F(Ax; y) (eq. BVLR_dual_up, Sec. 4.1): y - Ax for
+    the LS fidelity, psi_delta(y - Ax) for the Huber one."""
+    r = y - np.asarray(A, dtype=np.float64) @ x
+    return r if not math.isfinite(delta) else huber_grad(r, delta)
 
 
 def translate(A, z, t, J):
@@ -163,20 +218,22 @@ def translation_direction(A, choice: str):
     return -B[:, j].copy(), j
 
 
-def dual_point(A, y, u, x, t):
+def dual_point(A, y, u, x, t, delta=INF):
     """The dual update Theta(x) used by the screening loop.
 
-    * No infinite upper bound (BVLR): theta = y - Ax (Sec. 4.1).
+    * No infinite upper bound (BVLR): theta = -grad F(Ax; y) (Sec. 4.1).
     * Otherwise dual translation of y - Ax along t (Sec. 4.2) over J_inf.
     * If t is not in Int(F_D) for this matrix (possible for signed A, where
       Prop. 2 offers no direction), the always-feasible theta = 0 is used
       (D(0) = 0), so the gap equals P(x) and nothing can be screened.
+    * Huber fidelity with some u_j = +inf: theta = 0 as well (a translation
+      along t can leave the box |theta_i| <= delta where f* is finite).
     Returns (theta, eps, t_valid)."""
-    z = residual_dual_point(A, y, x)
+    z = residual_dual_point(A, y, x, delta)
     J = ~np.isfinite(u)
     if not np.any(J):
         return z, 0.0, True
-    if not interior_direction_ok(A, u, t):
+    if math.isfinite(delta) or not interior_direction_ok(A, u, t):
         return np.zeros_like(z), 0.0, False
     theta, eps = translate(A, z, t, J)
     return theta, eps, True
@@ -213,11 +270,13 @@ def project(x, l, u):
     return np.minimum(np.maximum(x, l), u)
 
 
-def pg_step(A, y, l, u, x, eta):
+def pg_step(A, y, l, u, x, eta, delta=INF):
     """One projected-gradient step x <- Pi_[l,u](x - eta grad P(x)) with
-    grad P(x) = -A^T (y - Ax) (eq. grad, Sec. 4.1)."""
+    grad P(x) = -A^T (y - Ax) (eq. grad, Sec. 4.1), -A^T psi_delta(y - Ax)
+    for the Huber fidelity."""
     A = np.asarray(A, dtype=np.float64)
-    g = A.T @ (y - A @ x)
+    r = y - A @ x
+    g = A.T @ (r if not math.isfinite(delta) else huber_grad(r, delta))
     return project(x + eta * g, l, u)
 
 
@@ -347,7 +406,8 @@ def oracle_dual_point(A, u, theta_star, t):
 
 def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
           max_iter: int = 100000, step: float | None = None, t=None,
-          screening: bool = True, x0=None, keep_theta: bool = False, theta_star=None) -> Result:
+          screening: bool = True, x0=None, keep_theta: bool = False, theta_star=None,
+          huber_delta: float = INF) -> Result:
     """Alg. 1 with the least-squares simplification of Remark 3.
 
     Each pass:
@@ -380,7 +440,10 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
     the history (for the safe-sphere checks).
     ``theta_star`` (a known dual optimum) replaces the dual update by
     ``oracle_dual_point`` at every pass: the experiment of Sec. 5.1 that
-    measures how much screening the dual update leaves undone (Fig. 3)."""
+    measures how much screening the dual update leaves undone (Fig. 3).
+    ``huber_delta`` (finite) selects the Huber fidelity (module docstring)
+    with the PG solver: its gradient, dual point, objectives and gap; the
+    radius keeps alpha = 1."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     y = np.asarray(y, dtype=np.float64)
@@ -389,6 +452,9 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
     t = -np.ones(m) if t is None else np.asarray(t, dtype=np.float64)
     if solver not in ("pg", "cd", "cp"):
         raise ValueError(solver)
+    hd = float(huber_delta)
+    if math.isfinite(hd) and (solver != "pg" or theta_star is not None or not hd > 0.0):
+        raise ValueError("the Huber fidelity runs with the PG solver and the usual dual update, delta > 0")
     if solver == "cp":
         # tau = sigma = step, default 1 / (1.05 ||A||_2): tau sigma ||A||^2 < 1
         eta = (1.0 / (1.05 * np.sqrt(lipschitz(A)))) if step is None else float(step)
@@ -411,7 +477,7 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
         kk = min(K, max_iter - iters)
         for _ in range(kk):
             if solver == "pg":
-                xP = pg_step(AP, yp, lP, uP, xP, eta)
+                xP = pg_step(AP, yp, lP, uP, xP, eta, hd)
             elif solver == "cd":
                 xP = cd_sweep(AP, yp, lP, uP, xP)
             else:
@@ -419,12 +485,12 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
         iters += kk
         x[P] = xP
         if theta_star is None:
-            theta, eps, t_valid = dual_point(AP, yp, uP, xP, t)
+            theta, eps, t_valid = dual_point(AP, yp, uP, xP, t, hd)
         else:
             theta, eps, t_valid = oracle_dual_point(AP, uP, theta_star, t)
-        prim = primal(AP, yp, xP)
-        dl = dual(AP, yp, lP, uP, theta)
-        gap = gap_per_coordinate(AP, yp, lP, uP, xP, theta)
+        prim = primal(AP, yp, xP, hd)
+        dl = dual(AP, yp, lP, uP, theta, hd)
+        gap = gap_per_coordinate(AP, yp, lP, uP, xP, theta, hd)
         rad = safe_radius(gap)
         passes += 1
         hist.append({"iters": iters, "gap": gap, "gap_pd": prim - dl, "radius": rad, "n_active": int(P.size),
@@ -454,12 +520,13 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
 # ---------------------------------------------------------------------------
 # Exact optima and optimality checks (Sec. 3.2, eqs. optimality1-2; App. C)
 # ---------------------------------------------------------------------------
-def kkt_violation(A, y, l, u, x) -> float:
+def kkt_violation(A, y, l, u, x, delta=INF) -> float:
     """Largest violation of the optimality conditions eqs. optimality1-2 at x
-    with theta = y - Ax: |a_j^T theta| on free coordinates, (a_j^T theta)^+ at
-    lower bounds, (-a_j^T theta)^+ at upper bounds, plus box infeasibility."""
+    with theta = -grad F(Ax; y) (y - Ax for LS, psi_delta(y - Ax) for Huber):
+    |a_j^T theta| on free coordinates, (a_j^T theta)^+ at lower bounds,
+    (-a_j^T theta)^+ at upper bounds, plus box infeasibility."""
     A = np.asarray(A, dtype=np.float64)
-    g = A.T @ (y - A @ x)
+    g = A.T @ residual_dual_point(A, y, x, delta)
     at_l = x <= l
     at_u = (x >= u) & np.isfinite(u)
     free = ~(at_l | at_u)

@@ -178,6 +178,6 @@ def test_planted_mistake_gap_by_subtraction_is_caught(monkeypatch):
     the computed gap is noise, the radius collapses and free coordinates get
     screened."""
     monkeypatch.setattr(ob, "gap_per_coordinate",
-                        lambda A, y, l, u, x, theta: ob.duality_gap(A, y, l, u, x, theta))
+                        lambda A, y, l, u, x, theta, delta=math.inf: ob.duality_gap(A, y, l, u, x, theta, delta))
     with pytest.raises(AssertionError):
         check_floor_safety()
