@@ -66,11 +66,19 @@ typedef enum {
  * tau = sigma = opts->step or 1 / (1.05 sqrt(L_est)); the screening test uses
  * the residual dual point of Sec. 4 like the other solvers) */
 typedef enum { BXS_PG = 0, BXS_CD = 1, BXS_CP = 2 } bxs_solver;
-/* Data-fidelity term f of eq. LR.  Only the least-squares fidelity
- * f(z) = 1/2 ||z - y||^2 (alpha = 1 in eq. GAP_Safe_sph) is built; the
- * values after it are reserved for the other fidelities that Sec. 3.3 leaves
- * to local strong-concavity bounds, and are rejected with BXS_ERR_ARG. */
-typedef enum { BXS_FID_LS = 0 } bxs_fidelity;
+/* Data-fidelity term f of eq. LR.  BXS_FID_LS: f(z; y) = 1/2 (z - y)^2.
+ * BXS_FID_HUBER: f(z; y) = h(y - z) with h(s) = s^2/2 for |s| <= delta and
+ * delta |s| - delta^2/2 beyond (delta = opts->huber_delta), a fidelity whose
+ * gradient is 1-Lipschitz, so eq. GAP_Safe_sph keeps alpha = 1 (Sec. 3.3).
+ * Its dual update (Sec. 4.1) is theta = clip(y' - Ax, -delta, delta), which
+ * lies where f* is finite; the PG gradient is -A^T theta.  It runs with the PG
+ * solver of solve_bvls, solve_nnls, solve_bvls_varbatch and
+ * solve_bvls_noalloc, without opts->theta_star.  A preserved column with
+ * u_j = +inf makes the pass use theta = 0 (no translation: it could leave the
+ * box |theta_i| <= delta), so such problems are solved but not screened
+ * (info.t_valid = 0).  Fidelities that need the local strong-concavity bounds
+ * Sec. 3.3 mentions (KL, beta-divergences) are not built. */
+typedef enum { BXS_FID_LS = 0, BXS_FID_HUBER = 1 } bxs_fidelity;
 /* Storage type of A.  Every element is promoted exactly to FP64 before it is
  * used, so the problem solved is the one the stored values define; BXS_BF16
  * (bfloat16: 8-bit significand) halves the bytes of FP32 storage for the
@@ -157,10 +165,11 @@ typedef struct {
                                 problem of a batch.                                           */
     int     t_choice;        /* bxs_translation; with BXS_T_GIVEN opts->t applies, otherwise
                                 opts->t must be NULL                                           */
-    int     fidelity;        /* bxs_fidelity (BXS_FID_LS)                                      */
+    int     fidelity;        /* bxs_fidelity                                                    */
     int     deterministic;   /* 0 or 1.  Every reduction of the library sums in a fixed order
                                 and no kernel uses floating-point atomics, so results repeat
                                 bit for bit on the same device, inputs and options either way */
+    double  huber_delta;     /* delta > 0, finite, of BXS_FID_HUBER; ignored for BXS_FID_LS    */
 } bxs_opts;
 
 typedef struct {
@@ -172,7 +181,7 @@ typedef struct {
     long   n_lower;     /* coordinates screened at l                                    */
     long   n_upper;     /* coordinates screened at u                                    */
     double gap;         /* certified gap at the returned x                              */
-    double primal;      /* 1/2 ||Ax - y||^2 at the returned x                           */
+    double primal;      /* P(x) at the returned x: 1/2 ||Ax - y||^2, or the Huber sum    */
     double radius;      /* last safe radius                                             */
     double eps;         /* last translation coefficient                                 */
     double step;        /* PG step used                                                 */

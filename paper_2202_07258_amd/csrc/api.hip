@@ -228,8 +228,14 @@ static bxs_status check_opts(const bxs_opts* o)
     if (o->t_choice < BXS_T_GIVEN || o->t_choice > BXS_T_NORMAL_EQUATIONS)
         return fail(BXS_ERR_ARG, "unknown t_choice %d", o->t_choice);
     if (o->t_choice != BXS_T_GIVEN && o->t) return fail(BXS_ERR_ARG, "t_choice computes t: opts->t must be NULL");
-    if (o->fidelity != BXS_FID_LS)
-        return fail(BXS_ERR_ARG, "fidelity %d: only the least-squares fidelity (BXS_FID_LS) is built", o->fidelity);
+    if (o->fidelity != BXS_FID_LS && o->fidelity != BXS_FID_HUBER)
+        return fail(BXS_ERR_ARG, "unknown fidelity %d", o->fidelity);
+    if (o->fidelity == BXS_FID_HUBER) {
+        if (!(o->huber_delta > 0.0) || isinf(o->huber_delta))
+            return fail(BXS_ERR_ARG, "huber_delta must be finite and > 0");
+        if (o->solver != BXS_PG) return fail(BXS_ERR_ARG, "the Huber fidelity runs with the PG solver");
+        if (o->theta_star) return fail(BXS_ERR_ARG, "the Huber fidelity takes no theta_star");
+    }
     if (o->deterministic != 0 && o->deterministic != 1) return fail(BXS_ERR_ARG, "deterministic must be 0 or 1");
     return BXS_OK;
 }
@@ -512,6 +518,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     for (long i = 0; i < count; ++i) {
         P.insts[i].t = P.tdir ? P.tbuf : t;
         P.insts[i].ts = o->theta_star;
+        P.insts[i].hub = (o->fidelity == BXS_FID_HUBER) ? o->huber_delta : HUGE_VAL;
     }
 
     // device tables
@@ -755,7 +762,9 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
         }
         BXS_HIP(launch_screen(c, (int)count, o->eps_gap, o->screening, final_pass, K, (int)kk, pg ? 1 : 0,
                               host_done, (host_done && count == 1) ? hgap + slot : nullptr,
-                              (host_done && poll) ? hseq : nullptr, o->theta_star != nullptr));
+                              (host_done && poll) ? hseq : nullptr,
+                              o->theta_star ? kScreenOracleDual
+                                            : (o->fidelity == BXS_FID_HUBER ? kScreenHuber : kScreenLS)));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
@@ -1192,6 +1201,7 @@ static bxs_status check_batched(long m, long n, long B, int a_dtype, const void*
     bxs_status s = check_opts(opts);
     if (s != BXS_OK) return s;
     if (opts->solver != BXS_PG) return fail(BXS_ERR_ARG, "the batched shared-matrix solver runs projected gradient");
+    if (opts->fidelity != BXS_FID_LS) return fail(BXS_ERR_ARG, "the batched shared-matrix solver is least squares only");
     if (a_dtype != BXS_F64 && a_dtype != BXS_F32) return fail(BXS_ERR_ARG, "unknown a_dtype %d", a_dtype);
     if (m < 1 || n < 1 || B < 1) return fail(BXS_ERR_SHAPE, "m=%ld n=%ld B=%ld must be >= 1", m, n, B);
     if (lda < m || ldy < m || ldx < n || ldsat < n) return fail(BXS_ERR_SHAPE, "a leading dimension is too small");
@@ -1236,6 +1246,7 @@ static bxs_status adjoint_common(long m, long n, long B, int a_dtype, const void
     if (!opts) return fail(BXS_ERR_ARG, "opts is NULL");
     if (opts->max_iter < 1) return fail(BXS_ERR_ARG, "max_iter must be >= 1");
     if (!(opts->eps_gap >= 0.0) || isinf(opts->eps_gap)) return fail(BXS_ERR_ARG, "eps_gap must be finite and >= 0");
+    if (opts->fidelity != BXS_FID_LS) return fail(BXS_ERR_ARG, "the adjoint is for the least-squares fidelity");
     if (a_dtype != BXS_F64 && a_dtype != BXS_F32) return fail(BXS_ERR_ARG, "unknown a_dtype %d", a_dtype);
     if (m < 1 || n < 1 || B < 1) return fail(BXS_ERR_SHAPE, "m=%ld n=%ld B=%ld must be >= 1", m, n, B);
     if (lda < m || ldy < m || ldx < n || ldg < n || lddy < m || (dA && ldda < m) || (dl && lddl < n) ||

@@ -58,6 +58,7 @@ struct Inst {
     int item_base;          // first work item of this instance in its bucket list
     int lz_steps;           // Lanczos steps of the ||A||_2^2 estimate (0: step given)
     double* lz;             // [2 lz_steps + 2 m] alpha, beta, q_k, q_{k-1}
+    double hub;             // Huber threshold delta of the fidelity; +inf for least squares
 };
 
 struct State {
@@ -288,10 +289,12 @@ hipError_t launch_count_free(const LaunchCtx& c, int count);
 // double that receives the gap of instance 0 (single-instance calls), or
 // nullptr; host_seq: pinned (coherent) host word that receives the number of
 // screening passes run, written last with a system-scope release, or nullptr;
-// oracle_dual: the instances carry a given dual optimum (Inst::ts).
+// kind: kScreenLS; kScreenOracleDual (the instances carry a given dual
+// optimum, Inst::ts); kScreenHuber (the Huber fidelity, Inst::hub).
+enum ScreenKind : int { kScreenLS = 0, kScreenOracleDual = 1, kScreenHuber = 2 };
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening,
                          int final_pass, int K, int kk, int ahead, int* host_done, double* host_gap,
-                         int* host_seq, int oracle_dual);
+                         int* host_seq, int kind);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
 // translation direction computed from A (tdir.hip, one instance)
 size_t tdir_scratch_doubles(long m, long n);

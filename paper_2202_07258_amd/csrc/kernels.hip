@@ -470,13 +470,16 @@ void k_lanczos(const Inst* __restrict__ insts, State* __restrict__ st, int k, in
 // e_j bounds |computed - exact| of a_j^T theta, delta_r bounds the residual
 // error, and each rounded sum, product and square root is pushed outward.
 // ---------------------------------------------------------------------------
-// OD selects the diagnostic mode with a given dual optimum (its own
-// instantiation, so the regular pass carries none of its registers).
-template <bool OD>
+// SK selects the pass: kScreenLS, kScreenOracleDual (the diagnostic mode
+// with a given dual optimum) or kScreenHuber (the Huber fidelity), each its
+// own instantiation, so the regular pass carries none of the others'
+// registers.
+template <int SK>
 __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, State* __restrict__ st,
                                             int* __restrict__ done_counter, double eps_gap, int screening,
                                             int final_pass, int K, int kk, int ahead)
 {
+    constexpr bool OD = SK == kScreenOracleDual;
     constexpr int NT = 1024;
     constexpr int E = 4;                       // consecutive preserved positions per thread per chunk
     constexpr int CH = NT * E;
@@ -614,7 +617,12 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
         tv = block_min<NT>(tvl, sh);
         emax = block_max<NT>(eml, sh);
     }
-    const bool fallback = has_inf && !(tv > 0.5);
+    // Huber fidelity: no translation for u_j = +inf columns (theta + eps t
+    // could leave the box |theta_i| <= delta where f* is finite), theta = 0
+    // instead
+    constexpr bool huber = SK == kScreenHuber;
+    const double hub = huber ? I.hub : 0.0;
+    const bool fallback = has_inf && (!(tv > 0.5) || huber);
     const double eps = (has_inf && !fallback) ? emax * (1.0 + 4.0 * u1) : 0.0;
     const double massall = (mass + S.mass_screened) * (1.0 + gamma_k((double)n + 64.0));
     const double delta_r = gamma_k(2.0 * n + 4.0 * passes + 64.0) * (S.ynorm + 2.0 * massall);
@@ -626,10 +634,28 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
         ej = c.cn * (e_g + gw * eps * tnorm) + 4.0 * u1 * (fabs(c.g) + eps * fabs(c.w));
     };
 
+    // Huber fidelity: its primal value sum_i h(r_i), h(s) = s^2 / 2 for
+    // |s| <= delta and delta (|s| - delta / 2) beyond (reported, and the gap
+    // of the theta = 0 fallback); one more pass over r
+    double hsum = 0.0;
+    if (huber) {
+        double ah = 0.0;
+        for (int i = tid; i < m; i += NT) {
+            const double ri = I.r[i], ar = fabs(ri);
+            ah += (ar <= hub) ? 0.5 * ri * ri : hub * (ar - 0.5 * hub);
+        }
+        hsum = block_sum<NT>(ah, sh);
+    }
     // gap: at eps = 0 the sweep already summed the per-column terms; with a
     // translation the terms change and are summed here in one more pass
     double G, zmax = z0;
-    if (fallback) {
+    if (fallback && huber) {
+        // theta = 0: the gap is P(x) = sum_i h(r_i) at the exact residual
+        // r = r~ + e, ||e|| <= delta_r; h is 1-smooth with |h'(r~_i)| <=
+        // |r~_i|, so P <= sum h(r~_i) + ||r~|| delta_r + delta_r^2 / 2
+        const double hb = hsum * (1.0 + gamma_k((double)(m / NT) + 24.0));
+        G = (hb + rnorm * delta_r + 0.5 * delta_r * delta_r) * (1.0 + 4.0 * u1);
+    } else if (fallback) {
         const double tt = rnorm + delta_r;
         G = 0.5 * tt * tt * (1.0 + 4.0 * u1);
     } else {
@@ -663,7 +689,7 @@ __device__ __forceinline__ void screen_pass(const Inst* __restrict__ insts, Stat
         G = (gsum * (1.0 + 3.0 * u1) + 0.5 * tt * tt * (1.0 + 4.0 * u1)) * (1.0 + gamma_k((double)n + 64.0));
     }
     const double rad = sqrt(2.0 * G) * (1.0 + 2.0 * u1);
-    const double primal = 0.5 * rsq;
+    const double primal = huber ? hsum : 0.5 * rsq;
     const bool stop = G < eps_gap;
     if (tid == 0) S.col_iters += (long long)nA * kk;
 
@@ -832,13 +858,13 @@ hipError_t launch_count_free(const LaunchCtx& c, int count)
 // it then stores the number of screening passes run so far (a counter after
 // the ticket) with a system-scope release, so the host can wait for the pass
 // by reading that word instead of a completion event.
-template <bool OD>
+template <int SK>
 __global__ __launch_bounds__(1024)
 void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
               double eps_gap, int screening, int final_pass, int K, int kk, int ahead, int* host_done,
               double* host_gap, int* host_seq)
 {
-    screen_pass<OD>(insts, st, done_counter, eps_gap, screening, final_pass, K, kk, ahead);
+    screen_pass<SK>(insts, st, done_counter, eps_gap, screening, final_pass, K, kk, ahead);
     if (host_done == nullptr) return;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1191,16 +1217,18 @@ hipError_t launch_cp_init(const LaunchCtx& c, int count)
 
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening, int final_pass,
                          int K, int kk, int ahead, int* host_done, double* host_gap, int* host_seq,
-                         int oracle_dual)
+                         int kind)
 {
-    if (oracle_dual)
-        k_screen<true><<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                                  final_pass, K, kk, ahead, host_done, host_gap,
-                                                                  host_seq);
+    const dim3 g(count), b(1024);
+    if (kind == kScreenOracleDual)
+        k_screen<kScreenOracleDual><<<g, b, 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
+                                                           final_pass, K, kk, ahead, host_done, host_gap, host_seq);
+    else if (kind == kScreenHuber)
+        k_screen<kScreenHuber><<<g, b, 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
+                                                      final_pass, K, kk, ahead, host_done, host_gap, host_seq);
     else
-        k_screen<false><<<dim3(count), dim3(1024), 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                                   final_pass, K, kk, ahead, host_done, host_gap,
-                                                                   host_seq);
+        k_screen<kScreenLS><<<g, b, 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
+                                                   final_pass, K, kk, ahead, host_done, host_gap, host_seq);
     return hipGetLastError();
 }
 

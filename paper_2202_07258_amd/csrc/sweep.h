@@ -81,6 +81,10 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
     // PG ascends along A^T r; Chambolle-Pock descends along A^T v
     const double eta = STP ? (CPM ? -S.step : S.step) : 0.0;
     const double* __restrict__ rsrc = CPM ? I.r2 : I.r;
+    // Huber fidelity: the gradient and the dual point use psi(r) =
+    // clip(r, -delta, delta) (delta = +inf for least squares: r itself)
+    constexpr bool HUB = (STP || SCR) && !CPM;
+    const double hub = HUB ? I.hub : 0.0;
     const double tnorm_c = SCR ? S.tnorm : 0.0;
 
     bool rowok[R];
@@ -99,7 +103,8 @@ void k_sweep(const Inst* __restrict__ insts, State* __restrict__ st, const Item*
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int row = (k * TPC + L) * V + e;
-                const double v = (row < m) ? rsrc[row] : 0.0;
+                double v = (row < m) ? rsrc[row] : 0.0;
+                if constexpr (HUB) v = fmin(fmax(v, -hub), hub);
                 if constexpr (RLDS) s_r[(k * V + e) * TPC + L] = v; else rl[k * V + e] = v;
             }
     }

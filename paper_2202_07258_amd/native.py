@@ -41,7 +41,8 @@ class Opts(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("history", C.POINTER(PassRecord)), ("history_cap", C.c_long), ("profile", C.c_int),
                 ("iter_precision", C.c_int), ("graph", C.c_int), ("theta_star", C.c_void_p),
-                ("t_choice", C.c_int), ("fidelity", C.c_int), ("deterministic", C.c_int)]
+                ("t_choice", C.c_int), ("fidelity", C.c_int), ("deterministic", C.c_int),
+                ("huber_delta", C.c_double)]
 
 
 class Info(C.Structure):
@@ -182,7 +183,7 @@ def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, 
               power_iters=0, t: torch.Tensor | None = None, history=0, stream=None,
               profile=False, iter_precision="f64", graph=False,
               theta_star: torch.Tensor | None = None, t_choice="given", fidelity="ls",
-              deterministic=True) -> tuple[Opts, Any]:
+              deterministic=True, huber_delta=0.0) -> tuple[Opts, Any]:
     lib = load()
     o = Opts()
     lib.bxs_default_opts(C.byref(o))
@@ -200,7 +201,8 @@ def make_opts(*, solver="pg", screening=True, screen_every=10, max_iter=100000, 
     o.graph = 1 if graph else 0
     o.theta_star = _ptr(theta_star)
     o.t_choice = T_CHOICES[t_choice] if isinstance(t_choice, str) else int(t_choice)
-    o.fidelity = {"ls": 0}[fidelity] if isinstance(fidelity, str) else int(fidelity)
+    o.fidelity = {"ls": 0, "huber": 1}[fidelity] if isinstance(fidelity, str) else int(fidelity)
+    o.huber_delta = float(huber_delta)
     o.deterministic = 1 if deterministic else 0
     hist = None
     if history:

@@ -36,9 +36,10 @@ def run_gpu(P, kind, **kw):
 
 
 def run_oracle(P, *, solver="pg", screen_every=10, eps_gap=1e-6, max_iter=100000, step=None,
-               screening=True, x0=None, t=None, theta_star=None):
+               screening=True, x0=None, t=None, theta_star=None, huber_delta=float("inf")):
     return ob.solve(P.A64(), P.y, P.l, P.u, solver=solver, K=screen_every, eps_gap=eps_gap,
-                    max_iter=max_iter, step=step, screening=screening, x0=x0, t=t, theta_star=theta_star)
+                    max_iter=max_iter, step=step, screening=screening, x0=x0, t=t, theta_star=theta_star,
+                    huber_delta=huber_delta)
 
 
 def assert_parity(P, xg, satg, info, res, xtol=1e-9, gap_rtol=1e-6, check_status=True):
@@ -57,7 +58,8 @@ def assert_parity(P, xg, satg, info, res, xtol=1e-9, gap_rtol=1e-6, check_status
     assert bool(info["t_valid"]) == res.t_valid
 
 
-ORACLE_KEYS = ("solver", "screen_every", "eps_gap", "max_iter", "step", "screening", "x0", "t", "theta_star")
+ORACLE_KEYS = ("solver", "screen_every", "eps_gap", "max_iter", "step", "screening", "x0", "t", "theta_star",
+               "huber_delta")
 
 
 def parity_vs_oracle(P, xg, sg, info, xtol=1e-9, **kw):

@@ -74,11 +74,32 @@ def test_shape_errors(lib, m, n, lda, code):
 
 @pytest.mark.parametrize("field,value", [("solver", 7), ("screening", 2), ("screen_every", 0),
                                          ("max_iter", 0), ("eps_gap", -1.0), ("eps_gap", float("inf")),
-                                         ("step", float("nan")), ("fidelity", 1), ("deterministic", 2)])
+                                         ("step", float("nan")), ("fidelity", 2), ("fidelity", 1),
+                                         ("deterministic", 2)])
 def test_option_errors(lib, field, value):
     o = _opts(lib, **{field: value})
     st = lib.solve_nnls(8, 8, 0, FAKE, 8, FAKE, FAKE, FAKE, C.byref(o), None)
     assert st == N.BXS_ERR_ARG
+
+
+@pytest.mark.parametrize("kw", [dict(huber_delta=0.0), dict(huber_delta=-1.0), dict(huber_delta=float("inf")),
+                                dict(huber_delta=float("nan")), dict(huber_delta=1.0, solver=N.BXS_CD),
+                                dict(huber_delta=1.0, solver=N.BXS_CP), dict(huber_delta=1.0, theta_star=FAKE)])
+def test_huber_option_errors(lib, kw):
+    # the Huber fidelity needs a finite delta > 0, the PG solver and no theta*
+    o = _opts(lib, fidelity=1, **kw)
+    assert lib.solve_nnls(8, 8, 0, FAKE, 8, FAKE, FAKE, FAKE, C.byref(o), None) == N.BXS_ERR_ARG
+    assert lib.bxs_last_error().decode()
+
+
+def test_huber_rejected_by_shared_matrix_solver_and_adjoint(lib):
+    o = _opts(lib, fidelity=1, huber_delta=1.0)
+    assert lib.solve_nnls_batched_shared(8, 8, 2, 0, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, C.byref(o), None) \
+        == N.BXS_ERR_ARG
+    assert "least squares" in lib.bxs_last_error().decode()
+    assert lib.nnls_adjoint(8, 8, 2, 0, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, None, 8, None, 8,
+                            C.byref(o), None) == N.BXS_ERR_ARG
+    assert "least-squares" in lib.bxs_last_error().decode()
 
 
 def test_normal_equations_direction_needs_tall_matrix(lib):
