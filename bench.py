@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16-storage leg of the C2 run")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="bound the oracle baseline to this many iterations (0: full solve)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "table1", "table2", "fig1", "sweep"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "table1", "table2", "fig1", "sweep", "huber"],
                     help="c2 (default): the headline workload; the others are measured separately")
     ap.add_argument("--sweep-m", type=int, default=8000)
     ap.add_argument("--sweep-n", type=int, default=16000)

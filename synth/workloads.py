@@ -287,6 +287,23 @@ def table2_bvls(rep: int, m: int, n: int) -> Problem:
     return Problem(A, y, np.zeros(n), np.ones(n), x, False, {"name": "table2", "kind": "bvls"})
 
 
+def huber_bvls(rep: int, m: int, n: int, dtype=np.float64, frac_out: float = 0.1) -> Problem:
+    """Input for the Huber fidelity (a fidelity with a 1-Lipschitz gradient,
+    eq. GAP_Safe_sph with alpha = 1): a tall matrix with N(0,1) entries
+    scaled to unit columns, x-bar ~ U(-3, 3) against the box [-1, 1] (so many
+    coordinates of the optimum sit on a bound), y = A x-bar + N(0, 0.05^2)
+    noise, and a fraction frac_out of the rows shifted by +-U(2, 5) (gross
+    outliers, the residuals the Huber function caps)."""
+    rng = rng_for(71, rep, m, n)
+    A = _colmajor(unit_columns(_gaussian(rng, m, n)), dtype)
+    x = rng.uniform(-3.0, 3.0, n)
+    y = np.asarray(A, dtype=np.float64) @ x + 0.05 * rng.standard_normal(m)
+    k = int(frac_out * m)
+    idx = rng.choice(m, k, replace=False)
+    y[idx] += rng.choice([-1.0, 1.0], k) * rng.uniform(2.0, 5.0, k)
+    return Problem(A, y, -np.ones(n), np.ones(n), None, False, {"name": "huber", "kind": "bvls"})
+
+
 def fig1_bvls(rep: int, m: int, n: int, b: float, dtype=np.float64) -> Problem:
     """The saturation-ratio experiment of Sec. 5.1 (Fig. 1): a_ij ~ N(0,1)
     (columns not normalised), y_i ~ N(0,1) drawn independently of A, box
