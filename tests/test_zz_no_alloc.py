@@ -59,6 +59,16 @@ def test_noalloc_matches_solve_bvls_two_calls():
     _check(ref, got, 1e-6)
 
 
+def test_noalloc_huber_matches_solve_bvls():
+    # the Huber fidelity through the fixed scratch: same kernels, same result
+    P = W.huber_bvls(3, 600, 250)
+    print("noalloc huber: 600x250 fp64", flush=True)
+    ref, got = _solve_both(P.A, P.y, P.l, P.u, fidelity="huber", huber_delta=0.5, screen_every=10, eps_gap=1e-8,
+                           max_iter=50000)
+    _check(ref, got, 1e-9)
+    assert np.count_nonzero(got[1]) > 0
+
+
 def test_noalloc_refuses_a_problem_larger_than_its_scratch():
     import paper_2202_07258_amd as bx
     from paper_2202_07258_amd import native as N
