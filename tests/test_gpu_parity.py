@@ -160,16 +160,16 @@ def test_cd_parity_multiwave(m, n, cd_block):
     assert res.status == "ok" and np.count_nonzero(res.sat) > 0
 
 
-@pytest.mark.parametrize("screening", [True, False])
-def test_cd_block_sweeps_match_oracle(screening, cd_block):
+@pytest.mark.parametrize("screening,dtype", [(True, np.float64), (False, np.float64), (True, np.float32)])
+def test_cd_block_sweeps_match_oracle(screening, dtype, cd_block):
     """Fixed budget of 60 CD sweeps (Sec. 5 CD solver), screening every 5, on
     a BVLS problem of 5 blocks of 128 with a ragged last one (n = 601) and
-    m = 1001 rows: the gap and preserved-set size after every pass match the
-    oracle's.  With screening the list shrinks over several passes to 400
+    m = 1001 rows, A stored in FP64 or FP32: the gap and preserved-set size
+    after every pass match the oracle's.  With screening the list shrinks over several passes to 400
     (4 blocks), so the Gram blocks are re-formed after those passes and
     reused after the others."""
-    print(f"\n[cd bvls sweeps] screening={screening} block={cd_block}", flush=True)
-    P = planted(31, 1001, 601)
+    print(f"\n[cd bvls sweeps] screening={screening} {np.dtype(dtype).name} block={cd_block}", flush=True)
+    P = planted(31, 1001, 601, dtype=dtype)
     kw = dict(solver="cd", screening=screening, screen_every=5, eps_gap=0.0, max_iter=60)
     xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, history=64, **kw)
     assert info["iters"] == res.iters == 60
