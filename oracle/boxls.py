@@ -280,7 +280,7 @@ def pg_step(A, y, l, u, x, eta, delta=INF):
     return project(x + eta * g, l, u)
 
 
-def cp_step(A, y, l, u, x, v, tau, sigma):
+def cp_step(A, y, l, u, x, v, tau, sigma, delta=INF):
     """One Chambolle-Pock primal-dual iteration (Chambolle & Pock 2011, the
     paper's second BVLS solver in Sec. 5) on min_x F(Ax) + G(x) with
     F(z) = 1/2 ||z - y||^2 and G the indicator of [l, u], in the order primal
@@ -290,11 +290,16 @@ def cp_step(A, y, l, u, x, v, tau, sigma):
         v+ = prox_{sigma F*}(v + sigma A xb) = (v + sigma (A xb - y)) / (1 + sigma)
     since F*(v) = 1/2 ||v||^2 + v^T y.  Converges for tau sigma ||A||_2^2 < 1;
     at a saddle point v = A x* - y, the negated dual optimum of eq. Dual_obj.
+    Huber fidelity, F(z) = sum_i h_delta(z_i - y_i): F*(v) = v^T y +
+    sum_i h_delta*(v_i) adds the box |v_i| <= delta to the same separable
+    quadratic, so its prox is the same point clipped to [-delta, delta].
     Returns (x+, v+)."""
     A = np.asarray(A, dtype=np.float64)
     xn = project(x - tau * (A.T @ v), l, u)
     xb = 2.0 * xn - x
     vn = (v + sigma * (A @ xb - y)) / (1.0 + sigma)
+    if math.isfinite(delta):
+        vn = np.clip(vn, -delta, delta)
     return xn, vn
 
 
@@ -442,8 +447,8 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
     ``oracle_dual_point`` at every pass: the experiment of Sec. 5.1 that
     measures how much screening the dual update leaves undone (Fig. 3).
     ``huber_delta`` (finite) selects the Huber fidelity (module docstring)
-    with the PG solver: its gradient, dual point, objectives and gap; the
-    radius keeps alpha = 1."""
+    with the PG or CP solver: its gradient (PG) or dual prox (CP), dual
+    point, objectives and gap; the radius keeps alpha = 1."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     y = np.asarray(y, dtype=np.float64)
@@ -453,8 +458,8 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
     if solver not in ("pg", "cd", "cp"):
         raise ValueError(solver)
     hd = float(huber_delta)
-    if math.isfinite(hd) and (solver != "pg" or theta_star is not None or not hd > 0.0):
-        raise ValueError("the Huber fidelity runs with the PG solver and the usual dual update, delta > 0")
+    if math.isfinite(hd) and (solver == "cd" or theta_star is not None or not hd > 0.0):
+        raise ValueError("the Huber fidelity runs with the PG and CP solvers and the usual dual update, delta > 0")
     if solver == "cp":
         # tau = sigma = step, default 1 / (1.05 ||A||_2): tau sigma ||A||^2 < 1
         eta = (1.0 / (1.05 * np.sqrt(lipschitz(A)))) if step is None else float(step)
@@ -463,6 +468,8 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
     x = project(np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64), l, u)
     # Chambolle-Pock dual iterate: the dual step from x0 with v = 0
     v = eta * (A @ x - y) / (1.0 + eta) if solver == "cp" else None
+    if v is not None and math.isfinite(hd):
+        v = np.clip(v, -hd, hd)
     sat = np.zeros(n, dtype=np.int8)
     P = np.arange(n)
     yp = y.copy()
@@ -481,7 +488,7 @@ def solve(A, y, l, u, *, solver: str = "pg", K: int = 10, eps_gap: float = 1e-6,
             elif solver == "cd":
                 xP = cd_sweep(AP, yp, lP, uP, xP)
             else:
-                xP, v = cp_step(AP, yp, lP, uP, xP, v, eta, eta)
+                xP, v = cp_step(AP, yp, lP, uP, xP, v, eta, eta, hd)
         iters += kk
         x[P] = xP
         if theta_star is None:

@@ -90,14 +90,14 @@ def _lbfgsb(A, y, l, u, delta):
     return res.x
 
 
-def _check_against_lbfgsb(seed):
+def _check_against_lbfgsb(seed, solver="pg"):
     A, y, l, u, delta = _instance(seed)
     xs = _lbfgsb(A, y, l, u, delta)
     rs = y - A @ xs
     # the optimum exercises both regimes and both bounds
     assert np.any(np.abs(rs) > 1.5 * delta) and np.any(np.abs(rs) < 0.5 * delta)
     assert np.any(xs <= l + 1e-9) and np.any(xs >= u - 1e-9)
-    res = ob.solve(A, y, l, u, solver="pg", K=10, eps_gap=1e-12, max_iter=400000, huber_delta=delta)
+    res = ob.solve(A, y, l, u, solver=solver, K=10, eps_gap=1e-12, max_iter=400000, huber_delta=delta)
     assert res.status == "ok"
     ps, po = ob.primal(A, y, xs, delta), ob.primal(A, y, res.x, delta)
     # the certified gap bounds the oracle's suboptimality; both solvers agree
@@ -117,6 +117,22 @@ def _check_against_lbfgsb(seed):
 @pytest.mark.parametrize("seed", [5, 6, 7])
 def test_huber_solve_matches_lbfgsb(seed):
     _check_against_lbfgsb(seed)
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_huber_chambolle_pock_matches_lbfgsb(seed):
+    # the primal-dual solver with the clipped dual prox reaches the same optimum
+    _check_against_lbfgsb(seed, solver="cp")
+
+
+def test_planted_mistake_unclipped_dual_prox_is_caught(monkeypatch):
+    """The Chambolle-Pock dual step without the clip to [-delta, delta] (the
+    LS prox): the iterates solve the LS problem instead."""
+    real = ob.cp_step
+    monkeypatch.setattr(ob, "cp_step", lambda A, y, l, u, x, v, tau, sigma, delta=math.inf:
+                        real(A, y, l, u, x, v, tau, sigma))
+    with pytest.raises(AssertionError):
+        _check_against_lbfgsb(5, solver="cp")
 
 
 def test_planted_mistake_ls_gradient_is_caught(monkeypatch):
@@ -153,8 +169,8 @@ def test_huber_with_unbounded_coordinates_uses_theta_zero():
     assert not np.any(res.sat) and res.gap == pytest.approx(res.primal, rel=1e-12)
 
 
-def test_huber_rejects_other_solvers():
+def test_huber_rejects_coordinate_descent():
+    # the exact coordinate step has no closed form for this fidelity
     A, y, l, u, delta = _instance(10)
-    for solver in ("cd", "cp"):
-        with pytest.raises(ValueError):
-            ob.solve(A, y, l, u, solver=solver, huber_delta=delta)
+    with pytest.raises(ValueError):
+        ob.solve(A, y, l, u, solver="cd", huber_delta=delta)
