@@ -71,9 +71,12 @@ typedef enum { BXS_PG = 0, BXS_CD = 1, BXS_CP = 2 } bxs_solver;
  * delta |s| - delta^2/2 beyond (delta = opts->huber_delta), a fidelity whose
  * gradient is 1-Lipschitz, so eq. GAP_Safe_sph keeps alpha = 1 (Sec. 3.3).
  * Its dual update (Sec. 4.1) is theta = clip(y' - Ax, -delta, delta), which
- * lies where f* is finite; the PG gradient is -A^T theta.  It runs with the PG
- * solver of solve_bvls, solve_nnls, solve_bvls_varbatch and
- * solve_bvls_noalloc, without opts->theta_star.  A preserved column with
+ * lies where f* is finite; the PG gradient is -A^T theta, and the
+ * Chambolle-Pock dual step is the least-squares one clipped to
+ * [-delta, delta] (the prox of the Huber F*).  It runs with the PG and CP
+ * solvers of solve_bvls, solve_nnls, solve_bvls_varbatch and
+ * solve_bvls_noalloc, without opts->theta_star (not with CD, whose exact
+ * coordinate step has no closed form for it).  A preserved column with
  * u_j = +inf makes the pass use theta = 0 (no translation: it could leave the
  * box |theta_i| <= delta), so such problems are solved but not screened
  * (info.t_valid = 0).  Fidelities that need the local strong-concavity bounds

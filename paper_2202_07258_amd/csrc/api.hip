@@ -233,7 +233,7 @@ static bxs_status check_opts(const bxs_opts* o)
     if (o->fidelity == BXS_FID_HUBER) {
         if (!(o->huber_delta > 0.0) || isinf(o->huber_delta))
             return fail(BXS_ERR_ARG, "huber_delta must be finite and > 0");
-        if (o->solver != BXS_PG) return fail(BXS_ERR_ARG, "the Huber fidelity runs with the PG solver");
+        if (o->solver == BXS_CD) return fail(BXS_ERR_ARG, "the Huber fidelity runs with the PG and CP solvers");
         if (o->theta_star) return fail(BXS_ERR_ARG, "the Huber fidelity takes no theta_star");
     }
     if (o->deterministic != 0 && o->deterministic != 1) return fail(BXS_ERR_ARG, "deterministic must be 0 or 1");

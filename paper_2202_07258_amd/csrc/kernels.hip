@@ -41,8 +41,10 @@ __device__ __forceinline__ void reduce_apply(const Inst& I, const State& S, int 
         I.r[row] -= tot2;
     } else if constexpr (MODE == kRedCP) {
         // dual step of Chambolle-Pock: prox of sigma F*, F*(v) = 1/2 ||v||^2 + v^T y'
-        const double sg = S.step;
-        I.r2[row] = (I.r2[row] + sg * (tot - ypv)) / (1.0 + sg);
+        // (least squares), restricted to |v_i| <= delta for the Huber fidelity,
+        // whose prox is the same point clipped (delta = +inf: no clip)
+        const double sg = S.step, hub = I.hub;
+        I.r2[row] = fmin(fmax((I.r2[row] + sg * (tot - ypv)) / (1.0 + sg), -hub), hub);
     } else {
         I.r[row] = tot;
     }
@@ -1205,8 +1207,9 @@ __global__ __launch_bounds__(256)
 void k_cp_init(const Inst* __restrict__ insts, const State* __restrict__ st)
 {
     const Inst& I = insts[blockIdx.y];
-    const double sg = st[blockIdx.y].step;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < I.m; i += gridDim.x * 256) I.r2[i] = -sg * I.r[i] / (1.0 + sg);
+    const double sg = st[blockIdx.y].step, hub = I.hub;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < I.m; i += gridDim.x * 256)
+        I.r2[i] = fmin(fmax(-sg * I.r[i] / (1.0 + sg), -hub), hub);
 }
 
 hipError_t launch_cp_init(const LaunchCtx& c, int count)

@@ -55,6 +55,19 @@ def test_huber_pg_parity(m, n, dtype):
     assert info["primal"] == pytest.approx(res.primal, rel=1e-9)
 
 
+@pytest.mark.parametrize("m,n,dtype", [(500, 260, np.float64), (1200, 500, np.float32)])
+def test_huber_chambolle_pock_parity(m, n, dtype):
+    """The primal-dual solver with the clipped dual step (the Huber F*'s
+    prox): same trajectory as the oracle's."""
+    print(f"\n[huber cp] m={m} n={n} {np.dtype(dtype).name}", flush=True)
+    P = huber_instance(4, m, n, dtype)
+    eta = 1.0 / (1.05 * math.sqrt(ob.lipschitz(P.A64())))
+    kw = dict(solver="cp", fidelity="huber", huber_delta=DELTA, screen_every=10, eps_gap=1e-8, max_iter=20000,
+              step=eta)
+    xg, sg, info, res = check_parity(P, "bvls", **kw)
+    assert res.status == "ok" and np.count_nonzero(res.sat) > 0
+
+
 def test_huber_unbounded_columns_use_theta_zero():
     """Columns with u_j = +inf: no translation for this fidelity, theta = 0
     (t_valid = 0), nothing screened; the iterates still match."""
