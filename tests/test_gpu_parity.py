@@ -180,6 +180,21 @@ def test_cd_block_sweeps_match_oracle(screening, dtype, cd_block):
         assert hg["gap"] == pytest.approx(ho["gap"], rel=1e-6, abs=1e-11)
 
 
+@pytest.mark.parametrize("m,n", [(1, 3), (5, 64), (70, 128), (64, 129), (63, 191), (130, 300)])
+def test_cd_block_edge_shapes(m, n, cd_block):
+    """Block-sequential CD at its boundaries: one row; a block of exactly 64
+    or 128 positions; a second block of one column; rows not filling the
+    64-row chunk; the second half of a block (positions 64-127) partly used.
+    A fixed budget of sweeps with screening every 5, against the oracle."""
+    print(f"\n[cd edge] m={m} n={n} block={cd_block}", flush=True)
+    rng = W.rng_for(95, 0, m, n)
+    A = np.asfortranarray(rng.standard_normal((m, n)))
+    P = W.Problem(A, rng.standard_normal(m), -np.ones(n), np.ones(n), None, False, {})
+    kw = dict(solver="cd", screen_every=5, eps_gap=0.0, max_iter=30)
+    xg, sg, info, res = check_parity(P, "bvls", xtol=1e-8, **kw)
+    assert info["iters"] == res.iters == 30
+
+
 @pytest.mark.parametrize("solver,dtype", [("pg", np.float32), ("pg", np.float64), ("cd", np.float64)])
 def test_oracle_dual_point_parity(solver, dtype):
     """Screening informed with the planted dual optimum theta* (Sec. 5.1,
