@@ -128,6 +128,118 @@ void k_cdb_gram(const Inst* __restrict__ insts, const State* __restrict__ st, do
 }
 
 // ---------------------------------------------------------------------------
+// The same Gram and cross blocks on the FP64 matrix cores
+// (v_mfma_f64_16x16x4_f64): grid (nbh, 4, 2), a 64 x 64 quadrant of a block
+// pair per workgroup, 4 waves of 32 x 32 outputs (2 x 2 blocks of 16 x 16).
+// Rows of A go through LDS 32 at a time (K-major: a fragment read is 16
+// consecutive doubles per quarter-wave), promoted exactly to FP64 on load;
+// the next 32 rows are loaded into registers while the current ones are
+// multiplied.  Each element is the sum over the row steps, in order, of
+// 4-term MFMA partial sums (deterministic for a given m).
+// ---------------------------------------------------------------------------
+typedef double cdb_d4 __attribute__((ext_vector_type(4)));
+
+template <typename TA>
+__global__ __launch_bounds__(256)
+void k_cdb_gram_mfma(const Inst* __restrict__ insts, const State* __restrict__ st, double* __restrict__ gram, int nbh)
+{
+    constexpr int B = kCdbB, Q = 64, KS = 32, PAD = 2;
+    const Inst& I = insts[0];
+    const State& S = st[0];
+    if (S.done || S.cdb_n == gram_tag(S.n_active)) return;
+    const int nA = S.n_active;
+    const int k = blockIdx.x, cross = blockIdx.z;
+    const int p0 = k * B;
+    if (p0 >= nA || (cross && k == 0)) return;
+    const int bs = min(B, nA - p0);
+    const int pb = cross ? p0 - B : p0, bsb = cross ? B : bs;
+    const int ta = blockIdx.y >> 1, tb = blockIdx.y & 1;
+    const int m = I.m;
+    const long long lda = I.lda;
+    const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
+    __shared__ double sA[KS][Q + PAD], sB[KS][Q + PAD];
+    __shared__ int ja[Q], jb[Q];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    if (tid < Q) {
+        const int qa = ta * Q + tid, qb = tb * Q + tid;
+        ja[tid] = (qa < bs) ? I.idx[p0 + qa] : -1;
+        jb[tid] = (qb < bsb) ? I.idx[pb + qb] : -1;
+    }
+    __syncthreads();
+    // one row step: 2048 elements per operand, a pair of consecutive rows of
+    // one column per thread and chunk (16 threads cover a column's 32 rows)
+    double ra[8], rb[8];
+    auto load = [&](int r0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 256 * q, col = c >> 4, rr = (c & 15) * 2;
+            const int i = r0 + rr;
+            const int ca = ja[col], cb = jb[col];
+            const TA* pa = A + (long long)(ca < 0 ? 0 : ca) * lda + i;
+            const TA* pbp = A + (long long)(cb < 0 ? 0 : cb) * lda + i;
+            ra[2 * q] = (ca >= 0 && i < m) ? (double)pa[0] : 0.0;
+            ra[2 * q + 1] = (ca >= 0 && i + 1 < m) ? (double)pa[1] : 0.0;
+            rb[2 * q] = (cb >= 0 && i < m) ? (double)pbp[0] : 0.0;
+            rb[2 * q + 1] = (cb >= 0 && i + 1 < m) ? (double)pbp[1] : 0.0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 256 * q, col = c >> 4, rr = (c & 15) * 2;
+            sA[rr][col] = ra[2 * q];
+            sA[rr + 1][col] = ra[2 * q + 1];
+            sB[rr][col] = rb[2 * q];
+            sB[rr + 1][col] = rb[2 * q + 1];
+        }
+    };
+    cdb_d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = cdb_d4{0.0, 0.0, 0.0, 0.0};
+    const int kq = lane >> 4, kr = lane & 15;
+    const int nk = (m + KS - 1) / KS;
+    load(0);
+    store();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load((kt + 1) * KS);
+#pragma unroll
+        for (int ks = 0; ks < KS / 4; ++ks) {
+            double fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) fa[a] = sA[ks * 4 + kq][wm * 32 + a * 16 + kr];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) fb[c] = sB[ks * 4 + kq][wn * 32 + c * 16 + kr];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[c], fa[a], acc[a][c], 0, 0, 0);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+    // register r of lane l holds element (row a-index l % 16, column 4 r + l / 16)
+    // of its 16 x 16 block: G[gb * B + ga], rows ga from J_k
+    double* __restrict__ G = gram + ((size_t)cross * nbh + k) * B * B;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ga = ta * Q + wm * 32 + a * 16 + kr, gb = tb * Q + wn * 32 + c * 16 + 4 * r + kq;
+                G[(size_t)gb * B + ga] = (ga < bs && gb < bsb) ? acc[a][c][r] : 0.0;
+            }
+}
+
+// ---------------------------------------------------------------------------
 // Launch k of a sweep (k = 0 .. nb + 1), 512 threads per workgroup.
 //
 // Workgroups 0 .. nchunks-1, kCdbRows rows each (64 rows x 8 groups):
@@ -438,12 +550,21 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
     }
 }
 
+int g_cdb_gram_mfma = 1;
+
 size_t cdb_gram_doubles(long n) { return (size_t)2 * ((n + kCdbB - 1) / kCdbB) * kCdbB * kCdbB; }
 size_t cdb_pg_doubles(long m) { return (size_t)2 * ((m + kCdbRows - 1) / kCdbRows) * kCdbB; }
 
 hipError_t launch_cdb_gram(const LaunchCtx& c, long n, double* gram)
 {
     const int nbh = (int)((n + kCdbB - 1) / kCdbB);
+    if (g_cdb_gram_mfma) {
+        const dim3 g((unsigned)nbh, 4, 2), b(256);
+        if (c.dtype == BXS_BF16) k_cdb_gram_mfma<__bf16><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+        else if (c.dtype == BXS_F32) k_cdb_gram_mfma<float><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+        else k_cdb_gram_mfma<double><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+        return hipGetLastError();
+    }
     const dim3 g((unsigned)nbh, 4, 2), b(256);
     if (c.dtype == BXS_BF16) k_cdb_gram<__bf16><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
     else if (c.dtype == BXS_F32) k_cdb_gram<float><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
