@@ -304,7 +304,6 @@ hipError_t launch_tdir(const LaunchCtx& c, int choice, long m, long n, double* s
 // preserved positions, kCdbRows rows per workgroup of the block products.
 constexpr int kCdbB = 128;
 constexpr int kCdbRows = 64;
-extern int g_cdb_gram_mfma;             // 1: Gram blocks on the FP64 matrix cores, 0: FP64 FMA tiles
 size_t cdb_gram_doubles(long n);        // Gram and cross-Gram blocks of up to n preserved columns
 size_t cdb_pg_doubles(long m);          // chunk partials of two blocks' correlations
 hipError_t launch_cdb_gram(const LaunchCtx& c, long n, double* gram);

@@ -57,80 +57,8 @@ __device__ __forceinline__ int gram_tag(int n_active) { return n_active + 1; }
 // Gram blocks.  blockIdx.z = 0: gram[k] = A_{J_k}^T A_{J_k}; z = 1 (k >= 1):
 // gram[nbh + k] = A_{J_k}^T A_{J_{k-1}}; both column-major B x B, element
 // (a, b) at b * B + a with rows a from J_k, zero outside the blocks' sizes.
-// Grid (nbh, 4, 2): a 64 x 64 tile per workgroup, rows of A staged through
-// LDS 32 at a time, a 4 x 4 register tile per thread.
-// ---------------------------------------------------------------------------
-template <typename TA>
-__global__ __launch_bounds__(256)
-void k_cdb_gram(const Inst* __restrict__ insts, const State* __restrict__ st, double* __restrict__ gram, int nbh)
-{
-    constexpr int B = kCdbB, RT = 32;
-    const Inst& I = insts[0];
-    const State& S = st[0];
-    if (S.done || S.cdb_n == gram_tag(S.n_active)) return;
-    const int nA = S.n_active;
-    const int k = blockIdx.x, cross = blockIdx.z;
-    const int p0 = k * B;
-    if (p0 >= nA || (cross && k == 0)) return;
-    const int bs = min(B, nA - p0);
-    const int pb = cross ? p0 - B : p0, bsb = cross ? B : bs;
-    const int ta = blockIdx.y >> 1, tb = blockIdx.y & 1;
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-    const int m = I.m;
-    const long long lda = I.lda;
-    const TA* __restrict__ A = reinterpret_cast<const TA*>(I.A);
-    __shared__ double sa[RT][65], sb[RT][65];
-    __shared__ int ja[64], jb[64];
-    if (tid < 64) {
-        const int qa = ta * 64 + tid, qb = tb * 64 + tid;
-        ja[tid] = (qa < bs) ? I.idx[p0 + qa] : -1;
-        jb[tid] = (qb < bsb) ? I.idx[pb + qb] : -1;
-    }
-    __syncthreads();
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int r0 = 0; r0 < m; r0 += RT) {
-#pragma unroll
-        for (int t = 0; t < (RT * 64) / 256; ++t) {
-            const int e = tid + 256 * t;
-            const int row = e % RT, col = e / RT;
-            const int i = r0 + row;
-            const int ca = ja[col], cb = jb[col];
-            sa[row][col] = (ca >= 0 && i < m) ? (double)A[(long long)ca * lda + i] : 0.0;
-            sb[row][col] = (cb >= 0 && i < m) ? (double)A[(long long)cb * lda + i] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < RT; ++rr) {
-            double va[4], vb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) va[a] = sa[rr][ty * 4 + a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) vb[b] = sb[rr][tx * 4 + b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(va[a], vb[b], acc[a][b]);
-        }
-        __syncthreads();
-    }
-    double* __restrict__ G = gram + ((size_t)cross * nbh + k) * B * B;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int ga = ta * 64 + ty * 4 + a, gb = tb * 64 + tx * 4 + b;
-            G[(size_t)gb * B + ga] = (ga < bs && gb < bsb) ? acc[a][b] : 0.0;
-        }
-}
-
-// ---------------------------------------------------------------------------
-// The same Gram and cross blocks on the FP64 matrix cores
-// (v_mfma_f64_16x16x4_f64): grid (nbh, 4, 2), a 64 x 64 quadrant of a block
-// pair per workgroup, 4 waves of 32 x 32 outputs (2 x 2 blocks of 16 x 16).
+// On the FP64 matrix cores (v_mfma_f64_16x16x4_f64): grid (nbh, 4, 2), a
+// 64 x 64 quadrant of a block pair per workgroup, 4 waves of 32 x 32 outputs (2 x 2 blocks of 16 x 16).
 // Rows of A go through LDS 32 at a time (K-major: a fragment read is 16
 // consecutive doubles per quarter-wave), promoted exactly to FP64 on load;
 // the next 32 rows are loaded into registers while the current ones are
@@ -550,25 +478,16 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
     }
 }
 
-int g_cdb_gram_mfma = 1;
-
 size_t cdb_gram_doubles(long n) { return (size_t)2 * ((n + kCdbB - 1) / kCdbB) * kCdbB * kCdbB; }
 size_t cdb_pg_doubles(long m) { return (size_t)2 * ((m + kCdbRows - 1) / kCdbRows) * kCdbB; }
 
 hipError_t launch_cdb_gram(const LaunchCtx& c, long n, double* gram)
 {
     const int nbh = (int)((n + kCdbB - 1) / kCdbB);
-    if (g_cdb_gram_mfma) {
-        const dim3 g((unsigned)nbh, 4, 2), b(256);
-        if (c.dtype == BXS_BF16) k_cdb_gram_mfma<__bf16><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
-        else if (c.dtype == BXS_F32) k_cdb_gram_mfma<float><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
-        else k_cdb_gram_mfma<double><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
-        return hipGetLastError();
-    }
     const dim3 g((unsigned)nbh, 4, 2), b(256);
-    if (c.dtype == BXS_BF16) k_cdb_gram<__bf16><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
-    else if (c.dtype == BXS_F32) k_cdb_gram<float><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
-    else k_cdb_gram<double><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+    if (c.dtype == BXS_BF16) k_cdb_gram_mfma<__bf16><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+    else if (c.dtype == BXS_F32) k_cdb_gram_mfma<float><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
+    else k_cdb_gram_mfma<double><<<g, b, 0, c.stream>>>(c.insts, c.st, gram, nbh);
     return hipGetLastError();
 }
 
