@@ -672,6 +672,11 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     hgap[0] = hgap[1] = -1.0;
     int* hseq = (int*)((char*)hdone + 32);                  // passes published: bytes 32..35
     __atomic_store_n(hseq, 0, __ATOMIC_RELEASE);
+    int* hnact = (int*)((char*)hdone + 40);                 // preserved-list length per slot: bytes 40..47
+    hnact[0] = hnact[1] = (int)P.specs[0].n;
+    // block-sequential CD: an upper bound of the preserved-list length, taken
+    // from the last pass the host has seen (the list only shrinks), so that a
+    // sweep launches only the blocks that can still exist
     const int K = o->screen_every;
     long long iters = 0;
     // Passes are enqueued one ahead of the stop check: while the host waits
@@ -718,6 +723,7 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
     int slot_seq[2] = {0, 0};
     // host_done: where the screening kernel publishes the stop counter
     // (nullptr inside a captured graph: a copy kernel follows the replay).
+    long cdb_bound = P.cdb ? P.specs[0].n : 0;
     auto enqueue_kernels = [&](int slot, long long kk, int final_pass, int* host_done) -> bxs_status {
         for (long long k = 0; k < kk; ++k) {
             const int first = (k == 0) ? 1 : 0;
@@ -731,7 +737,8 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
                 // pass (the kernel returns at once when the list is unchanged); the
                 // host's n bounds the device's block count
                 if (k == 0) BXS_HIP(launch_cdb_gram(c, P.specs[0].n, P.cdb_gram));
-                BXS_HIP(launch_cdb_sweep(c, P.specs[0].m, P.specs[0].n, P.cdb_pg, P.cdb_gram, P.cdb_delta));
+                BXS_HIP(launch_cdb_sweep(c, P.specs[0].m, P.specs[0].n, cdb_bound, P.cdb_pg, P.cdb_gram,
+                                         P.cdb_delta));
             } else {
                 for (int b = 0; b < kNumCdBuckets; ++b) BXS_HIP(launch_cd(c, b, D.lists[b], D.n_list[b], 1));
             }
@@ -764,7 +771,8 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
                               host_done, (host_done && count == 1) ? hgap + slot : nullptr,
                               (host_done && poll) ? hseq : nullptr,
                               o->theta_star ? kScreenOracleDual
-                                            : (o->fidelity == BXS_FID_HUBER ? kScreenHuber : kScreenLS)));
+                                            : (o->fidelity == BXS_FID_HUBER ? kScreenHuber : kScreenLS),
+                              (host_done && count == 1 && P.cdb) ? hnact + slot : nullptr));
         if (o->screening) {
             for (int b = 0; b < kNumVariants; ++b) BXS_HIP(launch_sweep(c, b, kModeFold, D.items[b], D.n_items[b]));
             BXS_HIP(launch_reduce(c, kRedFold, D.ritems, D.n_ritems, 0, D.nritems, D.n_nritems));
@@ -901,6 +909,9 @@ static bxs_status run(Plan& P, int dtype, const bxs_opts* o, const double* t, bx
             g_old = g_new;
             g_new = hgap[slot];
         }
+        // the pass that just completed published its preserved-list length
+        // (graph replay keeps the captured launches)
+        if (P.cdb && slot_gap[slot] && hnact[slot] >= 0 && hnact[slot] < cdb_bound) cdb_bound = hnact[slot];
         if (o->profile) {
             for (long long k = 0; k < slot_kk[slot]; ++k) {
                 // PG: the first sweep of a pass returns at once when the step

@@ -290,11 +290,13 @@ hipError_t launch_count_free(const LaunchCtx& c, int count);
 // nullptr; host_seq: pinned (coherent) host word that receives the number of
 // screening passes run, written last with a system-scope release, or nullptr;
 // kind: kScreenLS; kScreenOracleDual (the instances carry a given dual
-// optimum, Inst::ts); kScreenHuber (the Huber fidelity, Inst::hub).
+// optimum, Inst::ts); kScreenHuber (the Huber fidelity, Inst::hub);
+// host_nact: pinned host word that receives the preserved-list length of
+// instance 0 after the pass (single-instance calls), or nullptr.
 enum ScreenKind : int { kScreenLS = 0, kScreenOracleDual = 1, kScreenHuber = 2 };
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening,
                          int final_pass, int K, int kk, int ahead, int* host_done, double* host_gap,
-                         int* host_seq, int kind);
+                         int* host_seq, int kind, int* host_nact = nullptr);
 hipError_t launch_cd(const LaunchCtx& c, int bucket, const int* inst_list, int n_list, int sweeps);
 // translation direction computed from A (tdir.hip, one instance)
 size_t tdir_scratch_doubles(long m, long n);
@@ -308,7 +310,8 @@ size_t cdb_gram_doubles(long n);        // Gram and cross-Gram blocks of up to n
 size_t cdb_pg_doubles(long m);          // chunk partials of two blocks' correlations
 hipError_t launch_cdb_gram(const LaunchCtx& c, long n, double* gram);
 // one sweep over at most nb blocks (an upper bound of the device's count)
-hipError_t launch_cdb_sweep(const LaunchCtx& c, long m, long n, double* pg, const double* gram, double* delta);
+hipError_t launch_cdb_sweep(const LaunchCtx& c, long m, long n, long n_bound, double* pg, const double* gram,
+                            double* delta);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t s);
 
 }  // namespace bxs

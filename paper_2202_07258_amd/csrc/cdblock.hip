@@ -491,14 +491,17 @@ hipError_t launch_cdb_gram(const LaunchCtx& c, long n, double* gram)
     return hipGetLastError();
 }
 
-// One sweep over up to n preserved columns: launches 0 .. nbh + 1, nbh from
-// the host's n (an upper bound of the device's block count; launches past
-// the device's count return at once).
-hipError_t launch_cdb_sweep(const LaunchCtx& c, long m, long n, double* pg, const double* gram, double* delta)
+// One sweep: launches 0 .. nb + 1 with nb = ceil(n_bound / B), n_bound an
+// upper bound of the device's preserved-list length (the list only shrinks;
+// launches past the device's block count return at once).  n is the
+// problem's column count, which sets the layout of the cross blocks.
+hipError_t launch_cdb_sweep(const LaunchCtx& c, long m, long n, long n_bound, double* pg, const double* gram,
+                            double* delta)
 {
     const int nbh = (int)((n + kCdbB - 1) / kCdbB);
+    const int nbl = (int)((std::min(n, std::max(n_bound, 0L)) + kCdbB - 1) / kCdbB);
     const int chunks = (int)((m + kCdbRows - 1) / kCdbRows);
-    for (int k = 0; k <= nbh + 1; ++k) {
+    for (int k = 0; k <= nbl + 1; ++k) {
         if (c.dtype == BXS_BF16)
             k_cdb_step<__bf16><<<chunks + 1, 512, 0, c.stream>>>(c.insts, c.st, k, chunks, nbh, pg, gram, delta);
         else if (c.dtype == BXS_F32)

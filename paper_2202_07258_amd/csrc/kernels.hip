@@ -864,7 +864,7 @@ template <int SK>
 __global__ __launch_bounds__(1024)
 void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __restrict__ done_counter,
               double eps_gap, int screening, int final_pass, int K, int kk, int ahead, int* host_done,
-              double* host_gap, int* host_seq)
+              double* host_gap, int* host_seq, int* host_nact)
 {
     screen_pass<SK>(insts, st, done_counter, eps_gap, screening, final_pass, K, kk, ahead);
     if (host_done == nullptr) return;
@@ -877,6 +877,7 @@ void k_screen(const Inst* __restrict__ insts, State* __restrict__ st, int* __res
             __threadfence();
             host_done[0] = atomicAdd(done_counter, 0);
             if (host_gap) host_gap[0] = st[0].gap;
+            if (host_nact) host_nact[0] = st[0].n_active;
             atomicExch(ticket, 0);
             if (host_seq) {
                 const int seq = atomicAdd(done_counter + 2, 1) + 1;
@@ -1220,18 +1221,21 @@ hipError_t launch_cp_init(const LaunchCtx& c, int count)
 
 hipError_t launch_screen(const LaunchCtx& c, int count, double eps_gap, int screening, int final_pass,
                          int K, int kk, int ahead, int* host_done, double* host_gap, int* host_seq,
-                         int kind)
+                         int kind, int* host_nact)
 {
     const dim3 g(count), b(1024);
     if (kind == kScreenOracleDual)
         k_screen<kScreenOracleDual><<<g, b, 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                           final_pass, K, kk, ahead, host_done, host_gap, host_seq);
+                                                           final_pass, K, kk, ahead, host_done, host_gap, host_seq,
+                                                           host_nact);
     else if (kind == kScreenHuber)
         k_screen<kScreenHuber><<<g, b, 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                      final_pass, K, kk, ahead, host_done, host_gap, host_seq);
+                                                      final_pass, K, kk, ahead, host_done, host_gap, host_seq,
+                                                      host_nact);
     else
         k_screen<kScreenLS><<<g, b, 0, c.stream>>>(c.insts, c.st, c.done_counter, eps_gap, screening,
-                                                   final_pass, K, kk, ahead, host_done, host_gap, host_seq);
+                                                   final_pass, K, kk, ahead, host_done, host_gap, host_seq,
+                                                   host_nact);
     return hipGetLastError();
 }
 
