@@ -1,8 +1,10 @@
-"""The headline workload at its full size (BVLS 4000 x 16000, FP32 storage) in
-the launch configuration the benchmark times (default sweep shape, work-item
-spread and options): trajectory parity with the oracle on the instance as
-specified, and, on the planted companion of the same shape where screening
-fires, the safety of every screened coordinate against the planted optimum."""
+"""Benchmark workloads at their full size, in the launch configuration the
+benchmark times (default sweep shape, work-item spread and options): the
+headline (BVLS 4000 x 16000, FP32 storage) with trajectory parity against the
+oracle on the instance as specified and, on the planted companion of the same
+shape where screening fires, the safety of every screened coordinate against
+the planted optimum; coordinate descent at the largest Tab. 1 size; the Huber
+fidelity at its benchmark size."""
 import numpy as np
 import pytest
 import torch
@@ -78,3 +80,48 @@ def test_c2_planted_full_size_safety():
     assert info["gap"] < 1e-6 and sub <= info["gap"] + 1e-10
     assert _oracle_gap(A64, P, xg) == pytest.approx(info["gap"], rel=1e-5)
     assert np.max(np.abs(xg - P.x_true)) < 1e-5
+
+
+def test_table1_cd_full_size_sweeps():
+    """Coordinate descent at the largest size of the Tab. 1 setup (NNLS
+    2000 x 6000, |N(0,1)| entries) in the benchmark's configuration (the
+    block-sequential sweep, screening every 10 sweeps, t = -1): 30 sweeps
+    against the oracle's, gap of every pass and the iterate."""
+    import paper_2202_07258_amd as bx
+    P = W.table1_nnls(0, 2000, 6000)
+    print(f"\n[tab1 cd full size] m={P.m} n={P.n}", flush=True)
+    A64 = P.A64()
+    A, y, _, _ = _dev(P)
+    x, sat, info = bx.solve_nnls(A, y, solver="cd", screen_every=10, eps_gap=0.0, max_iter=30, history=8)
+    res = ob.solve(A64, P.y, P.l, P.u, solver="cd", K=10, eps_gap=0.0, max_iter=30)
+    xg = x.cpu().numpy()
+    assert info["iters"] == res.iters == 30 and info["passes"] == res.passes
+    assert np.max(np.abs(xg - res.x)) <= 1e-8 * max(1.0, float(np.max(np.abs(res.x))))
+    assert np.array_equal(sat.cpu().numpy(), res.sat)
+    for hg, ho in zip(info["history"], res.history):
+        assert hg["n_active"] == ho["n_active"]
+        assert hg["gap"] == pytest.approx(ho["gap"], rel=1e-6)
+
+
+def test_huber_full_size_trajectory():
+    """The Huber fidelity at the benchmark's size (BVLS 16000 x 4000 FP32 with
+    10% outlier rows, delta = 0.5), default launch configuration and the
+    library's own step (the oracle's Lanczos estimate from the same start):
+    same iterations, passes and screened set as the oracle, x within 1e-9."""
+    import paper_2202_07258_amd as bx
+    P = W.huber_bvls(0, 16000, 4000, np.float32)
+    print(f"\n[huber full size] m={P.m} n={P.n}", flush=True)
+    A64 = P.A64()
+    eta = 1.0 / (1.05 * ob.lipschitz_lanczos(A64, 8, _hash_start(P.m)))
+    A, y, l, u = _dev(P)
+    x, sat, info = bx.solve_bvls(A, y, l, u, fidelity="huber", huber_delta=0.5, eps_gap=1e-6, screen_every=10)
+    res = ob.solve(A64, P.y, P.l, P.u, K=10, eps_gap=1e-6, step=eta, huber_delta=0.5)
+    xg, sg = x.cpu().numpy(), sat.cpu().numpy()
+    assert info["status_name"] == "ok" and res.status == "ok"
+    assert info["iters"] == res.iters and info["passes"] == res.passes
+    assert np.array_equal(sg, res.sat) and np.count_nonzero(sg) > 0
+    assert np.max(np.abs(xg - res.x)) <= 1e-9 * max(1.0, float(np.max(np.abs(res.x))))
+    # the certified gap carries rounding margins of order u (||y||^2 / 2)
+    yy = 0.5 * float(P.y @ P.y)
+    assert info["gap"] >= res.gap - 1e-12 * (1 + yy)
+    assert abs(info["gap"] - res.gap) <= 1e-6 * res.gap + 1e-11 * (1 + yy)
