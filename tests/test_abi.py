@@ -102,6 +102,21 @@ def test_huber_rejected_by_shared_matrix_solver_and_adjoint(lib):
     assert "least-squares" in lib.bxs_last_error().decode()
 
 
+def test_cd_block_switch_and_workspace(lib):
+    # the switch takes 0 or 1; the block form's workspace adds its Gram and
+    # cross blocks (2 x 128 doubles per column), the one-workgroup form does not
+    assert lib.bxs_set_cd_block(2) == N.BXS_ERR_ARG
+    o = _opts(lib, solver=N.BXS_CD)
+    sizes = []
+    for enable in (1, 0):
+        assert lib.bxs_set_cd_block(enable) == N.BXS_OK
+        b = C.c_size_t(0)
+        assert lib.bxs_workspace_size(2000, 6000, C.byref(o), C.byref(b)) == N.BXS_OK
+        sizes.append(b.value)
+    assert lib.bxs_set_cd_block(1) == N.BXS_OK
+    assert sizes[0] - sizes[1] >= 2 * 128 * 8 * 6000
+
+
 def test_normal_equations_direction_needs_tall_matrix(lib):
     o = _opts(lib, t_choice=N.T_CHOICES["normal_equations"])
     assert lib.solve_nnls(8, 16, 0, FAKE, 8, FAKE, FAKE, FAKE, C.byref(o), None) == N.BXS_ERR_ARG
