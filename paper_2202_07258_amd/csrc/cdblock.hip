@@ -231,13 +231,15 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
                 // the previous block is full; its delta is in delta[(b - 1) & 1]
                 const double2* __restrict__ Cb2 = reinterpret_cast<const double2*>(gram + ((size_t)nbh + b) * B * B);
                 const double* __restrict__ dp = delta + (size_t)((b - 1) & 1) * B;
+                // a column of the cross block is read only for a position that
+                // moved (late in a solve most stay on their bound)
                 double2 cv[16];
                 double dv[16];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    cv[i] = Cb2[(cg + 8 * i) * (B / 2) + q2];
-                    dv[i] = dp[cg + 8 * i];
-                }
+                for (int i = 0; i < 16; ++i) dv[i] = dp[cg + 8 * i];
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    cv[i] = (dv[i] != 0.0) ? Cb2[(cg + 8 * i) * (B / 2) + q2] : make_double2(0.0, 0.0);
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     t2.x = fma(cv[i].x, dv[i], t2.x);
