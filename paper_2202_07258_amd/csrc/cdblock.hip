@@ -434,9 +434,10 @@ void k_cdb_step(const Inst* __restrict__ insts, State* __restrict__ st, int k, i
     const int part = tid & 7, slot = tid >> 3;
     double av[B / 8];                   // update: row i, columns grp + 8 t of block k-2
     double bv[2][8];                    // dot: column slot + 64 h, rows part + 8 e
-    if (upd && qs == B) {               // every block but the last
+    if (upd && qs == B) {               // every block but the last; columns that did not move are not read
 #pragma unroll
-        for (int t = 0; t < B / 8; ++t) av[t] = (double)A[(long long)sip[grp + 8 * t] * lda + ic];
+        for (int t = 0; t < B / 8; ++t)
+            av[t] = (sdl[grp + 8 * t] != 0.0) ? (double)A[(long long)sip[grp + 8 * t] * lda + ic] : 0.0;
     }
     if (dot) {
 #pragma unroll
