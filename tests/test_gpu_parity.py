@@ -379,6 +379,19 @@ def test_graph_replay_matches_direct_launches(solver, m, n):
     parity_vs_oracle(P, xg, sg, ig, solver=solver, eps_gap=1e-9, max_iter=4000, step=eta, screen_every=5)
 
 
+def test_cd_block_profile_mode_matches_direct():
+    """Block CD with per-sweep events (profile mode: the host waits on events,
+    the launches are still sized by the published preserved-list length)
+    gives the direct launches' result bit for bit."""
+    P = planted(16, 300, 900, dtype=np.float32)
+    kw = dict(solver="cd", eps_gap=1e-9, max_iter=4000, step=step_of(P), screen_every=5)
+    xd, sd, idd = run_gpu(P, "bvls", **kw)
+    xp, sp, ip = run_gpu(P, "bvls", profile=True, **kw)
+    assert np.array_equal(xd, xp) and np.array_equal(sd, sp)
+    assert idd["iters"] == ip["iters"] and idd["passes"] == ip["passes"] and idd["gap"] == ip["gap"]
+    assert ip["sweep_launches"] > 0 and np.count_nonzero(sd) > 0
+
+
 def test_history_records():
     P = planted(7, 200, 600)
     eta = step_of(P)
